@@ -1,0 +1,177 @@
+"""FP64 CPU oracle for the explicit finite-volume Gatenby-Gawlinski step.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use it to check and time the HIP library.  The product path
+never imports it.  It shares no code with the HIP path; the only common module
+is the seeded input generator, which holds none of the scheme's arithmetic.
+
+The arithmetic lives in ``ggfv_oracle.c`` (plain loops, FP64, no FMA).  This
+wrapper builds it with gcc into ``libggfv_oracle.so`` next to the source and
+exposes numpy-level functions.  Every function states the passage it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ggfv_oracle.c")
+_SRC_ADJ = os.path.join(_HERE, "ggfv_oracle_adjoint.c")
+LIB_PATH = os.path.join(_HERE, "libggfv_oracle.so")
+CFLAGS = ["-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-std=c11"]
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def sources():
+    return [p for p in (_SRC, _SRC_ADJ) if os.path.exists(p)]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (portable x86-64, no -march=native)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, *sources(), "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build(force=True)
+    _lib = bind(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def use_library(path):
+    """Bind another build of the oracle source (mutation tests); returns the
+    previous binding so the caller can restore it with ``restore_library``."""
+    global _lib
+    prev = _lib
+    _lib = bind(ctypes.CDLL(path))
+    return prev
+
+
+def restore_library(prev):
+    global _lib
+    _lib = prev
+
+
+def bind(lib):
+    i, d, l, p = ctypes.c_int, ctypes.c_double, ctypes.c_long, _D
+    lib.orc_tensor_from_eig.argtypes = [l, p, p, p, p, p, p]
+    lib.orc_lambda_max.argtypes = [d, d, d]
+    lib.orc_lambda_max.restype = d
+    lib.orc_count_not_spd.argtypes = [l, p, p, p]
+    lib.orc_count_not_spd.restype = l
+    lib.orc_stable_dt.argtypes = [i, i, d, d, p, p, p, d, d]
+    lib.orc_stable_dt.restype = d
+    lib.orc_div_w.argtypes = [i, i, d, d, p, p, p, p, p]
+    lib.orc_div_v.argtypes = [i, i, d, d, p, p, p]
+    lib.orc_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p, p, p, p, p, p, p]
+    lib.orc_diag.argtypes = [i, i, d, d, p, p, p, p, p, p, d, d, p]
+    lib.orc_run.argtypes = [i, i, d, d, p, d, l, p, p, p, p, p, p, l, p]
+    if hasattr(lib, "orc_adjoint_step"):
+        lib.orc_adjoint_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p,
+                                         p, p, p, p, p, p, p, p, p, p]
+    return lib
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr(x):
+    return None if x is None else x.ctypes.data_as(_D)
+
+
+def tensor_from_eig(lam1, lam2, theta):
+    """(lambda1, lambda2, theta) -> (a, b, c): A = R diag(l1, l2) R^T (eq. (2))."""
+    lam1, lam2, theta = _f64(lam1), _f64(lam2), _f64(theta)
+    a, b, c = (np.empty_like(lam1) for _ in range(3))
+    _load().orc_tensor_from_eig(lam1.size, _ptr(lam1), _ptr(lam2), _ptr(theta),
+                                _ptr(a), _ptr(b), _ptr(c))
+    return a, b, c
+
+
+def lambda_max(a, b, c) -> float:
+    return _load().orc_lambda_max(float(a), float(b), float(c))
+
+
+def count_not_spd(a, b, c) -> int:
+    """Cells violating Sylvester's criterion for A = [[a,b],[b,c]] (eq. (2))."""
+    a, b, c = _f64(a), _f64(b), _f64(c)
+    return int(_load().orc_count_not_spd(a.size, _ptr(a), _ptr(b), _ptr(c)))
+
+
+def stable_dt(a, b, c, Delta2, safety, lx=1.0, ly=1.0) -> float:
+    """Explicit step bound (Section 2, CFL restriction of the explicit scheme)."""
+    a, b, c = _f64(a), _f64(b), _f64(c)
+    ny, nx = a.shape
+    return _load().orc_stable_dt(nx, ny, lx, ly, _ptr(a), _ptr(b), _ptr(c),
+                                 float(Delta2), float(safety))
+
+
+def div_w(W, a, b, c, lx=1.0, ly=1.0):
+    """D2(W; A): Table 2 in flux form with zero boundary flux."""
+    W, a, b, c = _f64(W), _f64(a), _f64(b), _f64(c)
+    ny, nx = W.shape
+    out = np.empty_like(W)
+    _load().orc_div_w(nx, ny, lx, ly, _ptr(W), _ptr(a), _ptr(b), _ptr(c), _ptr(out))
+    return out
+
+
+def div_v(U, V, lx=1.0, ly=1.0):
+    """D1(V; U): Table 1 in flux form with zero boundary flux."""
+    U, V = _f64(U), _f64(V)
+    ny, nx = V.shape
+    out = np.empty_like(V)
+    _load().orc_div_v(nx, ny, lx, ly, _ptr(U), _ptr(V), _ptr(out))
+    return out
+
+
+def step(u, v, w, a, b, c, params, dt, lx=1.0, ly=1.0, sources=None):
+    """One forward-Euler step of eq. (3); returns new (u, v, w)."""
+    u, v, w, a, b, c = (_f64(x) for x in (u, v, w, a, b, c))
+    ny, nx = u.shape
+    prm = _f64(params)
+    un, vn, wn = np.empty_like(u), np.empty_like(v), np.empty_like(w)
+    su = sv = sw = None
+    if sources is not None:
+        su, sv, sw = (_f64(s) for s in sources)
+    _load().orc_step(nx, ny, lx, ly, _ptr(prm), float(dt), _ptr(u), _ptr(v), _ptr(w),
+                     _ptr(a), _ptr(b), _ptr(c), _ptr(un), _ptr(vn), _ptr(wn),
+                     _ptr(su), _ptr(sv), _ptr(sw))
+    return un, vn, wn
+
+
+def run(u, v, w, a, b, c, params, dt, nsteps, lx=1.0, ly=1.0, mass_every=0):
+    """nsteps steps of eq. (3).  Returns (u, v, w, mass_log) with mass_log of shape
+    (nsteps // mass_every, 3) (empty when mass_every == 0)."""
+    u, v, w = (np.array(x, dtype=np.float64, copy=True, order="C") for x in (u, v, w))
+    a, b, c = _f64(a), _f64(b), _f64(c)
+    ny, nx = u.shape
+    prm = _f64(params)
+    nlog = nsteps // mass_every if mass_every > 0 else 0
+    log = np.zeros((max(nlog, 1), 3))
+    _load().orc_run(nx, ny, lx, ly, _ptr(prm), float(dt), int(nsteps), _ptr(u), _ptr(v),
+                    _ptr(w), _ptr(a), _ptr(b), _ptr(c), int(mass_every), _ptr(log))
+    return u, v, w, log[:nlog]
+
+
+def diagnostics(u, v, w, a, b, c, Delta2, dt, lx=1.0, ly=1.0) -> dict:
+    """Masses, min/max, CFL number and non-finite count of a state."""
+    u, v, w, a, b, c = (_f64(x) for x in (u, v, w, a, b, c))
+    ny, nx = u.shape
+    out = np.zeros(11)
+    _load().orc_diag(nx, ny, lx, ly, _ptr(u), _ptr(v), _ptr(w), _ptr(a), _ptr(b), _ptr(c),
+                     float(Delta2), float(dt), _ptr(out))
+    return {"mass": out[0:3].copy(), "vmin": out[3:6].copy(), "vmax": out[6:9].copy(),
+            "cfl": float(out[9]), "nonfinite": int(out[10])}

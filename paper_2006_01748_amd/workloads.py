@@ -1,0 +1,258 @@
+"""Seeded synthetic inputs for the Gatenby-Gawlinski finite-volume step.
+
+This module only *draws* inputs: initial states, diffusion-tensor fields given by
+their eigen-description (lambda1, lambda2, theta), or by (a, b, c) directly, reaction
+parameters and run lengths.  It holds none of the scheme's arithmetic: no stencil,
+no tensor rotation, no time-step rule.  Both the CPU oracle and the HIP library
+consume what it returns, and each side does its own arithmetic on it.
+
+The model (Section 1, eq. (1)) has normal cells u, tumour cells v and excess lactic
+acid w on the unit square with Neumann boundaries; the acid diffuses with a
+symmetric positive-definite, heterogeneous tensor A = [[a, b], [b, c]] (eq. (2)).
+The paper prints no initial data or parameters for its runs, so the workloads
+below are synthetic and stand in for "tissue-like" anisotropic media:
+
+* ``cfg0`` 128x128, isotropic A = I, one central tumour disk (radius 0.1).
+* ``cfg1`` 1024x1024, smooth random orientation and anisotropy, five disks.
+* ``cfg2`` 4096x4096 layered tissue: 64 Voronoi regions with piecewise-constant
+  tensors and thin low-diffusion membranes along region borders.
+* ``cfg3`` ensembles of uneven square instances (64..512) with per-instance
+  parameters.
+* ``cfg4`` 512x512 smooth anisotropic field for gradient runs.
+
+Every random draw uses ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+BASE_SEED = 2006017480
+
+# Reaction parameters in the order (delta1, rho2, Delta2, rho3, delta3).  The paper
+# writes d, r, alpha and c (eq. (1)); delta1 = d, rho2 = r, Delta2 = alpha and the
+# acid term c(V - W) is generalised to rho3 V - delta3 W.
+PARAMS_REF = (12.5, 1.0, 0.01, 70.0, 70.0)
+
+
+@dataclasses.dataclass
+class Workload:
+    """One synthetic run: grid, tensor description, initial state, parameters."""
+
+    name: str
+    nx: int
+    ny: int
+    lx: float
+    ly: float
+    params: tuple                 # (delta1, rho2, Delta2, rho3, delta3)
+    u0: np.ndarray                # (ny, nx) float64, row-major, x fastest
+    v0: np.ndarray
+    w0: np.ndarray
+    # exactly one of the two tensor descriptions is set
+    abc: Optional[tuple] = None   # (a, b, c) arrays
+    eig: Optional[tuple] = None   # (lambda1, lambda2, theta) arrays
+    safety: float = 0.9           # fraction of the explicit stability bound
+    steps: int = 1
+    seed: int = 0
+    dt_closed_form: Optional[float] = None   # only where the recipe states dt outright
+    mass_every: int = 0
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+
+def cell_centres(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0):
+    """Cell-centre coordinates ((i + 1/2) dx, (j + 1/2) dy) as (ny, nx) arrays."""
+    x = (np.arange(nx, dtype=np.float64) + 0.5) * (lx / nx)
+    y = (np.arange(ny, dtype=np.float64) + 0.5) * (ly / ny)
+    return np.meshgrid(x, y)  # X[j, i], Y[j, i]
+
+
+def smooth_field(rng: np.random.Generator, nx: int, ny: int, modes: int = 16,
+                 kmin: int = 1, kmax: int = 8) -> np.ndarray:
+    """Sum of ``modes`` plane cosines with integer wavenumbers in [kmin, kmax],
+    uniform directions and phases, min-max normalised to [0, 1]."""
+    X, Y = cell_centres(nx, ny)
+    kappa = rng.integers(kmin, kmax + 1, size=modes)
+    psi = rng.uniform(0.0, 2.0 * math.pi, size=modes)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=modes)
+    S = np.zeros((ny, nx))
+    for m in range(modes):
+        S += np.cos(2.0 * math.pi * kappa[m] * (X * math.cos(psi[m]) + Y * math.sin(psi[m]))
+                    + phi[m])
+    lo, hi = S.min(), S.max()
+    return (S - lo) / (hi - lo)
+
+
+def disks_state(nx: int, ny: int, centres, radius: float):
+    """u = 1, v = 0, w = 0 outside; u = 0, v = 1 inside disks (cell centre test)."""
+    X, Y = cell_centres(nx, ny)
+    inside = np.zeros((ny, nx), dtype=bool)
+    for (x0, y0) in centres:
+        inside |= (X - x0) ** 2 + (Y - y0) ** 2 <= radius * radius
+    u = np.where(inside, 0.0, 1.0)
+    v = np.where(inside, 1.0, 0.0)
+    w = np.zeros((ny, nx))
+    return u, v, w
+
+
+def smooth_eig_fields(rng: np.random.Generator, nx: int, ny: int,
+                      lam_lo: float = 0.5, lam_hi: float = 2.0, ratio_max: float = 10.0):
+    """theta = pi * S1, anisotropy ratio = 1 + (ratio_max - 1) * S2, lambda1 i.i.d.
+    uniform per cell, lambda2 = lambda1 / ratio."""
+    theta = math.pi * smooth_field(rng, nx, ny)
+    ratio = 1.0 + (ratio_max - 1.0) * smooth_field(rng, nx, ny)
+    lam1 = rng.uniform(lam_lo, lam_hi, size=(ny, nx))
+    lam2 = lam1 / ratio
+    return lam1, lam2, theta
+
+
+def voronoi_labels(rng: np.random.Generator, nx: int, ny: int, nseeds: int = 64,
+                   chunk_rows: int = 64) -> np.ndarray:
+    """Nearest-seed labels of cell centres (ties go to the lower seed index)."""
+    seeds = rng.uniform(0.0, 1.0, size=(nseeds, 2))
+    x = (np.arange(nx) + 0.5) / nx
+    labels = np.empty((ny, nx), dtype=np.int32)
+    for j0 in range(0, ny, chunk_rows):
+        j1 = min(ny, j0 + chunk_rows)
+        y = (np.arange(j0, j1) + 0.5) / ny
+        dx2 = (x[None, :] - seeds[:, 0:1]) ** 2            # (nseeds, nx)
+        dy2 = (y[None, :] - seeds[:, 1:2]) ** 2            # (nseeds, rows)
+        d2 = dy2[:, :, None] + dx2[:, None, :]             # (nseeds, rows, nx)
+        labels[j0:j1] = np.argmin(d2, axis=0)              # first minimum = lower index
+    return labels
+
+
+def membrane_mask(labels: np.ndarray) -> np.ndarray:
+    """A cell is membrane if any 4-neighbour lies in another region (two cells
+    wide across every border)."""
+    m = np.zeros(labels.shape, dtype=bool)
+    d = labels[:, 1:] != labels[:, :-1]
+    m[:, 1:] |= d
+    m[:, :-1] |= d
+    d = labels[1:, :] != labels[:-1, :]
+    m[1:, :] |= d
+    m[:-1, :] |= d
+    return m
+
+
+def layered_eig_fields(rng: np.random.Generator, nx: int, ny: int, nregions: int = 64,
+                       membrane_scale: float = 0.05):
+    """Piecewise-constant (lambda1, lambda2, theta) on Voronoi regions, with both
+    eigenvalues scaled by ``membrane_scale`` on membrane cells."""
+    labels = voronoi_labels(rng, nx, ny, nregions)
+    th_r = rng.uniform(0.0, math.pi, size=nregions)
+    l1_r = rng.uniform(0.2, 2.0, size=nregions)
+    ratio_r = rng.uniform(1.0, 20.0, size=nregions)
+    theta = th_r[labels]
+    lam1 = l1_r[labels]
+    lam2 = lam1 / ratio_r[labels]
+    mem = membrane_mask(labels)
+    lam1 = np.where(mem, lam1 * membrane_scale, lam1)
+    lam2 = np.where(mem, lam2 * membrane_scale, lam2)
+    return lam1, lam2, theta
+
+
+# ---------------------------------------------------------------------------
+# The five standard workloads
+
+
+def cfg0(seed: int = BASE_SEED + 0, n: int = 128, steps: int = 2000) -> Workload:
+    """128^2, isotropic A = I, central disk r = 0.1; dt = 0.2 h^2 / (4 max(1, Delta2))."""
+    u, v, w = disks_state(n, n, [(0.5, 0.5)], 0.1)
+    ones, zeros = np.ones((n, n)), np.zeros((n, n))
+    h = 1.0 / n
+    dt = 0.2 * h * h / (4.0 * max(1.0, PARAMS_REF[2]))
+    return Workload("cfg0", n, n, 1.0, 1.0, PARAMS_REF, u, v, w, abc=(ones, zeros, ones.copy()),
+                    safety=0.2, steps=steps, seed=seed, dt_closed_form=dt)
+
+
+def cfg1(seed: int = BASE_SEED + 1, n: int = 1024, steps: int = 20000) -> Workload:
+    """Smooth anisotropic heterogeneous tensor, five disks r = 0.03."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lam1, lam2, theta = smooth_eig_fields(rng, n, n)
+    centres = rng.uniform(0.1, 0.9, size=(5, 2))
+    u, v, w = disks_state(n, n, centres, 0.03)
+    return Workload("cfg1", n, n, 1.0, 1.0, PARAMS_REF, u, v, w, eig=(lam1, lam2, theta),
+                    safety=0.9, steps=steps, seed=seed)
+
+
+def cfg2(seed: int = BASE_SEED + 2, n: int = 4096, delta1: float = 12.5,
+         steps: int = 10000) -> Workload:
+    """Layered tissue: Voronoi regions with membranes, central disk r = 0.05."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lam1, lam2, theta = layered_eig_fields(rng, n, n)
+    u, v, w = disks_state(n, n, [(0.5, 0.5)], 0.05)
+    p = (delta1,) + PARAMS_REF[1:]
+    return Workload("cfg2", n, n, 1.0, 1.0, p, u, v, w, eig=(lam1, lam2, theta),
+                    safety=0.9, steps=steps, seed=seed, mass_every=500)
+
+
+CFG3_SIDES = tuple(range(64, 513, 32))
+
+
+def cfg3_instance(i: int, steps: int = 5000, side: Optional[int] = None) -> Workload:
+    """Instance i of the ensemble: own size, parameters, tensor and dt."""
+    seed = BASE_SEED + 1000 + i
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(rng.choice(CFG3_SIDES)) if side is None else int(side)
+    delta1 = rng.uniform(0.5, 20.0)
+    Delta2 = 10.0 ** rng.uniform(-4.0, -1.0)
+    r3 = rng.uniform(10.0, 100.0)
+    lam1, lam2, theta = smooth_eig_fields(rng, n, n)
+    u, v, w = disks_state(n, n, [(0.5, 0.5)], 0.1)
+    return Workload(f"cfg3[{i}]", n, n, 1.0, 1.0, (delta1, 1.0, Delta2, r3, r3), u, v, w,
+                    eig=(lam1, lam2, theta), safety=0.9, steps=steps, seed=seed)
+
+
+def cfg3(count: int = 256, steps: int = 5000):
+    return [cfg3_instance(i, steps) for i in range(count)]
+
+
+def cfg4(seed: int = BASE_SEED + 4, n: int = 512, steps: int = 5000) -> Workload:
+    """Smooth anisotropic tensor (true theta), five disks r = 0.03, true parameters."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lam1, lam2, theta = smooth_eig_fields(rng, n, n)
+    centres = rng.uniform(0.1, 0.9, size=(5, 2))
+    u, v, w = disks_state(n, n, centres, 0.03)
+    return Workload("cfg4", n, n, 1.0, 1.0, PARAMS_REF, u, v, w, eig=(lam1, lam2, theta),
+                    safety=0.9, steps=steps, seed=seed)
+
+
+def cfg4_perturbation(seed: int = BASE_SEED + 4, n: int = 512):
+    """Perturbed parameters (each scaled by 1 +/- 0.2, seeded signs) and a theta
+    perturbation 0.1 pi * S with S a fresh smooth field mapped to [-1, 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed + 500))
+    signs = rng.choice([-1.0, 1.0], size=5)
+    p = tuple(PARAMS_REF[k] * (1.0 + 0.2 * signs[k]) for k in range(5))
+    dtheta = 0.1 * math.pi * (2.0 * smooth_field(rng, n, n) - 1.0)
+    return p, dtheta
+
+
+def random_state(rng: np.random.Generator, nx: int, ny: int):
+    """Generic smooth-plus-noise state in [0, 1] for operator tests."""
+    u = rng.uniform(0.0, 1.0, size=(ny, nx))
+    v = rng.uniform(0.0, 1.0, size=(ny, nx))
+    w = rng.uniform(0.0, 1.0, size=(ny, nx))
+    return u, v, w
+
+
+def random_eig(rng: np.random.Generator, nx: int, ny: int, ratio_max: float = 10.0):
+    """Per-cell random SPD tensor in eigen form (rough, not smooth)."""
+    lam1 = rng.uniform(0.5, 2.0, size=(ny, nx))
+    lam2 = lam1 / rng.uniform(1.0, ratio_max, size=(ny, nx))
+    theta = rng.uniform(0.0, math.pi, size=(ny, nx))
+    return lam1, lam2, theta
+
+
+def random_abc(rng: np.random.Generator, nx: int, ny: int):
+    """Per-cell random SPD tensor drawn directly as (a, b, c): a, c uniform in
+    [0.5, 2], b = r sqrt(a c) with |r| < 0.9, so a c - b^2 > 0."""
+    a = rng.uniform(0.5, 2.0, size=(ny, nx))
+    c = rng.uniform(0.5, 2.0, size=(ny, nx))
+    b = rng.uniform(-0.9, 0.9, size=(ny, nx)) * np.sqrt(a * c)
+    return a, b, c

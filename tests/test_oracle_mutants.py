@@ -1,0 +1,92 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies the oracle's C source, applies one plausible slip (a dropped
+term, a flipped sign, a swapped index or operand, a wrong coefficient), builds the
+copy with gcc into a temporary directory, binds it in place of the real oracle
+and runs the pin tests against it.  The case passes only if at least one pin
+fails.  Everything runs on the CPU.
+"""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+# (name, original text, replacement, expected number of occurrences)
+MUTANTS = [
+    ("cross-term sign", "+ 0.5 * (b[l] * tyl + b[r] * tyr)", "- 0.5 * (b[l] * tyl + b[r] * tyr)", 1),
+    ("cross operands swapped", "b[l] * tyl + b[r] * tyr", "b[l] * tyr + b[r] * tyl", 1),
+    ("cross factor 1/2 dropped", "+ 0.5 * (b[l] * txl + b[r] * txr)", "+ (b[l] * txl + b[r] * txr)", 1),
+    ("a used on y faces", "0.5 * (c[l] + c[r]) * ((W[r] - W[l]) * idy)", "0.5 * (a[l] + a[r]) * ((W[r] - W[l]) * idy)", 1),
+    ("idy on x faces", "0.5 * (a[l] + a[r]) * ((W[r] - W[l]) * idx)", "0.5 * (a[l] + a[r]) * ((W[r] - W[l]) * idy)", 1),
+    ("tangential difference one-sided", "(W[IX(i, clampi(j + 1, ny))] - W[IX(i, clampi(j - 1, ny))])",
+     "(W[IX(i, clampi(j + 1, ny))] - W[IX(i, clampi(j, ny))])", 1),
+    ("hy in tx", "tx_at(nx, ny, W, i, j, hx)", "tx_at(nx, ny, W, i, j, hy)", 1),
+    ("mobility of one cell", "(1.0 - 0.5 * (U[l] + U[r])) * ((V[r] - V[l]) * idx)",
+     "(1.0 - U[l]) * ((V[r] - V[l]) * idx)", 1),
+    ("divergence sign", "out[IX(i, j)] = (fe - fw) * idx", "out[IX(i, j)] = (fw - fe) * idx", 1),
+    ("kill term without U", "(d1 * U) * W", "d1 * W", 1),
+    ("Delta2 dropped", "D2 * dV[k]", "dV[k]", 1),
+    ("acid rates swapped", "(r3 * V - d3 * W)", "(d3 * V - r3 * W)", 1),
+    ("logistic of wrong field", "U * (1.0 - U)", "U * (1.0 - V)", 1),
+    ("boundary face carries flux", "for (int i = 0; i + 1 < nx; ++i) {\n            size_t l = IX(i, j), r = IX(i + 1, j);\n            double tyl",
+     "for (int i = 0; i + 1 < nx; ++i) {\n            size_t l = IX(i, j), r = IX(i + 1, j);\n            if (i == 0) FX[(size_t)j * (nx + 1)] = 0.5 * b[l] * ty_at(nx, ny, W, 0, j, hy);\n            double tyl", 1),
+    ("lambda_max sign", "return m + sqrt(d * d + b * b);", "return m - sqrt(d * d + b * b);", 1),
+    ("tensor map b sign", "b[k] = (lam1[k] - lam2[k]) * (sn * cs);", "b[k] = (lam2[k] - lam1[k]) * (sn * cs);", 1),
+]
+
+PIN_TESTS = [
+    lambda o: pins.test_p1_table2_transcription(o, 17, 11, 1.0, 1.0),
+    lambda o: pins.test_p1_table1_transcription(o, 24, 31, 1.3, 0.7),
+    lambda o: pins.test_p2_isotropic_is_textbook_laplacian(o, 13, 9),
+    lambda o: pins.test_p2_mobility_special_cases(o),
+    lambda o: pins.test_p3_eigenmode_decay_w(o, 2, 3),
+    lambda o: pins.test_p3_eigenmode_decay_v(o, 1, 1),
+    lambda o: pins.test_p4_mass_conservation(o),
+    lambda o: pins.test_p5_operator_symmetry_and_nullspace(o),
+    lambda o: pins.test_p7_transpose_and_reflection(o),
+    lambda o: pins.test_p8_reactions_first_order_convergence(o),
+    lambda o: pins.test_p10_polynomials(o),
+    lambda o: pins.test_tensor_from_eig_matches_eigh(o),
+    lambda o: pins.test_stable_dt_closed_form(o),
+]
+
+
+def _build_mutant(tmp, src_text):
+    srcs = []
+    for path in oracle.sources():
+        text = open(path).read()
+        if os.path.basename(path) == "ggfv_oracle.c":
+            text = src_text
+        dst = os.path.join(tmp, os.path.basename(path))
+        with open(dst, "w") as f:
+            f.write(text)
+        srcs.append(dst)
+    lib = os.path.join(tmp, "libmutant.so")
+    subprocess.run(["gcc", *oracle.CFLAGS, *srcs, "-o", lib, "-lm"], check=True)
+    return lib
+
+
+@pytest.mark.parametrize("name,old,new,count", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(name, old, new, count):
+    base = open(oracle._SRC).read()
+    assert base.count(old) == count, f"mutation anchor for '{name}' not found"
+    mutated = base.replace(old, new)
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _build_mutant(tmp, mutated)
+        oracle.build(force=False)
+        prev = oracle.use_library(lib)
+        caught = []
+        try:
+            for k, pin in enumerate(PIN_TESTS):
+                try:
+                    pin(oracle)
+                except AssertionError:
+                    caught.append(k)
+                    break
+        finally:
+            oracle.restore_library(prev)
+    assert caught, f"no pin caught the planted mistake '{name}'"
