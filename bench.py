@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the explicit finite-volume Gatenby-Gawlinski step on one MI355X.
+
+Workload: the 4096 x 4096 layered-tissue grid (64 seeded Voronoi regions with
+piecewise-constant anisotropic tensors and two-cell low-diffusion membranes along
+region borders, central tumour disk, delta1 = 12.5), stepped at 0.9 of the
+explicit stability bound with the masses logged every 500 steps.  Inputs are
+synthetic (seeded) and resident in HBM before the timed region starts.
+
+One bench step = one forward-Euler step of the whole grid (one launch of the
+step kernel); the timed region also contains the mass diagnostics every 500
+steps.  The headline value is FP64; the compensated-FP32 and plain-FP32 variants
+are measured beside it.  The oracle is timed on the host cores on a bounded
+sample of the same workload.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PEAK_HBM_GBS = 8000.0            # MI355X HBM3E peak
+# Algorithmic HBM bytes per cell-update of one step: read u, v, w, a, b, c and
+# write u, v, w once (the compensated state reads and writes a second word of u,
+# v and w).
+BYTES_PER_CELL = {"f64": 72, "f32c": 60, "f32": 36}
+KERNEL_NAME = {"f64": "step_kernel<double, false, 1>", "f32c": "step_kernel<float, true, 2>",
+               "f32": "step_kernel<float, false, 2>"}
+METRIC = "Gcell-updates/s + % HBM peak, 4096² aniso FV step FP32/FP64; adjoint/fwd ratio"
+MASS_EVERY = 500
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_variant(pk, torch, w, dtype, steps, warmup):
+    stream = torch.cuda.current_stream()
+    ctx = pk.Context(w.nx, w.ny, w.lx, w.ly, dtype=dtype, stream=stream.cuda_stream)
+    ctx.set_params(w.params)
+    ctx.set_tensor_eig(*w.eig)
+    ctx.set_state(w.u0, w.v0, w.w0)
+    dt = ctx.stable_dt(w.safety)
+    ctx.step(dt, warmup)
+    torch.cuda.synchronize()
+    segs = []
+    masses = []
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    done = 0
+    while done < steps:
+        n = min(steps - done, MASS_EVERY - (done % MASS_EVERY))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.step(dt, n)
+        e1.record(stream)
+        segs.append((e0, e1, n))
+        done += n
+        if done % MASS_EVERY == 0:
+            masses.append(ctx.diagnostics()["mass"].tolist())
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    step_ms = sum(a.elapsed_time(b) for a, b, _ in segs)
+    kernel_us = 1e3 * step_ms / steps
+    cells = w.nx * w.ny
+    value = cells * steps / (total_ms * 1e-3) / 1e9
+    achieved = BYTES_PER_CELL[dtype] * cells / (kernel_us * 1e-6) / 1e9
+    d = ctx.diagnostics()
+    ctx.close()
+    return {
+        "value": value, "ms_per_step": total_ms / steps, "kernel_avg_us": kernel_us,
+        "wall_s": wall, "dt": dt, "achieved_GBs": achieved,
+        "frac": achieved / PEAK_HBM_GBS, "mass_log": masses, "cfl": d["cfl"],
+    }
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=20):
+    """Plain device-to-device copy bandwidth (read + write bytes per second)."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(w, steps):
+    import oracle
+    a, b, c = oracle.tensor_from_eig(*w.eig)
+    dt = oracle.stable_dt(a, b, c, w.params[2], w.safety)
+    t0 = time.perf_counter()
+    oracle.run(w.u0, w.v0, w.w0, a, b, c, w.params, dt, steps)
+    sec = time.perf_counter() - t0
+    return {"value": w.nx * w.ny * steps / sec / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the same {w.nx}x{w.ny} layered-tissue grid, one thread "
+                      f"({sec:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=4096, help="grid side (4096 for the standard workload)")
+    ap.add_argument("--variants", default="f64,f32c,f32")
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-ceiling", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU "
+              "path; the step would shard by row slabs with halo exchange.", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs as a single process on one GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2006_01748_amd as pk
+    from paper_2006_01748_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    log(f"generating {args.n}x{args.n} layered-tissue workload")
+    w = wl.cfg2(n=args.n)
+    variants = [v for v in args.variants.split(",") if v]
+    res = {}
+    for v in variants:
+        log(f"timing {v}: {args.warmup} warm-up + {args.steps} timed steps")
+        res[v] = time_variant(pk, torch, w, v, args.steps, args.warmup)
+        log(f"  {v}: {res[v]['value']:.2f} Gcell/s, kernel {res[v]['kernel_avg_us']:.1f} us, "
+            f"{res[v]['achieved_GBs']:.0f} GB/s ({100 * res[v]['frac']:.1f}% of peak)")
+    ceiling = None if args.no_copy_ceiling else copy_ceiling(torch)
+    base = None
+    if not args.no_cpu_baseline:
+        log(f"timing the oracle on {args.cpu_steps} steps")
+        base = cpu_baseline(w, args.cpu_steps)
+
+    head = variants[0]
+    r = res[head]
+    line = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {
+            "workload": f"layered tissue {w.nx}x{w.ny}: 64 Voronoi regions with anisotropic tensors "
+                        f"and membranes, central disk, delta1={w.params[0]}, dt=0.9 of the "
+                        f"stability bound, masses every {MASS_EVERY} steps",
+            "grid": [w.nx, w.ny], "params": list(w.params), "dt": r["dt"],
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": r["frac"], "traffic": None, "kernel": KERNEL_NAME[head],
+            "kernel_avg_us": r["kernel_avg_us"], "bytes_per_cell_update": BYTES_PER_CELL[head],
+        },
+        "cpu_baseline": base,
+        "variants": {v: {"value": res[v]["value"], "kernel_avg_us": res[v]["kernel_avg_us"],
+                         "achieved_GBs": res[v]["achieved_GBs"], "frac": res[v]["frac"],
+                         "bytes_per_cell_update": BYTES_PER_CELL[v], "kernel": KERNEL_NAME[v]}
+                     for v in variants},
+        "copy_ceiling_GBs": ceiling,
+        "mass_log": r["mass_log"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

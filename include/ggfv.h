@@ -1,0 +1,186 @@
+/*
+ * ggfv.h -- C ABI of the MI355X (gfx950) library for the explicit finite-volume
+ * step of the anisotropic, heterogeneous Gatenby-Gawlinski model.
+ *
+ * The model (Section 1, eq. (1)) evolves normal cells u, tumour cells v and excess
+ * lactic acid w on a rectangle [0,lx] x [0,ly] with Neumann boundaries:
+ *   du/dt = u(1-u) - delta1 u w
+ *   dv/dt = rho2 v(1-v) + Delta2 div[(1-u) grad v]
+ *   dw/dt = rho3 v - delta3 w + div(A grad w),   A = [[a,b],[b,c]] SPD (eq. (2))
+ * The paper's symbols map as d = delta1, r = rho2, alpha = Delta2, and its acid
+ * term c(v - w) is the case rho3 = delta3 = c.
+ *
+ * One library step is the fully discrete scheme eq. (3) of Section 2: forward
+ * Euler with every right-hand side at the old level, the five-point flux of
+ * Table 1 for v, the nine-point flux of Table 2 for w (face coefficients are
+ * arithmetic means of the two cells; the cross terms use central tangential
+ * differences), and zero total flux through every boundary face; tangential
+ * differences in the first/last row or column use the boundary cell itself as the
+ * missing neighbour.
+ *
+ * Grid and layout.  nx by ny cells, dx = lx/nx, dy = ly/ny, cell (i,j) centred at
+ * ((i+1/2)dx, (j+1/2)dy).  Every field crossing this ABI is a dense row-major
+ * array of nx*ny values, index j*nx + i (x fastest), no padding.  Inside the
+ * library fields are structure-of-arrays with each row padded to a multiple of 64
+ * values; the padding never crosses the ABI.
+ *
+ * Precision (ggfv_dtype) is fixed per context and covers both storage and
+ * arithmetic:
+ *   GGFV_F64   FP64 state, tensor and arithmetic.
+ *   GGFV_F32   FP32 state, tensor and arithmetic.
+ *   GGFV_F32C  FP32 tensor and arithmetic with a compensated state: each of u, v,
+ *              w is held as an unevaluated sum hi + lo of two FP32 words; the
+ *              right-hand side is evaluated in FP32 from hi, and the update
+ *              x + dt*f is added with an error-free two-sum so that increments
+ *              below half an FP32 ulp of x are not lost.
+ * Arrays exchanged with the library are FP64 or FP32 as chosen by the io_dtype
+ * argument (GGFV_F64 or GGFV_F32), independent of the context precision; the
+ * library converts.  Reading an F32C state as FP64 returns hi + lo exactly.
+ *
+ * Memory and ownership.  `where` says whether a pointer is host memory
+ * (GGFV_HOST) or device memory on the context's GPU (GGFV_DEVICE).  The library
+ * never keeps a caller pointer past the call: host arrays are copied and the
+ * call returns after the copy; device arrays are read or written by work
+ * enqueued on the context's stream, so they must stay valid until that stream
+ * reaches it.  The context owns all its device memory (state in two buffers,
+ * tensor, reduction scratch) and frees it in ggfv_destroy.
+ *
+ * Streams.  All device work is enqueued on the stream given at creation (or by
+ * ggfv_set_stream); NULL means the default stream.  Calls that return data to
+ * the host (host reads, ggfv_stable_dt, ggfv_diagnostics) synchronize that
+ * stream; ggfv_step does not.
+ *
+ * Errors.  Every int-returning call returns a ggfv_status.  Invalid arguments are
+ * rejected before any device work is enqueued.  The message of the last failure
+ * of a context is available from ggfv_last_error.  Nothing aborts or throws
+ * across this ABI.  A context is not thread-safe; separate contexts are
+ * independent.
+ */
+#ifndef GGFV_H
+#define GGFV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ggfv_ctx ggfv_ctx;
+
+typedef enum {
+    GGFV_OK = 0,
+    GGFV_EINVAL = 1,     /* bad argument: sizes, pointers, dtype, dt, non-SPD tensor */
+    GGFV_ENOMEM = 2,     /* device or host allocation failed */
+    GGFV_EHIP = 3,       /* a HIP runtime call failed (message names it) */
+    GGFV_ESTATE = 4,     /* call out of order, e.g. stepping before state/tensor are set */
+    GGFV_EUNSTABLE = 5   /* diagnostics found non-finite values or cfl > 1 */
+} ggfv_status;
+
+typedef enum { GGFV_F32 = 1, GGFV_F64 = 2, GGFV_F32C = 3 } ggfv_dtype;
+typedef enum { GGFV_HOST = 0, GGFV_DEVICE = 1 } ggfv_where;
+
+/* Reaction and diffusion parameters of eq. (1) (nondimensional). */
+typedef struct {
+    double delta1;   /* acid kill rate of normal cells (paper: d) */
+    double rho2;     /* tumour growth rate (paper: r) */
+    double Delta2;   /* tumour diffusion constant (paper: alpha) */
+    double rho3;     /* acid production rate (paper: c) */
+    double delta3;   /* acid removal rate (paper: c) */
+} ggfv_params;
+
+/* Diagnostics of the current state (Section 2's explicit scheme is limited by its
+ * CFL condition; cfl is the per-cell Gershgorin bound of the update,
+ *   cfl = dt * max_ij max(2(a idx^2 + c idy^2) + |b| idx idy,
+ *                         2 Delta2 |1-u| (idx^2 + idy^2)),
+ * idx = 1/dx, idy = 1/dy; the step is stable while cfl <= 1). */
+typedef struct {
+    double t;              /* simulated time: sum of dt over all steps taken */
+    long long steps;       /* steps taken since the state was last set */
+    double mass[3];        /* dx*dy*sum of u, v, w */
+    double vmin[3];        /* minimum of u, v, w over finite values */
+    double vmax[3];        /* maximum of u, v, w over finite values */
+    double cfl;            /* see above, for the dt of the last step */
+    long long nonfinite;   /* number of non-finite values among u, v, w */
+} ggfv_diag;
+
+/* Create a context for an nx-by-ny grid on [0,lx] x [0,ly] with precision dtype
+ * on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t or NULL).
+ * Allocates all device memory.  EINVAL if nx < 1, ny < 1, lx or ly not > 0, or
+ * dtype unknown; ENOMEM if device memory is short; EHIP if the device cannot be
+ * selected.  On failure *out is NULL. */
+int ggfv_create(ggfv_ctx **out, int nx, int ny, double lx, double ly, int dtype,
+                int device, void *hip_stream);
+
+/* Release the context and all its device memory (waits for its stream first).
+ * NULL is ignored. */
+void ggfv_destroy(ggfv_ctx *ctx);
+
+/* Replace the stream used for all later work of this context. */
+int ggfv_set_stream(ggfv_ctx *ctx, void *hip_stream);
+
+/* Set the reaction/diffusion parameters (eq. (1)).  EINVAL if any is not finite
+ * or Delta2 < 0. */
+int ggfv_set_params(ggfv_ctx *ctx, const ggfv_params *params);
+
+/* Set the per-cell tensor entries a, b, c (eq. (2); piecewise constant per cell,
+ * Section 2).  Three arrays of nx*ny io_dtype values.  The tensor is checked for
+ * positive definiteness (a > 0 and a*c - b^2 > 0 in every cell, after rounding
+ * to the context precision): EINVAL if it fails. */
+int ggfv_set_tensor(ggfv_ctx *ctx, const void *a, const void *b, const void *c,
+                    int where, int io_dtype);
+
+/* Set the tensor from its eigen-description: A = R(theta) diag(lam1, lam2)
+ * R(theta)^T, i.e. a = lam1 cos^2 + lam2 sin^2, c = lam1 sin^2 + lam2 cos^2,
+ * b = (lam1 - lam2) sin cos, evaluated on the device.  EINVAL if the result is
+ * not positive definite (lam1 or lam2 not > 0). */
+int ggfv_set_tensor_eig(ggfv_ctx *ctx, const void *lam1, const void *lam2,
+                        const void *theta, int where, int io_dtype);
+
+/* Copy the tensor out (three arrays of nx*ny io_dtype values). */
+int ggfv_get_tensor(ggfv_ctx *ctx, void *a, void *b, void *c, int where, int io_dtype);
+
+/* Set the state u, v, w (three arrays of nx*ny io_dtype values); resets the
+ * simulated time and the step count to zero. */
+int ggfv_set_state(ggfv_ctx *ctx, const void *u, const void *v, const void *w,
+                   int where, int io_dtype);
+
+/* Copy the current state out.  For GGFV_F32C read as GGFV_F64 the value is the
+ * exact sum hi + lo; read as GGFV_F32 it is hi. */
+int ggfv_get_state(ggfv_ctx *ctx, void *u, void *v, void *w, int where, int io_dtype);
+
+/* Largest stable explicit step for the current tensor and parameters:
+ *   dt = safety / (2 * max(max_ij lambda_max(A_ij), Delta2) * (idx^2 + idy^2)),
+ * lambda_max(A) = (a+c)/2 + sqrt(((a-c)/2)^2 + b^2), reduced on the device in
+ * FP64 from the stored tensor.  EINVAL unless 0 < safety. Synchronizes. */
+int ggfv_stable_dt(ggfv_ctx *ctx, double safety, double *dt_out);
+
+/* Advance the state by nsteps forward-Euler steps of eq. (3) with step dt
+ * (rounded to FP32 for F32 and F32C contexts).  Enqueues the work and returns.
+ * EINVAL if dt is not finite and > 0 or nsteps < 0; ESTATE if the state, tensor
+ * or parameters were never set.  nsteps == 0 is a no-op. */
+int ggfv_step(ggfv_ctx *ctx, double dt, long long nsteps);
+
+/* Diagnostics of the current state (FP64 accumulation in a fixed order, so the
+ * result is reproducible).  Synchronizes.  Returns GGFV_EUNSTABLE (with *out
+ * filled) if nonfinite > 0 or cfl > 1. */
+int ggfv_diagnostics(ggfv_ctx *ctx, ggfv_diag *out);
+
+/* Launch shape of the step kernel.  rows_per_strip is the number of grid rows
+ * one workgroup sweeps (0 = chosen from the grid size); any value gives the same
+ * results bit for bit.  EINVAL if negative. */
+typedef struct {
+    int rows_per_strip;
+} ggfv_tuning;
+
+int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
+int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
+
+/* Message describing the last failure of this context ("" if none). */
+const char *ggfv_last_error(const ggfv_ctx *ctx);
+
+/* Static name of a status code. */
+const char *ggfv_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GGFV_H */

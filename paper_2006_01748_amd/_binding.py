@@ -1,0 +1,273 @@
+"""ctypes binding of ``libggfv.so`` (the C ABI of include/ggfv.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Arrays may be numpy arrays (host memory) or torch tensors; a torch
+tensor on the GPU is passed as device memory and work is enqueued on torch's
+current stream unless another stream is given.  If the library has not been
+built the binding raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libggfv.so")
+
+GGFV_OK, GGFV_EINVAL, GGFV_ENOMEM, GGFV_EHIP, GGFV_ESTATE, GGFV_EUNSTABLE = range(6)
+GGFV_F32, GGFV_F64, GGFV_F32C = 1, 2, 3
+GGFV_HOST, GGFV_DEVICE = 0, 1
+
+DTYPES = {"f32": GGFV_F32, "f64": GGFV_F64, "f32c": GGFV_F32C}
+
+# Every function of the ABI, in header order: (name, restype, argtypes).
+_c = ctypes
+_VP = _c.c_void_p
+_SIGNATURES = [
+    ("ggfv_create", _c.c_int, [_c.POINTER(_VP), _c.c_int, _c.c_int, _c.c_double, _c.c_double,
+                               _c.c_int, _c.c_int, _VP]),
+    ("ggfv_destroy", None, [_VP]),
+    ("ggfv_set_stream", _c.c_int, [_VP, _VP]),
+    ("ggfv_set_params", _c.c_int, [_VP, _VP]),
+    ("ggfv_set_tensor", _c.c_int, [_VP, _VP, _VP, _VP, _c.c_int, _c.c_int]),
+    ("ggfv_set_tensor_eig", _c.c_int, [_VP, _VP, _VP, _VP, _c.c_int, _c.c_int]),
+    ("ggfv_get_tensor", _c.c_int, [_VP, _VP, _VP, _VP, _c.c_int, _c.c_int]),
+    ("ggfv_set_state", _c.c_int, [_VP, _VP, _VP, _VP, _c.c_int, _c.c_int]),
+    ("ggfv_get_state", _c.c_int, [_VP, _VP, _VP, _VP, _c.c_int, _c.c_int]),
+    ("ggfv_stable_dt", _c.c_int, [_VP, _c.c_double, _c.POINTER(_c.c_double)]),
+    ("ggfv_step", _c.c_int, [_VP, _c.c_double, _c.c_longlong]),
+    ("ggfv_diagnostics", _c.c_int, [_VP, _VP]),
+    ("ggfv_set_tuning", _c.c_int, [_VP, _VP]),
+    ("ggfv_get_tuning", _c.c_int, [_VP, _VP]),
+    ("ggfv_last_error", _c.c_char_p, [_VP]),
+    ("ggfv_status_string", _c.c_char_p, [_c.c_int]),
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("delta1", ctypes.c_double), ("rho2", ctypes.c_double),
+                ("Delta2", ctypes.c_double), ("rho3", ctypes.c_double),
+                ("delta3", ctypes.c_double)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_longlong),
+                ("mass", ctypes.c_double * 3), ("vmin", ctypes.c_double * 3),
+                ("vmax", ctypes.c_double * 3), ("cfl", ctypes.c_double),
+                ("nonfinite", ctypes.c_longlong)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("rows_per_strip", ctypes.c_int)]
+
+
+class GGFVError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def _status_name(s):
+    names = ["GGFV_OK", "GGFV_EINVAL", "GGFV_ENOMEM", "GGFV_EHIP", "GGFV_ESTATE", "GGFV_EUNSTABLE"]
+    return names[s] if 0 <= s < len(names) else f"status {s}"
+
+
+def lib():
+    """The loaded library; raises if it was never built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2006_01748_amd.build` "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, res, args in _SIGNATURES:
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_names():
+    return [s[0] for s in _SIGNATURES]
+
+
+def _torch():
+    try:
+        import torch
+        return torch
+    except ImportError:  # pragma: no cover
+        return None
+
+
+def _is_device_tensor(x):
+    t = _torch()
+    return t is not None and isinstance(x, t.Tensor) and x.is_cuda
+
+
+def _io_of(x):
+    if _is_device_tensor(x):
+        t = _torch()
+        if x.dtype == t.float64:
+            return GGFV_F64
+        if x.dtype == t.float32:
+            return GGFV_F32
+        raise TypeError(f"unsupported tensor dtype {x.dtype}")
+    if x.dtype == np.float64:
+        return GGFV_F64
+    if x.dtype == np.float32:
+        return GGFV_F32
+    raise TypeError(f"unsupported array dtype {x.dtype}")
+
+
+def _current_stream():
+    t = _torch()
+    if t is None or not t.cuda.is_available():
+        return None
+    return ctypes.c_void_p(t.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One grid, its tensor, parameters and state on one GPU (see include/ggfv.h)."""
+
+    def __init__(self, nx, ny, lx=1.0, ly=1.0, dtype="f64", device=0, stream=None):
+        self._lib = lib()
+        self.nx, self.ny, self.lx, self.ly = int(nx), int(ny), float(lx), float(ly)
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        if stream is None:
+            stream = _current_stream()
+        rc = self._lib.ggfv_create(ctypes.byref(h), self.nx, self.ny, self.lx, self.ly,
+                                   DTYPES[dtype], int(device), stream)
+        if rc != GGFV_OK:
+            raise GGFVError(rc, f"ggfv_create({nx}, {ny}, {lx}, {ly}, {dtype}, device={device}) failed")
+        self._h = h
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, rc):
+        if rc != GGFV_OK:
+            raise GGFVError(rc, self._lib.ggfv_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ggfv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _prep_in(self, arrays):
+        """Returns (pointers, where, io, keepalive) for three input arrays."""
+        if all(_is_device_tensor(x) for x in arrays):
+            xs = [x.contiguous() for x in arrays]
+            io = _io_of(xs[0])
+            if any(_io_of(x) != io for x in xs):
+                raise TypeError("all three arrays must share a dtype")
+            for x in xs:
+                if x.numel() != self.nx * self.ny:
+                    raise ValueError(f"expected {self.nx * self.ny} values, got {x.numel()}")
+            return [ctypes.c_void_p(x.data_ptr()) for x in xs], GGFV_DEVICE, io, xs
+        xs = []
+        for x in arrays:
+            if _torch() is not None and isinstance(x, _torch().Tensor):
+                x = x.cpu().numpy()
+            x = np.asarray(x)
+            if x.dtype not in (np.float32, np.float64):
+                x = x.astype(np.float64)
+            x = np.ascontiguousarray(x)
+            if x.size != self.nx * self.ny:
+                raise ValueError(f"expected {self.nx * self.ny} values, got {x.size}")
+            xs.append(x)
+        io = _io_of(xs[0])
+        xs = [x.astype(xs[0].dtype, copy=False) for x in xs]
+        return [x.ctypes.data_as(ctypes.c_void_p) for x in xs], GGFV_HOST, io, xs
+
+    def _out(self, out, dtype):
+        if out is not None:
+            return out
+        dt = np.float64 if dtype == "f64" else np.float32
+        return [np.empty((self.ny, self.nx), dtype=dt) for _ in range(3)]
+
+    def _call_out(self, fn, out, dtype):
+        outs = self._out(out, dtype)
+        if all(_is_device_tensor(x) for x in outs):
+            for x in outs:
+                if not x.is_contiguous() or x.numel() != self.nx * self.ny:
+                    raise ValueError("device outputs must be contiguous with nx*ny values")
+            ptrs = [ctypes.c_void_p(x.data_ptr()) for x in outs]
+            self._check(fn(self._h, *ptrs, GGFV_DEVICE, _io_of(outs[0])))
+        else:
+            ptrs = [x.ctypes.data_as(ctypes.c_void_p) for x in outs]
+            self._check(fn(self._h, *ptrs, GGFV_HOST, _io_of(outs[0])))
+        return tuple(outs)
+
+    # -- API ---------------------------------------------------------------
+    def set_stream(self, stream):
+        self._check(self._lib.ggfv_set_stream(self._h, stream))
+
+    def set_params(self, params):
+        p = Params(*[float(x) for x in params])
+        self._check(self._lib.ggfv_set_params(self._h, ctypes.byref(p)))
+
+    def set_tensor(self, a, b, c):
+        ptrs, where, io, keep = self._prep_in((a, b, c))
+        self._check(self._lib.ggfv_set_tensor(self._h, *ptrs, where, io))
+
+    def set_tensor_eig(self, lam1, lam2, theta):
+        ptrs, where, io, keep = self._prep_in((lam1, lam2, theta))
+        self._check(self._lib.ggfv_set_tensor_eig(self._h, *ptrs, where, io))
+
+    def get_tensor(self, out=None, dtype="f64"):
+        return self._call_out(self._lib.ggfv_get_tensor, out, dtype)
+
+    def set_state(self, u, v, w):
+        ptrs, where, io, keep = self._prep_in((u, v, w))
+        self._check(self._lib.ggfv_set_state(self._h, *ptrs, where, io))
+
+    def get_state(self, out=None, dtype="f64"):
+        return self._call_out(self._lib.ggfv_get_state, out, dtype)
+
+    def stable_dt(self, safety):
+        d = ctypes.c_double()
+        self._check(self._lib.ggfv_stable_dt(self._h, float(safety), ctypes.byref(d)))
+        return d.value
+
+    def step(self, dt, nsteps=1):
+        self._check(self._lib.ggfv_step(self._h, float(dt), int(nsteps)))
+
+    def set_tuning(self, rows_per_strip=0):
+        t = Tuning(int(rows_per_strip))
+        self._check(self._lib.ggfv_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(self._lib.ggfv_get_tuning(self._h, ctypes.byref(t)))
+        return {"rows_per_strip": t.rows_per_strip}
+
+    def diagnostics(self, allow_unstable=False):
+        d = Diag()
+        rc = self._lib.ggfv_diagnostics(self._h, ctypes.byref(d))
+        if rc != GGFV_OK and not (allow_unstable and rc == GGFV_EUNSTABLE):
+            self._check(rc)
+        return {"t": d.t, "steps": d.steps, "mass": np.array(d.mass[:]), "vmin": np.array(d.vmin[:]),
+                "vmax": np.array(d.vmax[:]), "cfl": d.cfl, "nonfinite": d.nonfinite,
+                "status": rc}

@@ -1,0 +1,385 @@
+// ggfv_api.hip -- the C ABI declared in include/ggfv.h: context lifetime, device
+// buffers, host/device transfers, argument checking and the step loop.
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ggfv_internal.hpp"
+
+using namespace ggfv;
+
+namespace {
+
+int fail(ggfv_ctx *ctx, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+
+int fail(ggfv_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+// Makes the context's device current for the scope of an API call.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t status = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) status = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+#define GGFV_HIP(ctx, call)                                                                  \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), GGFV_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+bool valid_io(int io) { return io == GGFV_F32 || io == GGFV_F64; }
+size_t io_size(int io) { return io == GGFV_F64 ? 8 : 4; }
+
+int check_ptrs(ggfv_ctx *ctx, const void *p0, const void *p1, const void *p2, int where, int io)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!p0 || !p1 || !p2) return fail(ctx, GGFV_EINVAL, "null array pointer");
+    if (where != GGFV_HOST && where != GGFV_DEVICE)
+        return fail(ctx, GGFV_EINVAL, "where must be GGFV_HOST or GGFV_DEVICE (got %d)", where);
+    if (!valid_io(io))
+        return fail(ctx, GGFV_EINVAL, "io_dtype must be GGFV_F32 or GGFV_F64 (got %d)", io);
+    return GGFV_OK;
+}
+
+int ensure_staging(ggfv_ctx *ctx)
+{
+    const size_t need = 3 * (size_t)ctx->nx * ctx->ny * sizeof(double);
+    if (ctx->staging && ctx->staging_bytes >= need) return GGFV_OK;
+    if (ctx->staging) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->staging);
+        ctx->staging = nullptr;
+    }
+    if (hipMalloc(&ctx->staging, need) != hipSuccess) {
+        ctx->staging = nullptr;
+        return fail(ctx, GGFV_ENOMEM, "cannot allocate %zu bytes of staging memory", need);
+    }
+    ctx->staging_bytes = need;
+    return GGFV_OK;
+}
+
+// Copy three dense host arrays into the staging area; returns device pointers.
+int stage_in(ggfv_ctx *ctx, const void *h0, const void *h1, const void *h2, int io,
+             const void *(&d)[3])
+{
+    int rc = ensure_staging(ctx);
+    if (rc) return rc;
+    const size_t bytes = (size_t)ctx->nx * ctx->ny * io_size(io);
+    const void *h[3] = {h0, h1, h2};
+    for (int p = 0; p < 3; ++p) {
+        char *dst = static_cast<char *>(ctx->staging) + p * bytes;
+        GGFV_HIP(ctx, hipMemcpyAsync(dst, h[p], bytes, hipMemcpyHostToDevice, ctx->stream));
+        d[p] = dst;
+    }
+    return GGFV_OK;
+}
+
+int read_result(ggfv_ctx *ctx, double *host, int count)
+{
+    const double *res = static_cast<const double *>(ctx->scratch) + (size_t)kMaxPartialBlocks * kDiagSlots;
+    GGFV_HIP(ctx, hipMemcpyAsync(host, res, count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GGFV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ggfv_status_string(int s)
+{
+    switch (s) {
+    case GGFV_OK: return "GGFV_OK";
+    case GGFV_EINVAL: return "GGFV_EINVAL";
+    case GGFV_ENOMEM: return "GGFV_ENOMEM";
+    case GGFV_EHIP: return "GGFV_EHIP";
+    case GGFV_ESTATE: return "GGFV_ESTATE";
+    case GGFV_EUNSTABLE: return "GGFV_EUNSTABLE";
+    default: return "GGFV_UNKNOWN";
+    }
+}
+
+const char *ggfv_last_error(const ggfv_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ggfv_create(ggfv_ctx **out, int nx, int ny, double lx, double ly, int dtype, int device,
+                void *hip_stream)
+{
+    if (!out) return GGFV_EINVAL;
+    *out = nullptr;
+    if (nx < 1 || ny < 1) return GGFV_EINVAL;
+    if ((long long)nx * ny > (1LL << 34)) return GGFV_EINVAL;
+    if (!(lx > 0.0) || !(ly > 0.0) || !std::isfinite(lx) || !std::isfinite(ly)) return GGFV_EINVAL;
+    if (dtype != GGFV_F32 && dtype != GGFV_F64 && dtype != GGFV_F32C) return GGFV_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GGFV_EHIP;
+
+    ggfv_ctx *ctx = new (std::nothrow) ggfv_ctx;
+    if (!ctx) return GGFV_ENOMEM;
+    ctx->nx = nx;
+    ctx->ny = ny;
+    ctx->lx = lx;
+    ctx->ly = ly;
+    ctx->dtype = dtype;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->pitch = round_up(nx, kRowAlign);
+    ctx->plane = (size_t)ctx->pitch * ny;
+    ctx->elem = (dtype == GGFV_F64) ? 8 : 4;
+    ctx->nfields = (dtype == GGFV_F32C) ? 6 : 3;
+
+    DeviceGuard g(device);
+    if (g.status != hipSuccess) {
+        delete ctx;
+        return GGFV_EHIP;
+    }
+    const size_t sbytes = ctx->nfields * ctx->plane * ctx->elem;
+    const size_t tbytes = 3 * ctx->plane * ctx->elem;
+    ctx->scratch_bytes = ((size_t)kMaxPartialBlocks * kDiagSlots + 64) * sizeof(double);
+    bool ok = hipMalloc(&ctx->state[0], sbytes) == hipSuccess &&
+              hipMalloc(&ctx->state[1], sbytes) == hipSuccess &&
+              hipMalloc(&ctx->tensor, tbytes) == hipSuccess &&
+              hipMalloc(&ctx->scratch, ctx->scratch_bytes) == hipSuccess;
+    if (ok) {
+        // zero padding columns once; every kernel keeps them zero afterwards
+        ok = hipMemset(ctx->state[0], 0, sbytes) == hipSuccess &&
+             hipMemset(ctx->state[1], 0, sbytes) == hipSuccess &&
+             hipMemset(ctx->tensor, 0, tbytes) == hipSuccess &&
+             hipMemset(ctx->scratch, 0, ctx->scratch_bytes) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        ggfv_destroy(ctx);
+        return GGFV_ENOMEM;
+    }
+    *out = ctx;
+    return GGFV_OK;
+}
+
+void ggfv_destroy(ggfv_ctx *ctx)
+{
+    if (!ctx) return;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        for (void *p : {ctx->state[0], ctx->state[1], ctx->tensor, ctx->scratch, ctx->staging})
+            if (p) (void)hipFree(p);
+    }
+    delete ctx;
+}
+
+int ggfv_set_stream(ggfv_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return GGFV_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return GGFV_OK;
+}
+
+int ggfv_set_params(ggfv_ctx *ctx, const ggfv_params *p)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!p) return fail(ctx, GGFV_EINVAL, "null params");
+    const double v[5] = {p->delta1, p->rho2, p->Delta2, p->rho3, p->delta3};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(ctx, GGFV_EINVAL, "parameters must be finite");
+    if (p->Delta2 < 0.0) return fail(ctx, GGFV_EINVAL, "Delta2 must be >= 0 (got %g)", p->Delta2);
+    ctx->prm = *p;
+    ctx->has_params = true;
+    return GGFV_OK;
+}
+
+static int check_spd(ggfv_ctx *ctx)
+{
+    GGFV_HIP(ctx, launch_spd_count(ctx));
+    double r[2];
+    int rc = read_result(ctx, r, 2);
+    if (rc) return rc;
+    if (r[0] > 0.0) {
+        ctx->has_tensor = false;
+        return fail(ctx, GGFV_EINVAL,
+                    "tensor is not positive definite in %.0f cells (need a > 0 and a*c - b^2 > 0)", r[0]);
+    }
+    ctx->has_tensor = true;
+    return GGFV_OK;
+}
+
+int ggfv_set_tensor(ggfv_ctx *ctx, const void *a, const void *b, const void *c, int where, int io)
+{
+    int rc = check_ptrs(ctx, a, b, c, where, io);
+    if (rc) return rc;
+    DeviceGuard g(ctx->device);
+    const void *d[3] = {a, b, c};
+    if (where == GGFV_HOST && (rc = stage_in(ctx, a, b, c, io, d))) return rc;
+    GGFV_HIP(ctx, launch_pack3(ctx, d[0], d[1], d[2], io == GGFV_F64, ctx->tensor, 3, false));
+    return check_spd(ctx);
+}
+
+int ggfv_set_tensor_eig(ggfv_ctx *ctx, const void *l1, const void *l2, const void *th, int where, int io)
+{
+    int rc = check_ptrs(ctx, l1, l2, th, where, io);
+    if (rc) return rc;
+    DeviceGuard g(ctx->device);
+    const void *d[3] = {l1, l2, th};
+    if (where == GGFV_HOST && (rc = stage_in(ctx, l1, l2, th, io, d))) return rc;
+    GGFV_HIP(ctx, launch_tensor_eig(ctx, d[0], d[1], d[2], io == GGFV_F64));
+    return check_spd(ctx);
+}
+
+static int copy_out(ggfv_ctx *ctx, const void *src_base, bool has_lo, void *o0, void *o1, void *o2,
+                    int where, int io)
+{
+    if (where == GGFV_DEVICE) {
+        GGFV_HIP(ctx, launch_unpack3(ctx, src_base, has_lo, o0, o1, o2, io == GGFV_F64));
+        return GGFV_OK;
+    }
+    int rc = ensure_staging(ctx);
+    if (rc) return rc;
+    const size_t bytes = (size_t)ctx->nx * ctx->ny * io_size(io);
+    char *s = static_cast<char *>(ctx->staging);
+    GGFV_HIP(ctx, launch_unpack3(ctx, src_base, has_lo, s, s + bytes, s + 2 * bytes, io == GGFV_F64));
+    void *o[3] = {o0, o1, o2};
+    for (int p = 0; p < 3; ++p)
+        GGFV_HIP(ctx, hipMemcpyAsync(o[p], s + p * bytes, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GGFV_OK;
+}
+
+int ggfv_get_tensor(ggfv_ctx *ctx, void *a, void *b, void *c, int where, int io)
+{
+    int rc = check_ptrs(ctx, a, b, c, where, io);
+    if (rc) return rc;
+    if (!ctx->has_tensor) return fail(ctx, GGFV_ESTATE, "tensor not set");
+    DeviceGuard g(ctx->device);
+    return copy_out(ctx, ctx->tensor, false, a, b, c, where, io);
+}
+
+int ggfv_set_state(ggfv_ctx *ctx, const void *u, const void *v, const void *w, int where, int io)
+{
+    int rc = check_ptrs(ctx, u, v, w, where, io);
+    if (rc) return rc;
+    DeviceGuard g(ctx->device);
+    const void *d[3] = {u, v, w};
+    if (where == GGFV_HOST && (rc = stage_in(ctx, u, v, w, io, d))) return rc;
+    GGFV_HIP(ctx, launch_pack3(ctx, d[0], d[1], d[2], io == GGFV_F64, ctx->state[ctx->cur],
+                               ctx->nfields, ctx->dtype == GGFV_F32C));
+    if (where == GGFV_HOST) GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->has_state = true;
+    ctx->t = 0.0;
+    ctx->steps = 0;
+    return GGFV_OK;
+}
+
+int ggfv_get_state(ggfv_ctx *ctx, void *u, void *v, void *w, int where, int io)
+{
+    int rc = check_ptrs(ctx, u, v, w, where, io);
+    if (rc) return rc;
+    if (!ctx->has_state) return fail(ctx, GGFV_ESTATE, "state not set");
+    DeviceGuard g(ctx->device);
+    return copy_out(ctx, ctx->state[ctx->cur], ctx->dtype == GGFV_F32C, u, v, w, where, io);
+}
+
+int ggfv_stable_dt(ggfv_ctx *ctx, double safety, double *dt_out)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!dt_out) return fail(ctx, GGFV_EINVAL, "null dt_out");
+    if (!(safety > 0.0) || !std::isfinite(safety)) return fail(ctx, GGFV_EINVAL, "safety must be > 0");
+    if (!ctx->has_tensor || !ctx->has_params) return fail(ctx, GGFV_ESTATE, "tensor and parameters must be set");
+    DeviceGuard g(ctx->device);
+    GGFV_HIP(ctx, launch_lambda_max(ctx));
+    double r[2];
+    int rc = read_result(ctx, r, 2);
+    if (rc) return rc;
+    double lm = ctx->prm.Delta2;
+    if (r[1] > lm) lm = r[1];
+    if (!(lm > 0.0)) return fail(ctx, GGFV_EINVAL, "no positive diffusion: step bound undefined");
+    const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly;
+    *dt_out = safety / (2.0 * lm * (idx * idx + idy * idy));
+    return GGFV_OK;
+}
+
+int ggfv_step(ggfv_ctx *ctx, double dt, long long nsteps)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GGFV_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+    if (nsteps < 0) return fail(ctx, GGFV_EINVAL, "nsteps must be >= 0 (got %lld)", nsteps);
+    if (!ctx->has_state || !ctx->has_tensor || !ctx->has_params)
+        return fail(ctx, GGFV_ESTATE, "state, tensor and parameters must be set before stepping");
+    if (nsteps == 0) return GGFV_OK;
+    DeviceGuard g(ctx->device);
+    const double dt_used = (ctx->dtype == GGFV_F64) ? dt : (double)(float)dt;
+    for (long long s = 0; s < nsteps; ++s) {
+        GGFV_HIP(ctx, launch_step(ctx, dt));
+        ctx->cur ^= 1;
+        ctx->t += dt_used;
+        ctx->steps += 1;
+    }
+    ctx->last_dt = dt_used;
+    return GGFV_OK;
+}
+
+int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tn)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!tn) return fail(ctx, GGFV_EINVAL, "null tuning");
+    if (tn->rows_per_strip < 0) return fail(ctx, GGFV_EINVAL, "rows_per_strip must be >= 0");
+    ctx->rows_per_strip = tn->rows_per_strip;
+    return GGFV_OK;
+}
+
+int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tn)
+{
+    if (!ctx || !tn) return GGFV_EINVAL;
+    tn->rows_per_strip = ctx->rows_per_strip;
+    return GGFV_OK;
+}
+
+int ggfv_diagnostics(ggfv_ctx *ctx, ggfv_diag *out)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!out) return fail(ctx, GGFV_EINVAL, "null output");
+    if (!ctx->has_state || !ctx->has_tensor) return fail(ctx, GGFV_ESTATE, "state and tensor must be set");
+    DeviceGuard g(ctx->device);
+    GGFV_HIP(ctx, launch_diagnostics(ctx, ctx->last_dt));
+    double r[kDiagSlots];
+    int rc = read_result(ctx, r, kDiagSlots);
+    if (rc) return rc;
+    const double dx = ctx->lx / ctx->nx, dy = ctx->ly / ctx->ny;
+    out->t = ctx->t;
+    out->steps = ctx->steps;
+    for (int q = 0; q < 3; ++q) {
+        out->mass[q] = dx * dy * r[q];
+        out->vmin[q] = r[3 + q];
+        out->vmax[q] = r[6 + q];
+    }
+    out->cfl = ctx->last_dt * r[9];
+    out->nonfinite = (long long)r[10];
+    if (out->nonfinite > 0 || out->cfl > 1.0)
+        return fail(ctx, GGFV_EUNSTABLE, "unstable state: %lld non-finite values, cfl %.3g",
+                    out->nonfinite, out->cfl);
+    return GGFV_OK;
+}
+
+}  // extern "C"

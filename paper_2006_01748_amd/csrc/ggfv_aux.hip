@@ -1,0 +1,381 @@
+// ggfv_aux.hip -- data movement and reductions around the step kernel:
+//   * dense io arrays <-> padded storage planes (with the hi/lo split of the
+//     compensated FP32 state),
+//   * the tensor from its eigen-description, A = R(theta) diag(l1, l2) R(theta)^T
+//     (eq. (2)),
+//   * the positive-definiteness check of the tensor (Sylvester's criterion),
+//   * the largest eigenvalue of A over the grid, which sets the explicit step
+//     bound of the CFL condition (Section 2),
+//   * diagnostics: masses, extrema, non-finite count and the cfl number.
+//
+// Reductions are two-pass and deterministic: each block folds a fixed
+// grid-stride slice of cells in a fixed order, reduces across its wave64s with
+// xor-butterflies and LDS, writes one partial; a single block then folds the
+// partials in index order.  All accumulation is FP64.
+
+#include <cmath>
+
+#include "ggfv_internal.hpp"
+
+namespace ggfv {
+namespace {
+
+// ---------------------------------------------------------------------------
+// packing
+
+template <typename S, typename T>
+__global__ void pack_kernel(const S *__restrict__ s0, const S *__restrict__ s1,
+                            const S *__restrict__ s2, T *__restrict__ dst, size_t plane,
+                            int nx, int ny, int pitch, bool split_lo)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= pitch || j >= ny) return;
+    const size_t o = (size_t)j * pitch + i;
+    const S *src[3] = {s0, s1, s2};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        T hi = T(0), lo = T(0);
+        if (i < nx) {
+            const S x = src[p][(size_t)j * nx + i];
+            hi = T(x);
+            if (split_lo) lo = T(double(x) - double(hi));
+        }
+        dst[p * plane + o] = hi;
+        if (split_lo) dst[(3 + p) * plane + o] = lo;
+    }
+}
+
+template <typename T, typename D>
+__global__ void unpack_kernel(const T *__restrict__ src, size_t plane, bool has_lo,
+                              D *__restrict__ d0, D *__restrict__ d1, D *__restrict__ d2,
+                              int nx, int ny, int pitch)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= nx || j >= ny) return;
+    const size_t o = (size_t)j * pitch + i;
+    D *dst[3] = {d0, d1, d2};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        double x = double(src[p * plane + o]);
+        if (has_lo && sizeof(D) == 8) x = x + double(src[(3 + p) * plane + o]);
+        dst[p][(size_t)j * nx + i] = D(x);
+    }
+}
+
+template <typename S, typename T>
+__global__ void tensor_eig_kernel(const S *__restrict__ l1, const S *__restrict__ l2,
+                                  const S *__restrict__ th, T *__restrict__ abc, size_t plane,
+                                  int nx, int ny, int pitch)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= pitch || j >= ny) return;
+    const size_t o = (size_t)j * pitch + i;
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (i < nx) {
+        const size_t k = (size_t)j * nx + i;
+        const double L1 = double(l1[k]), L2 = double(l2[k]), TH = double(th[k]);
+        const double cs = cos(TH), sn = sin(TH);
+        a = L1 * (cs * cs) + L2 * (sn * sn);
+        c = L1 * (sn * sn) + L2 * (cs * cs);
+        b = (L1 - L2) * (sn * cs);
+    }
+    abc[o] = T(a);
+    abc[plane + o] = T(b);
+    abc[2 * plane + o] = T(c);
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+
+enum class Op { Sum, Min, Max };
+
+__device__ __forceinline__ double combine(Op op, double x, double y)
+{
+    if (op == Op::Sum) return x + y;
+    if (op == Op::Min) return fmin(x, y);
+    return fmax(x, y);
+}
+
+__device__ __forceinline__ double identity(Op op)
+{
+    if (op == Op::Sum) return 0.0;
+    if (op == Op::Min) return INFINITY;
+    return -INFINITY;
+}
+
+// Block-wide reduction of NS slots with per-slot operators; result valid in
+// thread 0.  Wave64 xor-butterfly then a fixed-order pass over the four waves.
+template <int NS>
+__device__ void block_reduce(double (&x)[NS], const Op (&ops)[NS])
+{
+    __shared__ double sm[kReduceThreads / 64][NS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x[s] = combine(ops[s], x[s], __shfl_xor(x[s], off, 64));
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) sm[wv][s] = x[s];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            double r = sm[0][s];
+            for (int w = 1; w < kReduceThreads / 64; ++w) r = combine(ops[s], r, sm[w][s]);
+            x[s] = r;
+        }
+    }
+}
+
+// Final pass: fold nparts partials of NS slots (row-major [part][slot]).
+template <int NS>
+__global__ __launch_bounds__(kReduceThreads) void final_kernel(const double *__restrict__ parts,
+                                                               int nparts, double *__restrict__ out,
+                                                               Op o0, Op o1, Op o2, int nsum3)
+{
+    // slot operators: o0 for slots [0, nsum3), o1 for [nsum3, 2*nsum3), o2 for the rest
+    Op ops[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) ops[s] = s < nsum3 ? o0 : (s < 2 * nsum3 ? o1 : o2);
+    double x[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) x[s] = identity(ops[s]);
+    for (int p = threadIdx.x; p < nparts; p += kReduceThreads) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) x[s] = combine(ops[s], x[s], parts[(size_t)p * NS + s]);
+    }
+    block_reduce<NS>(x, ops);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) out[s] = x[s];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void spd_kernel(const T *__restrict__ abc, size_t plane,
+                                                             int nx, int ny, int pitch,
+                                                             double *__restrict__ parts)
+{
+    const Op ops[2] = {Op::Sum, Op::Max};
+    double x[2] = {0.0, -INFINITY};
+    const long n = (long)nx * ny;
+    for (long k = blockIdx.x * (long)kReduceThreads + threadIdx.x; k < n;
+         k += (long)gridDim.x * kReduceThreads) {
+        const int j = (int)(k / nx), i = (int)(k - (long)j * nx);
+        const size_t o = (size_t)j * pitch + i;
+        const double a = abc[o], b = abc[plane + o], c = abc[2 * plane + o];
+        const double det = a * c - b * b;
+        const bool ok = (a > 0.0) && (det > 0.0) && isfinite(a) && isfinite(b) && isfinite(c);
+        if (!ok) x[0] += 1.0;
+        // largest eigenvalue (a+c)/2 + sqrt(((a-c)/2)^2 + b^2)
+        const double m = 0.5 * (a + c), d = 0.5 * (a - c);
+        const double lm = m + sqrt(d * d + b * b);
+        if (ok) x[1] = fmax(x[1], lm);
+    }
+    block_reduce<2>(x, ops);
+    if (threadIdx.x == 0) {
+        parts[blockIdx.x * 2 + 0] = x[0];
+        parts[blockIdx.x * 2 + 1] = x[1];
+    }
+}
+
+// Diagnostics partial: slots 0-2 sums, 3-5 minima, 6-8 maxima, 9 cfl max,
+// 10 non-finite count, 11 unused (kept zero).
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void diag_kernel(const T *__restrict__ st, size_t plane,
+                                                              bool has_lo,
+                                                              const T *__restrict__ abc, int nx,
+                                                              int ny, int pitch, double idx2,
+                                                              double idy2, double idxy, double D2,
+                                                              double *__restrict__ parts)
+{
+    const Op ops[kDiagSlots] = {Op::Sum, Op::Sum, Op::Sum, Op::Min, Op::Min, Op::Min,
+                                Op::Max, Op::Max, Op::Max, Op::Max, Op::Sum, Op::Sum};
+    double x[kDiagSlots];
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) x[s] = identity(ops[s]);
+    x[9] = 0.0;
+    const long n = (long)nx * ny;
+    for (long k = blockIdx.x * (long)kReduceThreads + threadIdx.x; k < n;
+         k += (long)gridDim.x * kReduceThreads) {
+        const int j = (int)(k / nx), i = (int)(k - (long)j * nx);
+        const size_t o = (size_t)j * pitch + i;
+        double f[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            f[p] = double(st[p * plane + o]);
+            if (has_lo) f[p] = f[p] + double(st[(3 + p) * plane + o]);
+            if (!isfinite(f[p])) {
+                x[10] += 1.0;
+            } else {
+                x[p] += f[p];
+                x[3 + p] = fmin(x[3 + p], f[p]);
+                x[6 + p] = fmax(x[6 + p], f[p]);
+            }
+        }
+        const double a = abc[o], b = abc[plane + o], c = abc[2 * plane + o];
+        const double cw = 2.0 * (a * idx2 + c * idy2) + fabs(b) * idxy;
+        const double cv = 2.0 * D2 * fabs(1.0 - f[0]) * (idx2 + idy2);
+        x[9] = fmax(x[9], fmax(cw, cv));
+    }
+    block_reduce<kDiagSlots>(x, ops);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < kDiagSlots; ++s) parts[(size_t)blockIdx.x * kDiagSlots + s] = x[s];
+    }
+}
+
+// Diagnostics final pass (fixed operators per slot).
+__global__ __launch_bounds__(kReduceThreads) void diag_final_kernel(const double *__restrict__ parts,
+                                                                    int nparts, double *__restrict__ out)
+{
+    const Op ops[kDiagSlots] = {Op::Sum, Op::Sum, Op::Sum, Op::Min, Op::Min, Op::Min,
+                                Op::Max, Op::Max, Op::Max, Op::Max, Op::Sum, Op::Sum};
+    double x[kDiagSlots];
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) x[s] = identity(ops[s]);
+    for (int p = threadIdx.x; p < nparts; p += kReduceThreads) {
+#pragma unroll
+        for (int s = 0; s < kDiagSlots; ++s) x[s] = combine(ops[s], x[s], parts[(size_t)p * kDiagSlots + s]);
+    }
+    block_reduce<kDiagSlots>(x, ops);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < kDiagSlots; ++s) out[s] = x[s];
+    }
+}
+
+int reduce_blocks(const ggfv_ctx *ctx)
+{
+    const long n = (long)ctx->nx * ctx->ny;
+    long b = (n + 4L * kReduceThreads - 1) / (4L * kReduceThreads);
+    if (b < 1) b = 1;
+    if (b > kMaxPartialBlocks) b = kMaxPartialBlocks;
+    return (int)b;
+}
+
+double *parts_of(ggfv_ctx *ctx) { return static_cast<double *>(ctx->scratch); }
+double *result_of(ggfv_ctx *ctx)
+{
+    return static_cast<double *>(ctx->scratch) + (size_t)kMaxPartialBlocks * kDiagSlots;
+}
+
+}  // namespace
+
+hipError_t launch_pack3(ggfv_ctx *ctx, const void *s0, const void *s1, const void *s2,
+                        bool src_is_f64, void *dst_base, int nplanes_dst, bool split_lo)
+{
+    (void)nplanes_dst;
+    dim3 blk(256), grd((ctx->pitch + 255) / 256, ctx->ny);
+    const bool dst_f64 = (ctx->dtype == GGFV_F64);
+    if (src_is_f64 && dst_f64)
+        hipLaunchKernelGGL((pack_kernel<double, double>), grd, blk, 0, ctx->stream,
+                           (const double *)s0, (const double *)s1, (const double *)s2,
+                           (double *)dst_base, ctx->plane, ctx->nx, ctx->ny, ctx->pitch, false);
+    else if (src_is_f64 && !dst_f64)
+        hipLaunchKernelGGL((pack_kernel<double, float>), grd, blk, 0, ctx->stream,
+                           (const double *)s0, (const double *)s1, (const double *)s2,
+                           (float *)dst_base, ctx->plane, ctx->nx, ctx->ny, ctx->pitch, split_lo);
+    else if (!src_is_f64 && dst_f64)
+        hipLaunchKernelGGL((pack_kernel<float, double>), grd, blk, 0, ctx->stream,
+                           (const float *)s0, (const float *)s1, (const float *)s2,
+                           (double *)dst_base, ctx->plane, ctx->nx, ctx->ny, ctx->pitch, false);
+    else
+        hipLaunchKernelGGL((pack_kernel<float, float>), grd, blk, 0, ctx->stream,
+                           (const float *)s0, (const float *)s1, (const float *)s2,
+                           (float *)dst_base, ctx->plane, ctx->nx, ctx->ny, ctx->pitch, split_lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack3(ggfv_ctx *ctx, const void *src_base, bool has_lo, void *d0, void *d1,
+                          void *d2, bool dst_is_f64)
+{
+    dim3 blk(256), grd((ctx->nx + 255) / 256, ctx->ny);
+    const bool src_f64 = (ctx->dtype == GGFV_F64);
+    if (src_f64 && dst_is_f64)
+        hipLaunchKernelGGL((unpack_kernel<double, double>), grd, blk, 0, ctx->stream,
+                           (const double *)src_base, ctx->plane, false, (double *)d0,
+                           (double *)d1, (double *)d2, ctx->nx, ctx->ny, ctx->pitch);
+    else if (src_f64 && !dst_is_f64)
+        hipLaunchKernelGGL((unpack_kernel<double, float>), grd, blk, 0, ctx->stream,
+                           (const double *)src_base, ctx->plane, false, (float *)d0,
+                           (float *)d1, (float *)d2, ctx->nx, ctx->ny, ctx->pitch);
+    else if (!src_f64 && dst_is_f64)
+        hipLaunchKernelGGL((unpack_kernel<float, double>), grd, blk, 0, ctx->stream,
+                           (const float *)src_base, ctx->plane, has_lo, (double *)d0,
+                           (double *)d1, (double *)d2, ctx->nx, ctx->ny, ctx->pitch);
+    else
+        hipLaunchKernelGGL((unpack_kernel<float, float>), grd, blk, 0, ctx->stream,
+                           (const float *)src_base, ctx->plane, false, (float *)d0,
+                           (float *)d1, (float *)d2, ctx->nx, ctx->ny, ctx->pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_tensor_eig(ggfv_ctx *ctx, const void *l1, const void *l2, const void *th,
+                             bool src_is_f64)
+{
+    dim3 blk(256), grd((ctx->pitch + 255) / 256, ctx->ny);
+    const bool dst_f64 = (ctx->dtype == GGFV_F64);
+#define GGFV_EIG(S, T)                                                                         \
+    hipLaunchKernelGGL((tensor_eig_kernel<S, T>), grd, blk, 0, ctx->stream, (const S *)l1,       \
+                       (const S *)l2, (const S *)th, (T *)ctx->tensor, ctx->plane, ctx->nx,      \
+                       ctx->ny, ctx->pitch)
+    if (src_is_f64 && dst_f64) GGFV_EIG(double, double);
+    else if (src_is_f64) GGFV_EIG(double, float);
+    else if (dst_f64) GGFV_EIG(float, double);
+    else GGFV_EIG(float, float);
+#undef GGFV_EIG
+    return hipGetLastError();
+}
+
+// Writes (count of non-SPD cells, max lambda_max over SPD cells) to result[0..1].
+hipError_t launch_spd_count(ggfv_ctx *ctx)
+{
+    const int nb = reduce_blocks(ctx);
+    if (ctx->dtype == GGFV_F64)
+        hipLaunchKernelGGL((spd_kernel<double>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
+                           (const double *)ctx->tensor, ctx->plane, ctx->nx, ctx->ny, ctx->pitch,
+                           parts_of(ctx));
+    else
+        hipLaunchKernelGGL((spd_kernel<float>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
+                           (const float *)ctx->tensor, ctx->plane, ctx->nx, ctx->ny, ctx->pitch,
+                           parts_of(ctx));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((final_kernel<2>), dim3(1), dim3(kReduceThreads), 0, ctx->stream,
+                       parts_of(ctx), nb, result_of(ctx), Op::Sum, Op::Max, Op::Max, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_lambda_max(ggfv_ctx *ctx) { return launch_spd_count(ctx); }
+
+hipError_t launch_diagnostics(ggfv_ctx *ctx, double dt)
+{
+    (void)dt;
+    const int nb = reduce_blocks(ctx);
+    const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly;
+    const bool lo = (ctx->dtype == GGFV_F32C);
+    if (ctx->dtype == GGFV_F64)
+        hipLaunchKernelGGL((diag_kernel<double>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
+                           (const double *)ctx->state[ctx->cur], ctx->plane, false,
+                           (const double *)ctx->tensor, ctx->nx, ctx->ny, ctx->pitch, idx * idx,
+                           idy * idy, idx * idy, ctx->prm.Delta2, parts_of(ctx));
+    else
+        hipLaunchKernelGGL((diag_kernel<float>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
+                           (const float *)ctx->state[ctx->cur], ctx->plane, lo,
+                           (const float *)ctx->tensor, ctx->nx, ctx->ny, ctx->pitch, idx * idx,
+                           idy * idy, idx * idy, ctx->prm.Delta2, parts_of(ctx));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kReduceThreads), 0, ctx->stream,
+                       parts_of(ctx), nb, result_of(ctx));
+    return hipGetLastError();
+}
+
+}  // namespace ggfv

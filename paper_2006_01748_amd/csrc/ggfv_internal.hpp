@@ -1,0 +1,90 @@
+// ggfv_internal.hpp -- context layout and kernel launchers shared by the HIP
+// sources of the library.  Not part of the public ABI (include/ggfv.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+
+#include "ggfv.h"
+
+namespace ggfv {
+
+// Every row of every internal field is padded to a multiple of this many values
+// so that wide vector loads of a row never straddle into the next row.
+constexpr int kRowAlign = 64;
+
+// Workgroup size of the streaming step kernel (four wave64s side by side).
+constexpr int kStepThreads = 256;
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Scratch layout (bytes): reduction partials of up to kMaxPartialBlocks blocks,
+// a small result area and an integer counter.
+constexpr int kReduceThreads = 256;
+constexpr int kMaxPartialBlocks = 1024;
+constexpr int kDiagSlots = 12;    // per-block partials of the diagnostics reduction
+
+}  // namespace ggfv
+
+struct ggfv_ctx {
+    int nx = 0, ny = 0, pitch = 0;
+    double lx = 1.0, ly = 1.0;
+    int dtype = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    size_t plane = 0;        // pitch * ny values per field
+    size_t elem = 0;         // bytes per stored value (4 or 8)
+    int nfields = 0;         // stored state fields: 3, or 6 for the compensated state
+    void *state[2] = {nullptr, nullptr};
+    int cur = 0;             // which of state[0], state[1] holds the current level
+    void *tensor = nullptr;  // a, b, c planes
+    void *scratch = nullptr; // reduction partials and counters
+    size_t scratch_bytes = 0;
+    void *staging = nullptr; // dense host<->device staging area (3 * nx*ny doubles)
+    size_t staging_bytes = 0;
+
+    ggfv_params prm{};
+    bool has_state = false, has_tensor = false, has_params = false;
+    double t = 0.0;
+    long long steps = 0;
+    double last_dt = 0.0;
+    int rows_per_strip = 0;  // 0: chosen per launch
+
+    std::string err;
+};
+
+namespace ggfv {
+
+// Pointers to the planes of one stored state level (lo planes are null unless
+// the state is compensated).
+template <typename T>
+struct StatePlanes {
+    T *u, *v, *w, *ulo, *vlo, *wlo;
+};
+
+// ---- kernel launchers (each returns the hipError_t of its launch) ----------
+
+// One step of eq. (3) from state[cur] to state[1 - cur].
+hipError_t launch_step(ggfv_ctx *ctx, double dt);
+
+// Dense io array (float or double, nx*ny) -> padded storage planes (and lo
+// planes for the compensated state).  src_is_f64 selects the io type.
+hipError_t launch_pack3(ggfv_ctx *ctx, const void *s0, const void *s1, const void *s2,
+                        bool src_is_f64, void *dst_base, int nplanes_dst, bool split_lo);
+// Padded storage -> dense io arrays.
+hipError_t launch_unpack3(ggfv_ctx *ctx, const void *src_base, bool has_lo, void *d0,
+                          void *d1, void *d2, bool dst_is_f64);
+// (lam1, lam2, theta) dense io arrays -> tensor planes a, b, c.
+hipError_t launch_tensor_eig(ggfv_ctx *ctx, const void *l1, const void *l2,
+                             const void *th, bool src_is_f64);
+// Count of cells whose stored tensor is not SPD -> *(unsigned long long*)scratch.
+hipError_t launch_spd_count(ggfv_ctx *ctx);
+// max over cells of lambda_max(A) -> *(double*)scratch (FP64).
+hipError_t launch_lambda_max(ggfv_ctx *ctx);
+// Diagnostics partials and final reduction -> kDiagSlots doubles at scratch.
+hipError_t launch_diagnostics(ggfv_ctx *ctx, double dt);
+
+}  // namespace ggfv

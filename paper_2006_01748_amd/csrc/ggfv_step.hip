@@ -1,0 +1,376 @@
+// ggfv_step.hip -- the explicit finite-volume step of eq. (3) for gfx950.
+//
+// One launch advances the whole grid by one forward-Euler step (Section 2): every
+// cell reads the old level of u, v, w and the tensor a, b, c, and writes the new
+// level of u, v, w into the other state buffer.
+//
+// Work decomposition.  A workgroup of 256 threads (four wave64s side by side)
+// owns a vertical strip of TXW = 256*CPL columns and `rows` rows.  Each thread
+// owns CPL adjacent columns and marches up its strip one row at a time
+// (a streaming, "2.5D" sweep): the newest row of every field is loaded once from
+// HBM with coalesced CPL-wide vector loads, staged in small LDS row rings for the
+// x-neighbours, and the y-neighbours are carried in registers from the previous
+// rows.  The y-face fluxes are carried too: the north face of row j is the south
+// face of row j+1, so each face flux is evaluated once and both cells see
+// identical bits (exact telescoping, hence exact conservation up to the sum).
+// The x-face fluxes are evaluated by both neighbouring threads from identical
+// operands in identical order, so they agree bit for bit as well.
+//
+// Boundaries (Section 2, Neumann): faces on the domain boundary carry zero flux;
+// the tangential differences in the first/last row and column take the boundary
+// cell itself as the missing neighbour.  Both are realised by clamping row and
+// column indices into the grid and zeroing boundary faces explicitly.
+//
+// Arithmetic order per cell (the same order as any FP64 reference must use for
+// bitwise agreement; no contraction into FMA, the library is built with
+// -ffp-contract=off):
+//   ty = (W(i,j+1) - W(i,j-1))*hy,  tx = (W(i+1,j) - W(i-1,j))*hx
+//   FX(i+1/2) = 0.5*(a_l + a_r)*((W_r - W_l)*idx) + 0.5*(b_l*ty_l + b_r*ty_r)
+//   FY(j+1/2) = 0.5*(c_l + c_r)*((W_r - W_l)*idy) + 0.5*(b_l*tx_l + b_r*tx_r)
+//   GX, GY    = (1 - 0.5*(U_l + U_r))*((V_r - V_l)*idx or idy)
+//   divW = (FX_e - FX_w)*idx + (FY_n - FY_s)*idy, divV alike
+//   U' = U + dt*(U*(1-U) - (delta1*U)*W)
+//   V' = V + dt*((rho2*V)*(1-V) + Delta2*divV)
+//   W' = W + dt*((rho3*V - delta3*W) + divW)
+// For the compensated FP32 state the increment dt*f is added to x = hi + lo as
+// s = hi + (dt*f + lo) with an error-free two-sum, which keeps the part of the
+// increment that falls below half an FP32 ulp of hi.
+//
+// XCD-aware order: workgroups are dealt round-robin to the eight XCDs, so the
+// linear workgroup id is remapped so that each XCD receives one contiguous band of
+// strips; horizontally adjacent strips (which re-read each other's edge columns)
+// then share one L2.
+
+#include "ggfv_internal.hpp"
+
+namespace ggfv {
+namespace {
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) VecN {
+    T v[N];
+};
+
+template <typename T>
+struct StepArgs {
+    const T *u, *v, *w, *ulo, *vlo, *wlo;   // old level (lo only if compensated)
+    T *un, *vn, *wn, *unlo, *vnlo, *wnlo;   // new level
+    const T *a, *b, *c;
+    int nx, ny, pitch, rows;
+    T idx, idy, hx, hy, dt;
+    T d1, r2, D2, r3, d3;
+};
+
+// Values of one row that a thread needs: its own CPL columns of every field.
+template <typename T, bool COMP, int CPL>
+struct Row {
+    T W[CPL], U[CPL], V[CPL], a[CPL], b[CPL], c[CPL];
+    T Ulo[COMP ? CPL : 1], Vlo[COMP ? CPL : 1], Wlo[COMP ? CPL : 1];
+    // halo column value (only meaningful in the two halo threads)
+    T hW, hU, hV, ha, hb;
+};
+
+template <typename T, int CPL>
+__device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&out)[CPL])
+{
+    VecN<T, CPL> x = *reinterpret_cast<const VecN<T, CPL> *>(p);
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) out[k] = x.v[k];
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&in)[CPL])
+{
+    VecN<T, CPL> x;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) x.v[k] = in[k];
+    *reinterpret_cast<VecN<T, CPL> *>(p) = x;
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ void lds_store_vec(T *p, const T (&in)[CPL])
+{
+    VecN<T, CPL> x;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) x.v[k] = in[k];
+    *reinterpret_cast<VecN<T, CPL> *>(p) = x;
+}
+
+// Load row `jr` (already clamped into [0, ny)) for the thread's columns starting
+// at `col` (clamped so the vector stays inside the padded row), plus the halo
+// column `hcol` when hcol >= 0.
+template <typename T, bool COMP, int CPL>
+__device__ __forceinline__ void load_row(const StepArgs<T> &A, int jr, int col, int hcol,
+                                         Row<T, COMP, CPL> &r)
+{
+    const size_t base = (size_t)jr * A.pitch;
+    load_vec<T, CPL>(A.w + base + col, r.W);
+    load_vec<T, CPL>(A.u + base + col, r.U);
+    load_vec<T, CPL>(A.v + base + col, r.V);
+    load_vec<T, CPL>(A.a + base + col, r.a);
+    load_vec<T, CPL>(A.b + base + col, r.b);
+    load_vec<T, CPL>(A.c + base + col, r.c);
+    if constexpr (COMP) {
+        load_vec<T, CPL>(A.ulo + base + col, r.Ulo);
+        load_vec<T, CPL>(A.vlo + base + col, r.Vlo);
+        load_vec<T, CPL>(A.wlo + base + col, r.Wlo);
+    }
+    if (hcol >= 0) {
+        r.hW = A.w[base + hcol];
+        r.hU = A.u[base + hcol];
+        r.hV = A.v[base + hcol];
+        r.ha = A.a[base + hcol];
+        r.hb = A.b[base + hcol];
+    }
+}
+
+// x + inc with the compensated pair (hi, lo): returns new (hi, lo).
+template <typename T>
+__device__ __forceinline__ void comp_add(T hi, T lo, T inc_dt, T &nhi, T &nlo)
+{
+    const T d = inc_dt + lo;
+    const T s = hi + d;
+    const T bb = s - hi;
+    const T e = (hi - (s - bb)) + (d - bb);
+    nhi = s;
+    nlo = e;
+}
+
+template <typename T, bool COMP, int CPL>
+__global__ __launch_bounds__(kStepThreads) void step_kernel(StepArgs<T> A)
+{
+    constexpr int NT = kStepThreads;
+    constexpr int TXW = NT * CPL;          // owned columns per workgroup
+    constexpr int LW = TXW + 2 * CPL;      // LDS row: CPL pad, TXW owned, CPL pad
+    __shared__ __align__(16) T sW[4][LW];  // W rows j-1, j, j+1 (+1 being filled)
+    __shared__ __align__(16) T sU[2][LW];
+    __shared__ __align__(16) T sV[2][LW];
+    __shared__ __align__(16) T sA[2][LW];
+    __shared__ __align__(16) T sB[2][LW];
+
+    // XCD-aware remap of the linear workgroup id to a (strip x, strip y) tile.
+    const int nbx = gridDim.x;
+    const int nb = gridDim.x * gridDim.y;
+    const int bid = blockIdx.x + nbx * blockIdx.y;
+    const int xcd = bid & 7, q = nb >> 3, rem = nb & 7;
+    const int lid = xcd * q + min(xcd, rem) + (bid >> 3);
+    const int sx = lid % nbx, sy = lid / nbx;
+
+    const int t = threadIdx.x;
+    const int nx = A.nx, ny = A.ny;
+    const int i0 = sx * TXW;
+    const int j0 = sy * A.rows;
+    const int j1 = min(ny, j0 + A.rows);
+    const int js = j0 > 0 ? j0 - 1 : j0;   // first row swept (warm-up row for FY_s)
+
+    // Own columns i0 + t*CPL .. +CPL-1; the vector load address is clamped into
+    // the padded row (values beyond nx are never used as neighbours).
+    const int cbase = i0 + t * CPL;
+    const int lcol = min(cbase, A.pitch - CPL);
+    // Halo columns: thread 0 loads i0-1, thread NT-1 loads i0+TXW (when inside).
+    int hcol = -1;
+    if (t == 0 && i0 > 0) hcol = i0 - 1;
+    if (t == NT - 1 && i0 + TXW < nx) hcol = i0 + TXW;
+    const int hpos = (t == 0) ? CPL - 1 : TXW + CPL;
+
+    auto clampj = [&](int j) { return j < 0 ? 0 : (j >= ny ? ny - 1 : j); };
+    // LDS position of a neighbour column, with mirrored (clamped) index.
+    auto posof = [&](int i) {
+        const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+        return ic - i0 + CPL;
+    };
+
+    Row<T, COMP, CPL> cur, nxt, pre;
+    T Wprev[CPL];
+    {
+        Row<T, COMP, CPL> rp;
+        load_row<T, COMP, CPL>(A, clampj(js - 1), lcol, hcol, rp);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) Wprev[k] = rp.W[k];
+        lds_store_vec<T, CPL>(&sW[(js - 1) & 3][t * CPL + CPL], rp.W);
+        if (hcol >= 0) sW[(js - 1) & 3][hpos] = rp.hW;
+    }
+    load_row<T, COMP, CPL>(A, clampj(js), lcol, hcol, cur);
+    lds_store_vec<T, CPL>(&sW[js & 3][t * CPL + CPL], cur.W);
+    if (hcol >= 0) sW[js & 3][hpos] = cur.hW;
+    load_row<T, COMP, CPL>(A, clampj(js + 1), lcol, hcol, nxt);
+
+    const T half = T(0.5), one = T(1);
+    T FYs[CPL], GYs[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) { FYs[k] = T(0); GYs[k] = T(0); }
+
+    for (int jj = js; jj < j1; ++jj) {
+        // Publish W(jj+1) and U, V, a, b (jj) for the x-neighbours.
+        {
+            const int s4 = (jj + 1) & 3, s2 = jj & 1;
+            lds_store_vec<T, CPL>(&sW[s4][t * CPL + CPL], nxt.W);
+            lds_store_vec<T, CPL>(&sU[s2][t * CPL + CPL], cur.U);
+            lds_store_vec<T, CPL>(&sV[s2][t * CPL + CPL], cur.V);
+            lds_store_vec<T, CPL>(&sA[s2][t * CPL + CPL], cur.a);
+            lds_store_vec<T, CPL>(&sB[s2][t * CPL + CPL], cur.b);
+            if (hcol >= 0) {
+                sW[s4][hpos] = nxt.hW;
+                sU[s2][hpos] = cur.hU;
+                sV[s2][hpos] = cur.hV;
+                sA[s2][hpos] = cur.ha;
+                sB[s2][hpos] = cur.hb;
+            }
+        }
+        __syncthreads();
+        // Prefetch row jj+2 while this row is computed.
+        if (jj + 2 <= j1) load_row<T, COMP, CPL>(A, clampj(jj + 2), lcol, hcol, pre);
+
+        const T *Wm = sW[(jj - 1) & 3];
+        const T *W0 = sW[jj & 3];
+        const T *Wp = sW[(jj + 1) & 3];
+        const T *U0 = sU[jj & 1];
+        const T *V0 = sV[jj & 1];
+        const T *A0 = sA[jj & 1];
+        const T *B0 = sB[jj & 1];
+        const bool has_n = (jj + 1 < ny);
+        const bool upd = (jj >= j0);
+
+        T ou[CPL], ov[CPL], ow[CPL], oul[CPL], ovl[CPL], owl[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            const int i = cbase + k;
+            const int pl = posof(i - 1), pr = posof(i + 1);
+            const T Wc = cur.W[k], Wn = nxt.W[k], Ws = Wprev[k];
+            const T WL = W0[pl], WR = W0[pr];
+            const T WLn = Wp[pl], WRn = Wp[pr];
+            const T WLs = Wm[pl], WRs = Wm[pr];
+            const T Uc = cur.U[k], Vc = cur.V[k];
+            const T UL = U0[pl], UR = U0[pr], VL = V0[pl], VR = V0[pr];
+            const T ac = cur.a[k], aL = A0[pl], aR = A0[pr];
+            const T bc = cur.b[k], bL = B0[pl], bR = B0[pr];
+
+            const T tyc = (Wn - Ws) * A.hy;
+            const T tyL = (WLn - WLs) * A.hy;
+            const T tyR = (WRn - WRs) * A.hy;
+            const T txc = (WR - WL) * A.hx;
+            const T txn = (WRn - WLn) * A.hx;
+
+            const bool has_e = (i + 1 < nx), has_w = (i > 0);
+            const T FXe = has_e ? half * (ac + aR) * ((WR - Wc) * A.idx) + half * (bc * tyc + bR * tyR) : T(0);
+            const T FXw = has_w ? half * (aL + ac) * ((Wc - WL) * A.idx) + half * (bL * tyL + bc * tyc) : T(0);
+            const T FYn = has_n ? half * (cur.c[k] + nxt.c[k]) * ((Wn - Wc) * A.idy) +
+                                      half * (bc * txc + nxt.b[k] * txn)
+                                : T(0);
+            const T GXe = has_e ? (one - half * (Uc + UR)) * ((VR - Vc) * A.idx) : T(0);
+            const T GXw = has_w ? (one - half * (UL + Uc)) * ((Vc - VL) * A.idx) : T(0);
+            const T GYn = has_n ? (one - half * (Uc + nxt.U[k])) * ((nxt.V[k] - Vc) * A.idy) : T(0);
+
+            const T divW = (FXe - FXw) * A.idx + (FYn - FYs[k]) * A.idy;
+            const T divV = (GXe - GXw) * A.idx + (GYn - GYs[k]) * A.idy;
+            const T fu = Uc * (one - Uc) - (A.d1 * Uc) * Wc;
+            const T fv = (A.r2 * Vc) * (one - Vc) + A.D2 * divV;
+            const T fw = (A.r3 * Vc - A.d3 * Wc) + divW;
+            const bool inside = (i < nx);
+            if constexpr (COMP) {
+                T h, l;
+                comp_add(Uc, cur.Ulo[k], A.dt * fu, h, l);
+                ou[k] = inside ? h : T(0);
+                oul[k] = inside ? l : T(0);
+                comp_add(Vc, cur.Vlo[k], A.dt * fv, h, l);
+                ov[k] = inside ? h : T(0);
+                ovl[k] = inside ? l : T(0);
+                comp_add(Wc, cur.Wlo[k], A.dt * fw, h, l);
+                ow[k] = inside ? h : T(0);
+                owl[k] = inside ? l : T(0);
+            } else {
+                ou[k] = inside ? Uc + A.dt * fu : T(0);
+                ov[k] = inside ? Vc + A.dt * fv : T(0);
+                ow[k] = inside ? Wc + A.dt * fw : T(0);
+            }
+            FYs[k] = FYn;
+            GYs[k] = GYn;
+        }
+        if (upd && cbase < A.pitch) {
+            const size_t o = (size_t)jj * A.pitch + cbase;
+            store_vec<T, CPL>(A.un + o, ou);
+            store_vec<T, CPL>(A.vn + o, ov);
+            store_vec<T, CPL>(A.wn + o, ow);
+            if constexpr (COMP) {
+                store_vec<T, CPL>(A.unlo + o, oul);
+                store_vec<T, CPL>(A.vnlo + o, ovl);
+                store_vec<T, CPL>(A.wnlo + o, owl);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) Wprev[k] = cur.W[k];
+        cur = nxt;
+        nxt = pre;
+    }
+}
+
+template <typename T, bool COMP, int CPL>
+hipError_t launch_typed(ggfv_ctx *ctx, double dt)
+{
+    StepArgs<T> A{};
+    T *in = static_cast<T *>(ctx->state[ctx->cur]);
+    T *out = static_cast<T *>(ctx->state[1 - ctx->cur]);
+    const size_t P = ctx->plane;
+    A.u = in;
+    A.v = in + P;
+    A.w = in + 2 * P;
+    A.un = out;
+    A.vn = out + P;
+    A.wn = out + 2 * P;
+    if (COMP) {
+        A.ulo = in + 3 * P;
+        A.vlo = in + 4 * P;
+        A.wlo = in + 5 * P;
+        A.unlo = out + 3 * P;
+        A.vnlo = out + 4 * P;
+        A.wnlo = out + 5 * P;
+    }
+    const T *tn = static_cast<const T *>(ctx->tensor);
+    A.a = tn;
+    A.b = tn + P;
+    A.c = tn + 2 * P;
+    A.nx = ctx->nx;
+    A.ny = ctx->ny;
+    A.pitch = ctx->pitch;
+    const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly;
+    A.idx = T(idx);
+    A.idy = T(idy);
+    A.hx = T(0.5 * idx);
+    A.hy = T(0.5 * idy);
+    A.dt = T(dt);
+    A.d1 = T(ctx->prm.delta1);
+    A.r2 = T(ctx->prm.rho2);
+    A.D2 = T(ctx->prm.Delta2);
+    A.r3 = T(ctx->prm.rho3);
+    A.d3 = T(ctx->prm.delta3);
+
+    constexpr int TXW = kStepThreads * CPL;
+    const int nbx = (ctx->nx + TXW - 1) / TXW;
+    int rows = ctx->rows_per_strip;
+    if (rows <= 0) {
+        // Aim for about four workgroups per CU (256 CUs) with strips of >= 16 rows.
+        const long target = 1024;
+        long per = ((long)ctx->ny * nbx + target - 1) / target;
+        rows = (int)(per < 16 ? 16 : per);
+    }
+    if (rows > ctx->ny) rows = ctx->ny;
+    A.rows = rows;
+    const int nby = (ctx->ny + rows - 1) / rows;
+    hipLaunchKernelGGL((step_kernel<T, COMP, CPL>), dim3(nbx, nby), dim3(kStepThreads), 0,
+                       ctx->stream, A);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step(ggfv_ctx *ctx, double dt)
+{
+    switch (ctx->dtype) {
+    case GGFV_F64: return launch_typed<double, false, 1>(ctx, dt);
+    case GGFV_F32: return launch_typed<float, false, 2>(ctx, dt);
+    case GGFV_F32C: return launch_typed<float, true, 2>(ctx, dt);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ggfv

@@ -111,19 +111,20 @@ def smooth_eig_fields(rng: np.random.Generator, nx: int, ny: int,
     return lam1, lam2, theta
 
 
-def voronoi_labels(rng: np.random.Generator, nx: int, ny: int, nseeds: int = 64,
-                   chunk_rows: int = 64) -> np.ndarray:
-    """Nearest-seed labels of cell centres (ties go to the lower seed index)."""
+def voronoi_labels(rng: np.random.Generator, nx: int, ny: int, nseeds: int = 64) -> np.ndarray:
+    """Nearest-seed labels of cell centres (ties go to the lower seed index: a
+    later seed replaces the running best only when strictly closer)."""
     seeds = rng.uniform(0.0, 1.0, size=(nseeds, 2))
     x = (np.arange(nx) + 0.5) / nx
-    labels = np.empty((ny, nx), dtype=np.int32)
-    for j0 in range(0, ny, chunk_rows):
-        j1 = min(ny, j0 + chunk_rows)
-        y = (np.arange(j0, j1) + 0.5) / ny
-        dx2 = (x[None, :] - seeds[:, 0:1]) ** 2            # (nseeds, nx)
-        dy2 = (y[None, :] - seeds[:, 1:2]) ** 2            # (nseeds, rows)
-        d2 = dy2[:, :, None] + dx2[:, None, :]             # (nseeds, rows, nx)
-        labels[j0:j1] = np.argmin(d2, axis=0)              # first minimum = lower index
+    y = (np.arange(ny) + 0.5) / ny
+    best = np.full((ny, nx), np.inf)
+    labels = np.zeros((ny, nx), dtype=np.int32)
+    d = np.empty((ny, nx))
+    for s in range(nseeds):
+        np.add(((y - seeds[s, 1]) ** 2)[:, None], ((x - seeds[s, 0]) ** 2)[None, :], out=d)
+        closer = d < best
+        np.copyto(best, d, where=closer)
+        labels[closer] = s
     return labels
 
 

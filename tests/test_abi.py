@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI: the built library loads, exports every function
+that include/ggfv.h declares, the binding covers exactly those, argument checks
+that run before any device work reject bad input, and the product path has no
+CPU fallback.  No GPU is used."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2006_01748_amd as pk
+from paper_2006_01748_amd import _binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ggfv.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ggfv_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(_binding.LIB_PATH):
+        from paper_2006_01748_amd import build
+        build.build()
+    return _binding.LIB_PATH
+
+
+def test_every_declared_symbol_is_exported(built):
+    lib = ctypes.CDLL(built)
+    names = header_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header_exactly():
+    assert sorted(pk.exported_names()) == header_functions()
+
+
+def test_library_does_not_contain_oracle(built):
+    out = subprocess.run(["nm", "-D", built], capture_output=True, text=True).stdout
+    assert "orc_" not in out
+    assert "ggfv_step" in out
+
+
+def test_status_strings(built):
+    lib = pk.lib()
+    assert lib.ggfv_status_string(0) == b"GGFV_OK"
+    assert lib.ggfv_status_string(5) == b"GGFV_EUNSTABLE"
+    assert lib.ggfv_status_string(99) == b"GGFV_UNKNOWN"
+
+
+@pytest.mark.parametrize("nx,ny,lx,ly,dtype", [
+    (0, 4, 1.0, 1.0, pk.GGFV_F64), (4, -1, 1.0, 1.0, pk.GGFV_F64), (4, 4, 0.0, 1.0, pk.GGFV_F64),
+    (4, 4, 1.0, float("nan"), pk.GGFV_F64), (4, 4, 1.0, 1.0, 7), (1 << 20, 1 << 20, 1.0, 1.0, pk.GGFV_F64)])
+def test_create_rejects_bad_arguments_before_device_work(built, nx, ny, lx, ly, dtype):
+    lib = pk.lib()
+    h = ctypes.c_void_p(123)
+    rc = lib.ggfv_create(ctypes.byref(h), nx, ny, lx, ly, dtype, 0, None)
+    assert rc == pk.GGFV_EINVAL
+    assert h.value is None
+
+
+def test_null_context_is_rejected(built):
+    lib = pk.lib()
+    assert lib.ggfv_step(None, 1e-3, 1) == pk.GGFV_EINVAL
+    assert lib.ggfv_set_params(None, None) == pk.GGFV_EINVAL
+    assert lib.ggfv_diagnostics(None, None) == pk.GGFV_EINVAL
+    assert lib.ggfv_create(None, 4, 4, 1.0, 1.0, pk.GGFV_F64, 0, None) == pk.GGFV_EINVAL
+    lib.ggfv_destroy(None)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_binding, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(_binding, "_lib", None)
+    with pytest.raises(ImportError):
+        _binding.lib()

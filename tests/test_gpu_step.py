@@ -1,0 +1,341 @@
+"""GPU parity of the HIP step against the FP64 oracle (through the C ABI).
+
+Bar: FP64 within 1e-12 relative max-norm per field (bitwise agreement is expected
+since both sides follow the same arithmetic order without FMA, and is checked
+where both sides see identical inputs); FP32 with compensated state within 1e-5
+relative after 1e4 steps against the FP64 oracle run on the FP32-rounded inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_01748_amd as pk
+from paper_2006_01748_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SEED = wl.BASE_SEED + 300
+PRM = wl.PARAMS_REF
+
+
+def rng(k):
+    return np.random.Generator(np.random.PCG64(SEED + k))
+
+
+def rel_err(got, ref):
+    return max(float(np.max(np.abs(np.asarray(g, np.float64) - r)) / max(np.max(np.abs(r)), 1e-300))
+               for g, r in zip(got, ref))
+
+
+def gpu_ctx(nx, ny, dtype, params, state, abc=None, eig=None, lx=1.0, ly=1.0, rows=0):
+    ctx = pk.Context(nx, ny, lx, ly, dtype=dtype)
+    ctx.set_params(params)
+    if abc is not None:
+        ctx.set_tensor(*abc)
+    else:
+        ctx.set_tensor_eig(*eig)
+    ctx.set_state(*state)
+    if rows:
+        ctx.set_tuning(rows)
+    return ctx
+
+
+# ---------------------------------------------------------------------------
+# FP64
+
+def test_f64_isotropic_disk_full_run():
+    """128^2, A = I, central disk, 2000 steps at dt = 0.2 h^2/(4 max(1, Delta2))."""
+    w = wl.cfg0()
+    ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), abc=w.abc)
+    dt = ctx.stable_dt(0.2)
+    assert dt == w.dt_closed_form
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    ref = oracle.run(w.u0, w.v0, w.w0, *w.abc, w.params, dt, w.steps)[:3]
+    assert rel_err(got, ref) <= 1e-12
+    assert all(np.array_equal(g, r) for g, r in zip(got, ref)), "expected bitwise agreement"
+    d = ctx.diagnostics()
+    od = oracle.diagnostics(*ref, *w.abc, w.params[2], dt)
+    assert np.allclose(d["mass"], od["mass"], rtol=1e-12, atol=0)
+    assert d["steps"] == w.steps and math.isclose(d["t"], w.steps * dt, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("nx,ny,rows", [(300, 77, 0), (1, 50, 7), (50, 1, 0), (257, 3, 2), (64, 64, 5),
+                                        (513, 130, 0), (2, 2, 1), (1000, 9, 4), (3, 700, 0)])
+def test_f64_ragged_shapes_bitwise(nx, ny, rows):
+    g = rng(nx * 7 + ny)
+    a, b, c = wl.random_abc(g, nx, ny)
+    u, v, w = wl.random_state(g, nx, ny)
+    prm = (12.5, 1.0, 0.05, 70.0, 55.0)
+    lx, ly = 1.0, 0.8
+    dt = oracle.stable_dt(a, b, c, prm[2], 0.9, lx, ly)
+    ctx = gpu_ctx(nx, ny, "f64", prm, (u, v, w), abc=(a, b, c), lx=lx, ly=ly, rows=rows)
+    assert ctx.stable_dt(0.9) == dt
+    ctx.step(dt, 25)
+    got = ctx.get_state()
+    ref = oracle.run(u, v, w, a, b, c, prm, dt, 25, lx, ly)[:3]
+    assert rel_err(got, ref) <= 1e-12
+    assert all(np.array_equal(x, y) for x, y in zip(got, ref))
+
+
+def test_f64_smooth_anisotropic_eig_tensor():
+    """cfg1 recipe at 256^2; each side maps (lambda1, lambda2, theta) itself."""
+    w = wl.cfg1(n=256, steps=1000)
+    a, b, c = oracle.tensor_from_eig(*w.eig)
+    dt = oracle.stable_dt(a, b, c, w.params[2], 0.9)
+    ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), eig=w.eig)
+    ga, gb, gc = ctx.get_tensor()
+    scale = np.max(w.eig[0])
+    for x, y in ((ga, a), (gb, b), (gc, c)):
+        assert np.max(np.abs(x - y)) <= 4e-16 * scale
+    gdt = ctx.stable_dt(0.9)
+    assert math.isclose(gdt, dt, rel_tol=1e-15)
+    ctx.step(gdt, w.steps)
+    got = ctx.get_state()
+    ref = oracle.run(w.u0, w.v0, w.w0, a, b, c, w.params, dt, w.steps)[:3]
+    assert rel_err(got, ref) <= 1e-12
+
+
+def _patch_reference(w, a, b, c, dt, steps, j0, j1, i0, i1):
+    """Oracle on a sub-window grown by `steps` cells on every side that is not a
+    domain edge; the inner window is then exact (the scheme has a one-cell
+    stencil per step)."""
+    J0, J1 = max(0, j0 - steps), min(w.ny, j1 + steps)
+    I0, I1 = max(0, i0 - steps), min(w.nx, i1 + steps)
+    sl = (slice(J0, J1), slice(I0, I1))
+    dx = w.lx / w.nx
+    dy = w.ly / w.ny
+    lx, ly = (I1 - I0) * dx, (J1 - J0) * dy
+    # idx and idy must be the full grid's: same cell size, so nx'/lx' = nx/lx
+    u, v, ww, _ = oracle.run(w.u0[sl], w.v0[sl], w.w0[sl], a[sl], b[sl], c[sl], w.params, dt, steps, lx, ly)
+    inner = (slice(j0 - J0, j1 - J0), slice(i0 - I0, i1 - I0))
+    return u[inner], v[inner], ww[inner]
+
+
+@pytest.mark.parametrize("dtype", ["f64"])
+def test_full_size_layered_tissue_patches(dtype):
+    """4096^2 layered tissue (Voronoi regions + membranes), launch shape as timed
+    by the benchmark, 60 steps; outputs sampled on corner, edge and interior
+    windows, each recomputed exactly by the oracle on a grown sub-window."""
+    w = wl.cfg2(steps=60)
+    a, b, c = oracle.tensor_from_eig(*w.eig)
+    ctx = gpu_ctx(w.nx, w.ny, dtype, w.params, (w.u0, w.v0, w.w0), eig=w.eig)
+    dt = ctx.stable_dt(0.9)
+    assert math.isclose(dt, oracle.stable_dt(a, b, c, w.params[2], 0.9), rel_tol=1e-15)
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    n = w.nx
+    windows = [(0, 40, 0, 40), (n - 40, n, n - 40, n), (0, 40, 2000, 2060), (2030, 2070, 2030, 2070),
+               (1000, 1040, n - 40, n)]
+    for (j0, j1, i0, i1) in windows:
+        ref = _patch_reference(w, a, b, c, dt, w.steps, j0, j1, i0, i1)
+        sub = [x[j0:j1, i0:i1] for x in got]
+        for s, r in zip(sub, ref):
+            assert np.max(np.abs(s - r)) <= 1e-12 * max(np.max(np.abs(r)), 1.0)
+
+
+# ---------------------------------------------------------------------------
+# FP32: compensated state meets 1e-5 after 1e4 steps; plain FP32 does not
+
+def _f32_inputs(n=256):
+    w = wl.cfg1(n=n, steps=10000)
+    f = lambda x: np.asarray(x, np.float32)
+    eig = tuple(f(x) for x in w.eig)
+    st = tuple(f(x) for x in (w.u0, w.v0, w.w0))
+    prm32 = tuple(float(np.float32(p)) for p in w.params)
+    # oracle tensor from the same FP32 eigen-fields, rounded to FP32 like the device
+    a, b, c = (np.float64(np.float32(x)) for x in oracle.tensor_from_eig(*[np.float64(x) for x in eig]))
+    # step of the 1024^2 grid (4x finer): the increments per step then match cfg1's
+    dt = float(np.float32(oracle.stable_dt(a, b, c, prm32[2], 0.9) / 16.0))
+    return w, eig, st, prm32, (a, b, c), dt
+
+
+@pytest.fixture(scope="module")
+def f32_case():
+    w, eig, st, prm32, abc, dt = _f32_inputs()
+    ref = oracle.run(*[np.float64(x) for x in st], *abc, prm32, dt, w.steps)[:3]
+    return w, eig, st, prm32, abc, dt, ref
+
+
+def test_f32c_tolerance_after_1e4_steps(f32_case):
+    w, eig, st, prm32, abc, dt, ref = f32_case
+    ctx = gpu_ctx(w.nx, w.ny, "f32c", prm32, st, eig=eig)
+    ga, gb, gc = ctx.get_tensor()
+    for x, y in zip((ga, gb, gc), abc):
+        assert np.max(np.abs(x - y)) <= 2.5e-7 * np.max(np.abs(y))
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    err = rel_err(got, ref)
+    print(f"f32c rel err after {w.steps} steps: {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_f32_plain_stated_tolerance(f32_case):
+    w, eig, st, prm32, abc, dt, ref = f32_case
+    ctx = gpu_ctx(w.nx, w.ny, "f32", prm32, st, eig=eig)
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    err = rel_err(got, ref)
+    print(f"f32 plain rel err after {w.steps} steps: {err:.3e}")
+    assert err <= 2e-3
+
+
+# ---------------------------------------------------------------------------
+# properties on the device
+
+def test_diagnostics_parity_and_unstable_flag():
+    nx, ny = 333, 211
+    g = rng(1)
+    a, b, c = wl.random_abc(g, nx, ny)
+    u, v, w = wl.random_state(g, nx, ny)
+    prm = (3.0, 1.0, 0.2, 2.0, 1.0)
+    dt = oracle.stable_dt(a, b, c, prm[2], 0.5)
+    ctx = gpu_ctx(nx, ny, "f64", prm, (u, v, w), abc=(a, b, c))
+    ctx.step(dt, 3)
+    ref = oracle.run(u, v, w, a, b, c, prm, dt, 3)[:3]
+    d = ctx.diagnostics()
+    od = oracle.diagnostics(*ref, a, b, c, prm[2], dt)
+    assert np.allclose(d["mass"], od["mass"], rtol=1e-12, atol=0)
+    assert np.array_equal(d["vmin"], od["vmin"]) and np.array_equal(d["vmax"], od["vmax"])
+    assert math.isclose(d["cfl"], od["cfl"], rel_tol=1e-14) and d["cfl"] <= 0.5 + 1e-12
+    assert d["nonfinite"] == 0
+    # determinism of the reduction order
+    d2 = ctx.diagnostics()
+    assert np.array_equal(d["mass"], d2["mass"])
+    # a state with non-finite values is flagged
+    w2 = w.copy()
+    w2[5, 7] = np.nan
+    w2[100, 3] = np.inf
+    ctx.set_state(u, v, w2)
+    with pytest.raises(pk.GGFVError) as e:
+        ctx.diagnostics()
+    assert e.value.status == pk.GGFV_EUNSTABLE
+    assert ctx.diagnostics(allow_unstable=True)["nonfinite"] == 2
+
+
+def test_conservation_on_device():
+    nx, ny = 400, 250
+    g = rng(2)
+    a, b, c = wl.random_abc(g, nx, ny)
+    u, v, w = wl.random_state(g, nx, ny)
+    prm = (3.0, 0.0, 0.05, 0.0, 0.0)
+    ctx = gpu_ctx(nx, ny, "f64", prm, (u, v, w), abc=(a, b, c))
+    dt = ctx.stable_dt(0.9)
+    ctx.step(dt, 1)
+    m0 = ctx.diagnostics()["mass"]
+    ctx.step(dt, 3000)
+    m1 = ctx.diagnostics()["mass"]
+    assert abs(m1[1] - m0[1]) <= 1e-12 * m0[1]
+    assert abs(m1[2] - m0[2]) <= 1e-12 * m0[2]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32c"])
+def test_equilibria_bitwise_on_device(dtype):
+    nx, ny = 190, 130
+    g = rng(3)
+    a, b, c = wl.random_abc(g, nx, ny)
+    ones, zeros = np.ones((ny, nx)), np.zeros((ny, nx))
+    for st in ((ones, zeros, zeros), (zeros, ones, ones)):
+        ctx = gpu_ctx(nx, ny, dtype, PRM, st, abc=(a, b, c))
+        ctx.step(ctx.stable_dt(0.9), 1000)
+        got = ctx.get_state()
+        assert all(np.array_equal(x, y) for x, y in zip(got, st))
+
+
+def test_determinism_resume_and_launch_shape_invariance():
+    nx, ny = 700, 300
+    g = rng(4)
+    a, b, c = wl.random_abc(g, nx, ny)
+    u, v, w = wl.random_state(g, nx, ny)
+    ctx = gpu_ctx(nx, ny, "f64", PRM, (u, v, w), abc=(a, b, c))
+    dt = ctx.stable_dt(0.9)
+    ctx.step(dt, 100)
+    full = ctx.get_state()
+    ctx.set_state(u, v, w)
+    ctx.step(dt, 100)
+    again = ctx.get_state()
+    assert all(np.array_equal(x, y) for x, y in zip(full, again))
+    ctx.set_state(u, v, w)
+    ctx.step(dt, 50)
+    half = ctx.get_state()
+    ctx.set_state(*half)
+    ctx.step(dt, 50)
+    assert all(np.array_equal(x, y) for x, y in zip(full, ctx.get_state()))
+    for rows in (1, 3, 17, 300):
+        ctx.set_tuning(rows)
+        ctx.set_state(u, v, w)
+        ctx.step(dt, 100)
+        assert all(np.array_equal(x, y) for x, y in zip(full, ctx.get_state())), rows
+
+
+def test_device_pointer_io_matches_host_io():
+    torch = pytest.importorskip("torch")
+    nx, ny = 129, 65
+    g = rng(5)
+    a, b, c = wl.random_abc(g, nx, ny)
+    u, v, w = wl.random_state(g, nx, ny)
+    dev = [torch.from_numpy(x).cuda() for x in (u, v, w)]
+    tdev = [torch.from_numpy(x).cuda() for x in (a, b, c)]
+    ctx = pk.Context(nx, ny, dtype="f64")
+    ctx.set_params(PRM)
+    ctx.set_tensor(*tdev)
+    ctx.set_state(*dev)
+    dt = ctx.stable_dt(0.9)
+    ctx.step(dt, 10)
+    outs = [torch.empty((ny, nx), dtype=torch.float64, device="cuda") for _ in range(3)]
+    ctx.get_state(out=outs)
+    torch.cuda.synchronize()
+    ref = oracle.run(u, v, w, a, b, c, PRM, dt, 10)[:3]
+    assert all(np.array_equal(o.cpu().numpy(), r) for o, r in zip(outs, ref))
+
+
+def test_f32c_io_roundtrip_and_conversions():
+    nx, ny = 70, 33
+    g = rng(6)
+    a, b, c = wl.random_abc(g, nx, ny)
+    u, v, w = wl.random_state(g, nx, ny)
+    ctx = gpu_ctx(nx, ny, "f32c", PRM, (u, v, w), abc=(a, b, c))
+    got = ctx.get_state()
+    for x, y in zip(got, (u, v, w)):
+        assert np.max(np.abs(x - y)) <= 2.0 ** -46 * np.max(np.abs(y))
+    hi = ctx.get_state(dtype="f32")
+    for x, y in zip(hi, (u, v, w)):
+        assert np.array_equal(x, y.astype(np.float32))
+
+
+def test_error_paths():
+    nx, ny = 16, 12
+    ones, zeros = np.ones((ny, nx)), np.zeros((ny, nx))
+    ctx = pk.Context(nx, ny, dtype="f64")
+    with pytest.raises(pk.GGFVError) as e:
+        ctx.step(1e-4, 1)
+    assert e.value.status == pk.GGFV_ESTATE
+    ctx.set_params(PRM)
+    with pytest.raises(pk.GGFVError) as e:
+        ctx.set_tensor(ones, 2 * ones, ones)        # a c - b^2 < 0
+    assert e.value.status == pk.GGFV_EINVAL
+    with pytest.raises(pk.GGFVError) as e:
+        ctx.set_tensor(-ones, zeros, ones)          # a < 0
+    assert e.value.status == pk.GGFV_EINVAL
+    ctx.set_tensor(ones, zeros, ones)
+    ctx.set_state(ones, zeros, zeros)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(pk.GGFVError) as e:
+            ctx.step(bad, 1)
+        assert e.value.status == pk.GGFV_EINVAL
+    with pytest.raises(pk.GGFVError):
+        ctx.step(1e-4, -1)
+    ctx.step(1e-4, 0)
+    with pytest.raises(pk.GGFVError):
+        ctx.set_params((1.0, 1.0, -0.1, 1.0, 1.0))
+    with pytest.raises(ValueError):
+        ctx.set_state(np.ones(5), np.ones(5), np.ones(5))
+    # an unstable step is detected by the diagnostics
+    ctx.set_state(*wl.random_state(rng(7), nx, ny))
+    dt = ctx.stable_dt(0.9)
+    ctx.step(dt * 5.0, 1)
+    with pytest.raises(pk.GGFVError) as e:
+        ctx.diagnostics()
+    assert e.value.status == pk.GGFV_EUNSTABLE
