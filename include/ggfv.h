@@ -173,7 +173,8 @@ typedef struct {
 int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
 int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
 
-/* Message describing the last failure of this context ("" if none). */
+/* Message describing the last failure of this context ("" if none).  With
+ * ctx == NULL: the message of the last failed ggfv_create on the calling thread. */
 const char *ggfv_last_error(const ggfv_ctx *ctx);
 
 /* Static name of a status code. */

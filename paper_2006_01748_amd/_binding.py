@@ -84,6 +84,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2006_01748_amd.build` "
                           "(there is no CPU fallback)")
+    # One HIP runtime per process: when torch is present its bundled runtime
+    # (same soname) must be loaded first so that the library binds to it and
+    # torch's streams and device pointers are valid in the library's calls.
+    _torch()
     L = ctypes.CDLL(LIB_PATH)
     for name, res, args in _SIGNATURES:
         f = getattr(L, name)
@@ -145,7 +149,8 @@ class Context:
         rc = self._lib.ggfv_create(ctypes.byref(h), self.nx, self.ny, self.lx, self.ly,
                                    DTYPES[dtype], int(device), stream)
         if rc != GGFV_OK:
-            raise GGFVError(rc, f"ggfv_create({nx}, {ny}, {lx}, {ly}, {dtype}, device={device}) failed")
+            why = self._lib.ggfv_last_error(None).decode()
+            raise GGFVError(rc, f"ggfv_create({nx}, {ny}, {lx}, {ly}, {dtype}, device={device}) failed: {why}")
         self._h = h
 
     # -- plumbing ----------------------------------------------------------

@@ -27,6 +27,7 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
     "-std=c++17",
+    "-mcode-object-version=5",
     "-fPIC",
     "-ffp-contract=off",
     "-fno-fast-math",

@@ -13,18 +13,23 @@ using namespace ggfv;
 
 namespace {
 
+// Message of the last failed ggfv_create on this thread (there is no context to
+// hold it); reported by ggfv_last_error(NULL).
+thread_local std::string g_create_error;
+
 int fail(ggfv_ctx *ctx, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 
 int fail(ggfv_ctx *ctx, int code, const char *fmt, ...)
 {
-    if (ctx) {
-        char buf[512];
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(buf, sizeof buf, fmt, ap);
-        va_end(ap);
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
         ctx->err = buf;
-    }
+    else
+        g_create_error = buf;
     return code;
 }
 
@@ -123,19 +128,24 @@ const char *ggfv_status_string(int s)
     }
 }
 
-const char *ggfv_last_error(const ggfv_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *ggfv_last_error(const ggfv_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
 int ggfv_create(ggfv_ctx **out, int nx, int ny, double lx, double ly, int dtype, int device,
                 void *hip_stream)
 {
-    if (!out) return GGFV_EINVAL;
+    if (!out) return fail(nullptr, GGFV_EINVAL, "null output pointer");
     *out = nullptr;
-    if (nx < 1 || ny < 1) return GGFV_EINVAL;
-    if ((long long)nx * ny > (1LL << 34)) return GGFV_EINVAL;
-    if (!(lx > 0.0) || !(ly > 0.0) || !std::isfinite(lx) || !std::isfinite(ly)) return GGFV_EINVAL;
-    if (dtype != GGFV_F32 && dtype != GGFV_F64 && dtype != GGFV_F32C) return GGFV_EINVAL;
+    if (nx < 1 || ny < 1) return fail(nullptr, GGFV_EINVAL, "grid must be at least 1x1 (got %dx%d)", nx, ny);
+    if ((long long)nx * ny > (1LL << 34)) return fail(nullptr, GGFV_EINVAL, "grid too large (%dx%d)", nx, ny);
+    if (!(lx > 0.0) || !(ly > 0.0) || !std::isfinite(lx) || !std::isfinite(ly))
+        return fail(nullptr, GGFV_EINVAL, "domain sides must be finite and > 0");
+    if (dtype != GGFV_F32 && dtype != GGFV_F64 && dtype != GGFV_F32C)
+        return fail(nullptr, GGFV_EINVAL, "unknown dtype %d", dtype);
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GGFV_EHIP;
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess) return fail(nullptr, GGFV_EHIP, "hipGetDeviceCount failed: %s", hipGetErrorString(he));
+    if (device < 0 || device >= ndev)
+        return fail(nullptr, GGFV_EHIP, "device %d out of range (%d devices)", device, ndev);
 
     ggfv_ctx *ctx = new (std::nothrow) ggfv_ctx;
     if (!ctx) return GGFV_ENOMEM;
@@ -154,7 +164,7 @@ int ggfv_create(ggfv_ctx **out, int nx, int ny, double lx, double ly, int dtype,
     DeviceGuard g(device);
     if (g.status != hipSuccess) {
         delete ctx;
-        return GGFV_EHIP;
+        return fail(nullptr, GGFV_EHIP, "hipSetDevice(%d) failed: %s", device, hipGetErrorString(g.status));
     }
     const size_t sbytes = ctx->nfields * ctx->plane * ctx->elem;
     const size_t tbytes = 3 * ctx->plane * ctx->elem;
@@ -173,7 +183,8 @@ int ggfv_create(ggfv_ctx **out, int nx, int ny, double lx, double ly, int dtype,
     if (!ok) {
         (void)hipGetLastError();
         ggfv_destroy(ctx);
-        return GGFV_ENOMEM;
+        return fail(nullptr, GGFV_ENOMEM, "cannot allocate %zu bytes of device memory",
+                    2 * sbytes + tbytes);
     }
     *out = ctx;
     return GGFV_OK;

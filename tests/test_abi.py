@@ -80,3 +80,10 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_binding, "_lib", None)
     with pytest.raises(ImportError):
         _binding.lib()
+
+
+def test_create_failure_message_is_reported(built):
+    lib = pk.lib()
+    h = ctypes.c_void_p()
+    assert lib.ggfv_create(ctypes.byref(h), 0, 5, 1.0, 1.0, pk.GGFV_F64, 0, None) == pk.GGFV_EINVAL
+    assert b"grid" in lib.ggfv_last_error(None)
