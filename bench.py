@@ -34,6 +34,24 @@ METRIC = "Gcell-updates/s + % HBM peak, 4096² aniso FV step FP32/FP64; adjoint/
 MASS_EVERY = 500
 
 
+def measured_traffic(variant):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when the step kernel source changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "step_kernel_traffic.json")) as f:
+            data = json.load(f)
+        with open(os.path.join(here, data["kernel_source"]), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if digest != data.get("kernel_source_sha256"):
+        return None
+    t = data["bytes_per_launch"].get(variant)
+    return None if t is None else t["read"] + t["write"]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -179,13 +197,14 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": r["frac"], "traffic": None, "kernel": KERNEL_NAME[head],
+            "frac": r["frac"], "traffic": measured_traffic(head), "kernel": KERNEL_NAME[head],
             "kernel_avg_us": r["kernel_avg_us"], "bytes_per_cell_update": BYTES_PER_CELL[head],
         },
         "cpu_baseline": base,
         "variants": {v: {"value": res[v]["value"], "kernel_avg_us": res[v]["kernel_avg_us"],
                          "achieved_GBs": res[v]["achieved_GBs"], "frac": res[v]["frac"],
-                         "bytes_per_cell_update": BYTES_PER_CELL[v], "kernel": KERNEL_NAME[v]}
+                         "bytes_per_cell_update": BYTES_PER_CELL[v], "kernel": KERNEL_NAME[v],
+                         "traffic": measured_traffic(v)}
                      for v in variants},
         "copy_ceiling_GBs": ceiling,
         "mass_log": r["mass_log"],
