@@ -78,9 +78,10 @@ def bind(lib):
     lib.orc_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p, p, p, p, p, p, p]
     lib.orc_diag.argtypes = [i, i, d, d, p, p, p, p, p, p, d, d, p]
     lib.orc_run.argtypes = [i, i, d, d, p, d, l, p, p, p, p, p, p, l, p]
-    if hasattr(lib, "orc_adjoint_step"):
-        lib.orc_adjoint_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p,
-                                         p, p, p, p, p, p, p, p, p, p]
+    lib.orc_adjoint_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p,
+                                     p, p, p, p, p, p, p, p, p, p]
+    lib.orc_eig_backward.argtypes = [l, p, p, p, p, p, p, p, p, p]
+    lib.orc_adjoint_run.argtypes = [i, i, d, d, p, d, l, p, p, p, p, p, p, p, p, p, p, p, p, p]
     return lib
 
 
@@ -175,3 +176,44 @@ def diagnostics(u, v, w, a, b, c, Delta2, dt, lx=1.0, ly=1.0) -> dict:
                      float(Delta2), float(dt), _ptr(out))
     return {"mass": out[0:3].copy(), "vmin": out[3:6].copy(), "vmax": out[6:9].copy(),
             "cfl": float(out[9]), "nonfinite": int(out[10])}
+
+
+def adjoint_step(u, v, w, a, b, c, params, dt, lam_next, lx=1.0, ly=1.0):
+    """Transpose of one step of eq. (3) (dt fixed).  Returns (lam, g_abc, g_params):
+    lam = (dF/dx)^T lam_next, g_abc = (dF/d(a,b,c))^T lam_next (three arrays),
+    g_params = (dF/d(delta1, rho2, Delta2, rho3, delta3))^T lam_next."""
+    u, v, w, a, b, c = (_f64(x) for x in (u, v, w, a, b, c))
+    lu1, lv1, lw1 = (_f64(x) for x in lam_next)
+    ny, nx = u.shape
+    prm = _f64(params)
+    lu, lv, lw = (np.empty_like(u) for _ in range(3))
+    ga, gb, gc = (np.zeros_like(u) for _ in range(3))
+    gp = np.zeros(5)
+    _load().orc_adjoint_step(nx, ny, lx, ly, _ptr(prm), float(dt), _ptr(u), _ptr(v), _ptr(w),
+                             _ptr(a), _ptr(b), _ptr(c), _ptr(lu1), _ptr(lv1), _ptr(lw1),
+                             _ptr(lu), _ptr(lv), _ptr(lw), _ptr(ga), _ptr(gb), _ptr(gc), _ptr(gp))
+    return (lu, lv, lw), (ga, gb, gc), gp
+
+
+def eig_backward(lam1, lam2, theta, ga, gb, gc):
+    """Chain rule of the tensor map (lambda1, lambda2, theta) -> (a, b, c)."""
+    lam1, lam2, theta, ga, gb, gc = (_f64(x) for x in (lam1, lam2, theta, ga, gb, gc))
+    g1, g2, gt = (np.empty_like(lam1) for _ in range(3))
+    _load().orc_eig_backward(lam1.size, _ptr(lam1), _ptr(lam2), _ptr(theta), _ptr(ga), _ptr(gb),
+                             _ptr(gc), _ptr(g1), _ptr(g2), _ptr(gt))
+    return g1, g2, gt
+
+
+def adjoint_run(u0, v0, w0, a, b, c, params, dt, nsteps, lam_final, lx=1.0, ly=1.0):
+    """Reverse sweep over nsteps steps from x^0 (all states kept; small grids only).
+    Returns (lam0, g_abc, g_params) for the loss whose gradient at x^N is lam_final."""
+    u0, v0, w0, a, b, c = (_f64(x) for x in (u0, v0, w0, a, b, c))
+    lu, lv, lw = (np.array(x, dtype=np.float64, copy=True, order="C") for x in lam_final)
+    ny, nx = u0.shape
+    prm = _f64(params)
+    ga, gb, gc = (np.zeros_like(u0) for _ in range(3))
+    gp = np.zeros(5)
+    _load().orc_adjoint_run(nx, ny, lx, ly, _ptr(prm), float(dt), int(nsteps), _ptr(u0), _ptr(v0),
+                            _ptr(w0), _ptr(a), _ptr(b), _ptr(c), _ptr(lu), _ptr(lv), _ptr(lw),
+                            _ptr(ga), _ptr(gb), _ptr(gc), _ptr(gp))
+    return (lu, lv, lw), (ga, gb, gc), gp

@@ -13,6 +13,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_adjoint as adj
 import test_oracle_pins as pins
 
 # (name, original text, replacement, expected number of occurrences)
@@ -55,11 +56,31 @@ PIN_TESTS = [
 ]
 
 
-def _build_mutant(tmp, src_text):
+ADJ_MUTANTS = [
+    ("mobility derivative sign", "lu[l] += sv * (-0.5 * (v[r] - v[l]) * idx);", "lu[l] += sv * (0.5 * (v[r] - v[l]) * idx);", 1),
+    ("mirror term of ty dropped", "lw[IX(i, jm)] -= s * 0.5 * b[l] * hy;", "", 1),
+    ("b gradient with the neighbour's ty", "gb[l] += s * 0.5 * tyl;", "gb[l] += s * 0.5 * tyr;", 1),
+    ("kill-term adjoint uses w", "- dt * d1 * u[k] * lu1[k]", "- dt * d1 * w[k] * lu1[k]", 1),
+    ("Delta2 gradient without divV", "gp[2] += dt * dV[k] * lv1[k];", "gp[2] += dt * lv1[k];", 1),
+    ("theta chain rule sign", "(-ga[k] * s2 + gc[k] * s2 + gb[k] * c2)", "(ga[k] * s2 - gc[k] * s2 + gb[k] * c2)", 1),
+    ("c gradient scaled by idx", "gc[l] += s * 0.5 * (w[r] - w[l]) * idy;", "gc[l] += s * 0.5 * (w[r] - w[l]) * idx;", 1),
+    ("growth adjoint of v", "(1.0 + dt * r2 * (1.0 - 2.0 * v[k]))", "(1.0 + dt * r2 * (1.0 - v[k]))", 1),
+]
+
+ADJ_PINS = [
+    lambda: adj.test_state_adjoint_dot_identity(13, 9),
+    lambda: adj.test_state_adjoint_dot_identity(1, 6),
+    lambda: adj.test_parameter_gradients_exact_differences(),
+    lambda: adj.test_tensor_gradients_exact_differences(),
+    lambda: adj.test_eig_chain_rule(),
+]
+
+
+def _build_mutant(tmp, src_text, target="ggfv_oracle.c"):
     srcs = []
     for path in oracle.sources():
         text = open(path).read()
-        if os.path.basename(path) == "ggfv_oracle.c":
+        if os.path.basename(path) == target:
             text = src_text
         dst = os.path.join(tmp, os.path.basename(path))
         with open(dst, "w") as f:
@@ -90,3 +111,25 @@ def test_pins_catch_mutant(name, old, new, count):
         finally:
             oracle.restore_library(prev)
     assert caught, f"no pin caught the planted mistake '{name}'"
+
+
+@pytest.mark.parametrize("name,old,new,count", ADJ_MUTANTS, ids=[m[0] for m in ADJ_MUTANTS])
+def test_adjoint_pins_catch_mutant(name, old, new, count):
+    base = open(oracle._SRC_ADJ).read()
+    assert base.count(old) == count, f"mutation anchor for '{name}' not found"
+    mutated = base.replace(old, new)
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _build_mutant(tmp, mutated, "ggfv_oracle_adjoint.c")
+        oracle.build(force=False)
+        prev = oracle.use_library(lib)
+        caught = False
+        try:
+            for pin in ADJ_PINS:
+                try:
+                    pin()
+                except AssertionError:
+                    caught = True
+                    break
+        finally:
+            oracle.restore_library(prev)
+    assert caught, f"no adjoint pin caught the planted mistake '{name}'"
