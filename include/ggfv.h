@@ -163,6 +163,65 @@ int ggfv_step(ggfv_ctx *ctx, double dt, long long nsteps);
  * filled) if nonfinite > 0 or cfl > 1. */
 int ggfv_diagnostics(ggfv_ctx *ctx, ggfv_diag *out);
 
+/* ---- gradients ------------------------------------------------------------
+ *
+ * The adjoint of the explicit step: for a loss L of the state after N steps,
+ * lam^k = dL/dx^k satisfies lam^k = (dF/dx)^T lam^{k+1} with F one step of
+ * eq. (3) (dt fixed), and the gradients with respect to the tensor (a, b, c) and
+ * the five parameters are sums over steps of (dF/dA)^T lam^{k+1} and
+ * (dF/dp)^T lam^{k+1}.  F is differentiated exactly as implemented (the
+ * discrete adjoint), including the zero-flux faces and the mirrored tangential
+ * differences of the boundary rule.  The arithmetic is in the context precision
+ * (for GGFV_F32C the adjoint reads the hi word of the state); the five scalar
+ * gradients are accumulated in FP64 in a fixed order. */
+
+/* Bytes of one stored state (all fields, padded rows): the unit of checkpoint and
+ * work buffers below. */
+long long ggfv_state_bytes(const ggfv_ctx *ctx);
+
+/* Like ggfv_step, and also copies the state before steps 0, every, 2*every, ...
+ * into the caller's device buffer ckpt (slot k at byte offset k*state_bytes),
+ * i.e. ceil(nsteps/every) slots.  EINVAL if every < 1, nsteps < 1 or ckpt_bytes
+ * is too small.  Asynchronous on the context's stream. */
+int ggfv_step_checkpointed(ggfv_ctx *ctx, double dt, long long nsteps, long long every,
+                           void *ckpt, long long ckpt_bytes);
+
+/* One adjoint step at the state x = (u, v, w): lam_out = (dF/dx)^T lam_in;
+ * (g_a, g_b, g_c) += (dF/dA)^T lam_in (in place); g_params[0..4] (host, FP64,
+ * order delta1, rho2, Delta2, rho3, delta3) += (dF/dp)^T lam_in.  All arrays are
+ * nx*ny io_dtype values at `where`.  Uses the context's tensor and parameters;
+ * does not touch its state.  Synchronizes. */
+int ggfv_adjoint_step(ggfv_ctx *ctx, double dt, const void *u, const void *v, const void *w,
+                      const void *lam_u, const void *lam_v, const void *lam_w, void *out_u,
+                      void *out_v, void *out_w, void *g_a, void *g_b, void *g_c,
+                      double *g_params, int where, int io_dtype);
+
+/* Reverse sweep over nsteps steps with the checkpoints written by
+ * ggfv_step_checkpointed(dt, nsteps, every): for each segment of `every` steps,
+ * last to first, the states of the segment are recomputed from its checkpoint
+ * into the caller's device buffer work (at least max(1, every-1) states) and the
+ * adjoint steps run backwards through them.  Memory is ceil(N/every) + every
+ * states; every ~ sqrt(N) gives 2 sqrt(N).
+ * lam_u, lam_v, lam_w: on entry dL/dx^N, on exit dL/dx^0.  g_a, g_b, g_c and
+ * g_params[5] (host) are overwritten with the gradients.  Arrays at `where` in
+ * io_dtype; ckpt and work are device memory.  Uses the context's tensor and
+ * parameters; does not touch its state.  Synchronizes. */
+int ggfv_adjoint_run(ggfv_ctx *ctx, double dt, long long nsteps, long long every,
+                     const void *ckpt, long long ckpt_bytes, void *work, long long work_bytes,
+                     void *lam_u, void *lam_v, void *lam_w, void *g_a, void *g_b, void *g_c,
+                     double *g_params, int where, int io_dtype);
+
+/* Chain rule of the tensor map of ggfv_set_tensor_eig: from (g_a, g_b, g_c) and
+ * (lam1, lam2, theta) to the gradients with respect to lam1, lam2 and theta:
+ *   g_l1 = g_a cos^2 + g_c sin^2 + g_b sin cos
+ *   g_l2 = g_a sin^2 + g_c cos^2 - g_b sin cos
+ *   g_th = (lam1 - lam2)((g_c - g_a) sin 2theta + g_b cos 2theta)
+ * (FP64 arithmetic).  Nine arrays of nx*ny io_dtype values at `where`.
+ * Synchronizes for host arrays. */
+int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const void *theta,
+                      const void *g_a, const void *g_b, const void *g_c, void *g_l1, void *g_l2,
+                      void *g_th, int where, int io_dtype);
+
 /* Launch shape of the step kernel.  rows_per_strip is the number of grid rows
  * one workgroup sweeps (0 = chosen from the grid size); any value gives the same
  * results bit for bit.  EINVAL if negative. */

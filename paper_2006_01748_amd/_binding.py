@@ -38,6 +38,12 @@ _SIGNATURES = [
     ("ggfv_stable_dt", _c.c_int, [_VP, _c.c_double, _c.POINTER(_c.c_double)]),
     ("ggfv_step", _c.c_int, [_VP, _c.c_double, _c.c_longlong]),
     ("ggfv_diagnostics", _c.c_int, [_VP, _VP]),
+    ("ggfv_state_bytes", _c.c_longlong, [_VP]),
+    ("ggfv_step_checkpointed", _c.c_int, [_VP, _c.c_double, _c.c_longlong, _c.c_longlong, _VP, _c.c_longlong]),
+    ("ggfv_adjoint_step", _c.c_int, [_VP, _c.c_double] + [_VP] * 12 + [_c.POINTER(_c.c_double), _c.c_int, _c.c_int]),
+    ("ggfv_adjoint_run", _c.c_int, [_VP, _c.c_double, _c.c_longlong, _c.c_longlong, _VP, _c.c_longlong, _VP,
+                                    _c.c_longlong] + [_VP] * 6 + [_c.POINTER(_c.c_double), _c.c_int, _c.c_int]),
+    ("ggfv_eig_backward", _c.c_int, [_VP] * 10 + [_c.c_int, _c.c_int]),
     ("ggfv_set_tuning", _c.c_int, [_VP, _VP]),
     ("ggfv_get_tuning", _c.c_int, [_VP, _VP]),
     ("ggfv_last_error", _c.c_char_p, [_VP]),
@@ -258,6 +264,72 @@ class Context:
 
     def step(self, dt, nsteps=1):
         self._check(self._lib.ggfv_step(self._h, float(dt), int(nsteps)))
+
+    # -- gradients -----------------------------------------------------------
+    def state_bytes(self):
+        return int(self._lib.ggfv_state_bytes(self._h))
+
+    def step_checkpointed(self, dt, nsteps, every, ckpt):
+        """Step and store the state before every `every`-th step into the device
+        tensor `ckpt` (at least ceil(nsteps/every) * state_bytes() bytes)."""
+        self._check(self._lib.ggfv_step_checkpointed(self._h, float(dt), int(nsteps), int(every),
+                                                     ctypes.c_void_p(ckpt.data_ptr()),
+                                                     ckpt.numel() * ckpt.element_size()))
+
+    def _ptrs9(self, arrays):
+        dev = [_is_device_tensor(x) for x in arrays]
+        if all(dev):
+            for x in arrays:
+                if not x.is_contiguous() or x.numel() != self.nx * self.ny:
+                    raise ValueError("device arrays must be contiguous with nx*ny values")
+            io = _io_of(arrays[0])
+            return [ctypes.c_void_p(x.data_ptr()) for x in arrays], GGFV_DEVICE, io
+        if any(dev):
+            raise TypeError("mixing host and device arrays")
+        for x in arrays:
+            if not (isinstance(x, np.ndarray) and x.flags.c_contiguous and x.size == self.nx * self.ny):
+                raise ValueError("host arrays must be C-contiguous numpy arrays with nx*ny values")
+        io = _io_of(arrays[0])
+        if any(x.dtype != arrays[0].dtype for x in arrays):
+            raise TypeError("all arrays must share a dtype")
+        return [x.ctypes.data_as(ctypes.c_void_p) for x in arrays], GGFV_HOST, io
+
+    def adjoint_step(self, dt, x, lam_next, g_abc):
+        """One adjoint step at state x: returns (lam, g_params) with lam = (dF/dx)^T
+        lam_next; the tensor gradient is added into g_abc in place."""
+        if _is_device_tensor(x[0]):
+            outs = [x[0].new_empty((self.ny, self.nx)) for _ in range(3)]
+        else:
+            outs = [np.empty((self.ny, self.nx), dtype=np.asarray(x[0]).dtype) for _ in range(3)]
+        p1, where, io = self._ptrs9(list(x) + list(lam_next) + outs)
+        p2, where2, io2 = self._ptrs9(list(g_abc) + list(x))
+        if (where2, io2) != (where, io):
+            raise TypeError("gradient arrays must match the other arrays' location and dtype")
+        gp = (ctypes.c_double * 5)()
+        self._check(self._lib.ggfv_adjoint_step(self._h, float(dt), *p1, *p2[:3], gp, where, io))
+        return tuple(outs), np.array(gp[:])
+
+    def adjoint_run(self, dt, nsteps, every, ckpt, work, lam, g_abc):
+        """Reverse sweep: lam (3 arrays, in: dL/dx^N, out: dL/dx^0), g_abc (3 arrays,
+        overwritten).  Returns the five parameter gradients."""
+        ptrs = self._ptrs9(list(lam))[0] + self._ptrs9(list(g_abc))[0]
+        _, where, io = self._ptrs9(list(lam))
+        gp = (ctypes.c_double * 5)()
+        self._check(self._lib.ggfv_adjoint_run(
+            self._h, float(dt), int(nsteps), int(every), ctypes.c_void_p(ckpt.data_ptr()),
+            ckpt.numel() * ckpt.element_size(), ctypes.c_void_p(work.data_ptr()),
+            work.numel() * work.element_size(), *ptrs, gp, where, io))
+        return np.array(gp[:])
+
+    def eig_backward(self, lam1, lam2, theta, ga, gb, gc):
+        arrays = [lam1, lam2, theta, ga, gb, gc]
+        if all(_is_device_tensor(x) for x in arrays):
+            outs = [lam1.new_empty(lam1.shape) for _ in range(3)]
+        else:
+            outs = [np.empty((self.ny, self.nx), dtype=np.asarray(lam1).dtype) for _ in range(3)]
+        ptrs, where, io = self._ptrs9(arrays + outs)
+        self._check(self._lib.ggfv_eig_backward(self._h, *ptrs, where, io))
+        return tuple(outs)
 
     def set_tuning(self, rows_per_strip=0):
         t = Tuning(int(rows_per_strip))

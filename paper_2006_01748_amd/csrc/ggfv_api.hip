@@ -70,9 +70,9 @@ int check_ptrs(ggfv_ctx *ctx, const void *p0, const void *p1, const void *p2, in
     return GGFV_OK;
 }
 
-int ensure_staging(ggfv_ctx *ctx)
+int ensure_staging(ggfv_ctx *ctx, int narrays = 3)
 {
-    const size_t need = 3 * (size_t)ctx->nx * ctx->ny * sizeof(double);
+    const size_t need = (size_t)narrays * ctx->nx * ctx->ny * sizeof(double);
     if (ctx->staging && ctx->staging_bytes >= need) return GGFV_OK;
     if (ctx->staging) {
         (void)hipStreamSynchronize(ctx->stream);
@@ -108,6 +108,51 @@ int read_result(ggfv_ctx *ctx, double *host, int count)
     const double *res = static_cast<const double *>(ctx->scratch) + (size_t)kMaxPartialBlocks * kDiagSlots;
     GGFV_HIP(ctx, hipMemcpyAsync(host, res, count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GGFV_OK;
+}
+
+// Adjoint buffers (context precision planes, then FP64 slots):
+//   planes 0-2: a state x for a single adjoint step; 3-5 and 6-8: adjoint state
+//   ping-pong; 9-11: tensor gradient; then adjoint_blocks()*5 partial-sum slots
+//   and 8 result doubles.
+int ensure_adjoint(ggfv_ctx *ctx)
+{
+    const size_t planes = 12 * ctx->plane * ctx->elem;
+    const size_t slots = ((size_t)adjoint_blocks(ctx) * 5 + 8) * sizeof(double);
+    const size_t need = planes + slots;
+    if (ctx->adj && ctx->adj_bytes >= need) return GGFV_OK;
+    if (ctx->adj) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->adj);
+        ctx->adj = nullptr;
+    }
+    if (hipMalloc(&ctx->adj, need) != hipSuccess) {
+        ctx->adj = nullptr;
+        return fail(ctx, GGFV_ENOMEM, "cannot allocate %zu bytes for the adjoint", need);
+    }
+    ctx->adj_bytes = need;
+    return GGFV_OK;
+}
+
+void *adj_planes(ggfv_ctx *ctx, int first)
+{
+    return static_cast<char *>(ctx->adj) + (size_t)first * ctx->plane * ctx->elem;
+}
+
+double *adj_slots(ggfv_ctx *ctx)
+{
+    return reinterpret_cast<double *>(static_cast<char *>(ctx->adj) + 12 * ctx->plane * ctx->elem);
+}
+
+double *adj_result(ggfv_ctx *ctx) { return adj_slots(ctx) + (size_t)adjoint_blocks(ctx) * 5; }
+
+// Pack three caller arrays (host or device) into three storage planes.
+int pack_in(ggfv_ctx *ctx, const void *p0, const void *p1, const void *p2, int where, int io, void *dst)
+{
+    const void *d[3] = {p0, p1, p2};
+    int rc;
+    if (where == GGFV_HOST && (rc = stage_in(ctx, p0, p1, p2, io, d))) return rc;
+    GGFV_HIP(ctx, launch_pack3(ctx, d[0], d[1], d[2], io == GGFV_F64, dst, 3, false));
     return GGFV_OK;
 }
 
@@ -196,7 +241,7 @@ void ggfv_destroy(ggfv_ctx *ctx)
     {
         DeviceGuard g(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
-        for (void *p : {ctx->state[0], ctx->state[1], ctx->tensor, ctx->scratch, ctx->staging})
+        for (void *p : {ctx->state[0], ctx->state[1], ctx->tensor, ctx->scratch, ctx->staging, ctx->adj})
             if (p) (void)hipFree(p);
     }
     delete ctx;
@@ -257,6 +302,159 @@ int ggfv_set_tensor_eig(ggfv_ctx *ctx, const void *l1, const void *l2, const voi
     if (where == GGFV_HOST && (rc = stage_in(ctx, l1, l2, th, io, d))) return rc;
     GGFV_HIP(ctx, launch_tensor_eig(ctx, d[0], d[1], d[2], io == GGFV_F64));
     return check_spd(ctx);
+}
+
+static int copy_out(ggfv_ctx *ctx, const void *src_base, bool has_lo, void *o0, void *o1, void *o2,
+                    int where, int io);
+
+static int check9(ggfv_ctx *ctx, const void *const *p, int where, int io)
+{
+    for (int k = 0; k < 9; k += 3) {
+        int rc = check_ptrs(ctx, p[k], p[k + 1], p[k + 2], where, io);
+        if (rc) return rc;
+    }
+    return GGFV_OK;
+}
+
+long long ggfv_state_bytes(const ggfv_ctx *ctx)
+{
+    if (!ctx) return 0;
+    return (long long)(ctx->nfields * ctx->plane * ctx->elem);
+}
+
+int ggfv_step_checkpointed(ggfv_ctx *ctx, double dt, long long nsteps, long long every, void *ckpt,
+                           long long ckpt_bytes)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GGFV_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+    if (nsteps < 1 || every < 1) return fail(ctx, GGFV_EINVAL, "need nsteps >= 1 and every >= 1");
+    if (!ckpt) return fail(ctx, GGFV_EINVAL, "null checkpoint buffer");
+    if (!ctx->has_state || !ctx->has_tensor || !ctx->has_params)
+        return fail(ctx, GGFV_ESTATE, "state, tensor and parameters must be set before stepping");
+    const long long sb = ggfv_state_bytes(ctx);
+    const long long nck = (nsteps + every - 1) / every;
+    if (ckpt_bytes < nck * sb)
+        return fail(ctx, GGFV_EINVAL, "checkpoint buffer holds %lld bytes, %lld needed", ckpt_bytes, nck * sb);
+    DeviceGuard g(ctx->device);
+    const double dt_used = (ctx->dtype == GGFV_F64) ? dt : (double)(float)dt;
+    for (long long s = 0; s < nsteps; ++s) {
+        if (s % every == 0)
+            GGFV_HIP(ctx, hipMemcpyAsync(static_cast<char *>(ckpt) + (s / every) * sb, ctx->state[ctx->cur],
+                                         sb, hipMemcpyDeviceToDevice, ctx->stream));
+        GGFV_HIP(ctx, launch_step(ctx, dt));
+        ctx->cur ^= 1;
+        ctx->t += dt_used;
+        ctx->steps += 1;
+    }
+    ctx->last_dt = dt_used;
+    return GGFV_OK;
+}
+
+int ggfv_adjoint_step(ggfv_ctx *ctx, double dt, const void *u, const void *v, const void *w,
+                      const void *lam_u, const void *lam_v, const void *lam_w, void *out_u, void *out_v,
+                      void *out_w, void *g_a, void *g_b, void *g_c, double *g_params, int where, int io)
+{
+    if (!ctx) return GGFV_EINVAL;
+    const void *ins[9] = {u, v, w, lam_u, lam_v, lam_w, g_a, g_b, g_c};
+    int rc = check9(ctx, ins, where, io);
+    if (rc) return rc;
+    if ((rc = check_ptrs(ctx, out_u, out_v, out_w, where, io))) return rc;
+    if (!g_params) return fail(ctx, GGFV_EINVAL, "null g_params");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GGFV_EINVAL, "dt must be finite and > 0");
+    if (!ctx->has_tensor || !ctx->has_params) return fail(ctx, GGFV_ESTATE, "tensor and parameters must be set");
+    DeviceGuard g(ctx->device);
+    if ((rc = ensure_adjoint(ctx))) return rc;
+    void *X = adj_planes(ctx, 0), *LA = adj_planes(ctx, 3), *LB = adj_planes(ctx, 6), *G = adj_planes(ctx, 9);
+    if ((rc = pack_in(ctx, u, v, w, where, io, X))) return rc;
+    if ((rc = pack_in(ctx, lam_u, lam_v, lam_w, where, io, LA))) return rc;
+    if ((rc = pack_in(ctx, g_a, g_b, g_c, where, io, G))) return rc;
+    const int nb = adjoint_blocks(ctx);
+    GGFV_HIP(ctx, launch_zero(ctx, adj_slots(ctx), (size_t)nb * 5 * sizeof(double)));
+    GGFV_HIP(ctx, launch_adjoint_step(ctx, X, LA, LB, G, adj_slots(ctx), dt));
+    GGFV_HIP(ctx, launch_slots_reduce(ctx, adj_slots(ctx), nb, adj_result(ctx)));
+    if ((rc = copy_out(ctx, LB, false, out_u, out_v, out_w, where, io))) return rc;
+    if ((rc = copy_out(ctx, G, false, g_a, g_b, g_c, where, io))) return rc;
+    double gp[5];
+    GGFV_HIP(ctx, hipMemcpyAsync(gp, adj_result(ctx), sizeof gp, hipMemcpyDeviceToHost, ctx->stream));
+    GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 5; ++k) g_params[k] += gp[k];
+    return GGFV_OK;
+}
+
+int ggfv_adjoint_run(ggfv_ctx *ctx, double dt, long long nsteps, long long every, const void *ckpt,
+                     long long ckpt_bytes, void *work, long long work_bytes, void *lam_u, void *lam_v,
+                     void *lam_w, void *g_a, void *g_b, void *g_c, double *g_params, int where, int io)
+{
+    if (!ctx) return GGFV_EINVAL;
+    int rc = check_ptrs(ctx, lam_u, lam_v, lam_w, where, io);
+    if (rc) return rc;
+    if ((rc = check_ptrs(ctx, g_a, g_b, g_c, where, io))) return rc;
+    if (!g_params || !ckpt || !work) return fail(ctx, GGFV_EINVAL, "null checkpoint, work or g_params");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GGFV_EINVAL, "dt must be finite and > 0");
+    if (nsteps < 1 || every < 1) return fail(ctx, GGFV_EINVAL, "need nsteps >= 1 and every >= 1");
+    if (!ctx->has_tensor || !ctx->has_params) return fail(ctx, GGFV_ESTATE, "tensor and parameters must be set");
+    const long long sb = ggfv_state_bytes(ctx);
+    const long long nck = (nsteps + every - 1) / every;
+    const long long nwork = every > 1 ? every - 1 : 1;
+    if (ckpt_bytes < nck * sb) return fail(ctx, GGFV_EINVAL, "checkpoint buffer too small");
+    if (work_bytes < nwork * sb) return fail(ctx, GGFV_EINVAL, "work buffer too small (%lld < %lld)", work_bytes, nwork * sb);
+    DeviceGuard g(ctx->device);
+    if ((rc = ensure_adjoint(ctx))) return rc;
+    void *L[2] = {adj_planes(ctx, 3), adj_planes(ctx, 6)};
+    void *G = adj_planes(ctx, 9);
+    if ((rc = pack_in(ctx, lam_u, lam_v, lam_w, where, io, L[0]))) return rc;
+    const int nb = adjoint_blocks(ctx);
+    GGFV_HIP(ctx, launch_zero(ctx, G, 3 * ctx->plane * ctx->elem));
+    GGFV_HIP(ctx, launch_zero(ctx, adj_slots(ctx), (size_t)nb * 5 * sizeof(double)));
+    int cur = 0;
+    const char *ck = static_cast<const char *>(ckpt);
+    char *wk = static_cast<char *>(work);
+    for (long long c = nck - 1; c >= 0; --c) {
+        const long long s0 = c * every;
+        const long long len = (nsteps - s0 < every) ? nsteps - s0 : every;
+        auto state = [&](long long t) -> const void * {
+            return t == 0 ? static_cast<const void *>(ck + c * sb) : static_cast<const void *>(wk + (t - 1) * sb);
+        };
+        for (long long t = 0; t + 1 < len; ++t)
+            GGFV_HIP(ctx, launch_step_planes(ctx, state(t), wk + t * sb, dt));
+        for (long long t = len - 1; t >= 0; --t) {
+            GGFV_HIP(ctx, launch_adjoint_step(ctx, state(t), L[cur], L[1 - cur], G, adj_slots(ctx), dt));
+            cur ^= 1;
+        }
+    }
+    GGFV_HIP(ctx, launch_slots_reduce(ctx, adj_slots(ctx), nb, adj_result(ctx)));
+    if ((rc = copy_out(ctx, L[cur], false, lam_u, lam_v, lam_w, where, io))) return rc;
+    if ((rc = copy_out(ctx, G, false, g_a, g_b, g_c, where, io))) return rc;
+    GGFV_HIP(ctx, hipMemcpyAsync(g_params, adj_result(ctx), 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GGFV_OK;
+}
+
+int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const void *theta, const void *g_a,
+                      const void *g_b, const void *g_c, void *g_l1, void *g_l2, void *g_th, int where, int io)
+{
+    if (!ctx) return GGFV_EINVAL;
+    const void *ins[9] = {lam1, lam2, theta, g_a, g_b, g_c, g_l1, g_l2, g_th};
+    int rc = check9(ctx, ins, where, io);
+    if (rc) return rc;
+    DeviceGuard g(ctx->device);
+    const bool f64 = io == GGFV_F64;
+    if (where == GGFV_DEVICE) {
+        GGFV_HIP(ctx, launch_eig_backward(ctx, lam1, lam2, theta, g_a, g_b, g_c, g_l1, g_l2, g_th, f64));
+        return GGFV_OK;
+    }
+    if ((rc = ensure_staging(ctx, 9))) return rc;
+    const size_t bytes = (size_t)ctx->nx * ctx->ny * io_size(io);
+    char *s = static_cast<char *>(ctx->staging);
+    for (int k = 0; k < 6; ++k)
+        GGFV_HIP(ctx, hipMemcpyAsync(s + k * bytes, ins[k], bytes, hipMemcpyHostToDevice, ctx->stream));
+    GGFV_HIP(ctx, launch_eig_backward(ctx, s, s + bytes, s + 2 * bytes, s + 3 * bytes, s + 4 * bytes,
+                                      s + 5 * bytes, s + 6 * bytes, s + 7 * bytes, s + 8 * bytes, f64));
+    void *outs[3] = {g_l1, g_l2, g_th};
+    for (int k = 0; k < 3; ++k)
+        GGFV_HIP(ctx, hipMemcpyAsync(outs[k], s + (6 + k) * bytes, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GGFV_OK;
 }
 
 static int copy_out(ggfv_ctx *ctx, const void *src_base, bool has_lo, void *o0, void *o1, void *o2,

@@ -53,6 +53,9 @@ struct ggfv_ctx {
     double last_dt = 0.0;
     int rows_per_strip = 0;  // 0: chosen per launch
 
+    void *adj = nullptr;     // adjoint buffers (see ggfv_adjoint.hip), allocated on first use
+    size_t adj_bytes = 0;
+
     std::string err;
 };
 
@@ -69,6 +72,27 @@ struct StatePlanes {
 
 // One step of eq. (3) from state[cur] to state[1 - cur].
 hipError_t launch_step(ggfv_ctx *ctx, double dt);
+// One step from the stored state at `in` (nfields planes) to `out`.
+hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double dt);
+
+// ---- adjoint (ggfv_adjoint.hip) ---------------------------------------------
+// Buffers of the adjoint, allocated on first use: state planes for a single
+// adjoint step (3), adjoint state ping-pong (2 x 3), tensor gradient (3), and one
+// slot of five partial sums per adjoint block.
+int adjoint_blocks(const ggfv_ctx *ctx);
+// lam_out = (dF/dx)^T lam_in at state x (three planes u, v, w of the stored
+// precision); g (three planes) += (dF/dA)^T lam_in; per-block partial sums of
+// (dF/dp)^T lam_in are added into slots[block][5].
+hipError_t launch_adjoint_step(ggfv_ctx *ctx, const void *x, const void *lam_in, void *lam_out,
+                               void *g, double *slots, double dt);
+// slots[nblocks][5] -> out[5] (fixed order).
+hipError_t launch_slots_reduce(ggfv_ctx *ctx, const double *slots, int nblocks, double *out);
+// zero `count` doubles (or floats) on the stream (a fill kernel, not a memset).
+hipError_t launch_zero(ggfv_ctx *ctx, void *p, size_t bytes);
+// Chain rule of the tensor map from dense io arrays to dense io arrays.
+hipError_t launch_eig_backward(ggfv_ctx *ctx, const void *l1, const void *l2, const void *th,
+                               const void *ga, const void *gb, const void *gc, void *g1,
+                               void *g2, void *gt, bool f64);
 
 // Dense io array (float or double, nx*ny) -> padded storage planes (and lo
 // planes for the compensated state).  src_is_f64 selects the io type.

@@ -305,11 +305,11 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(StepArgs<T> A)
 }
 
 template <typename T, bool COMP, int CPL>
-hipError_t launch_typed(ggfv_ctx *ctx, double dt)
+hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, double dt)
 {
     StepArgs<T> A{};
-    T *in = static_cast<T *>(ctx->state[ctx->cur]);
-    T *out = static_cast<T *>(ctx->state[1 - ctx->cur]);
+    const T *in = static_cast<const T *>(in_base);
+    T *out = static_cast<T *>(out_base);
     const size_t P = ctx->plane;
     A.u = in;
     A.v = in + P;
@@ -363,14 +363,19 @@ hipError_t launch_typed(ggfv_ctx *ctx, double dt)
 
 }  // namespace
 
-hipError_t launch_step(ggfv_ctx *ctx, double dt)
+hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double dt)
 {
     switch (ctx->dtype) {
-    case GGFV_F64: return launch_typed<double, false, 1>(ctx, dt);
-    case GGFV_F32: return launch_typed<float, false, 2>(ctx, dt);
-    case GGFV_F32C: return launch_typed<float, true, 2>(ctx, dt);
+    case GGFV_F64: return launch_typed<double, false, 1>(ctx, in, out, dt);
+    case GGFV_F32: return launch_typed<float, false, 2>(ctx, in, out, dt);
+    case GGFV_F32C: return launch_typed<float, true, 2>(ctx, in, out, dt);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_step(ggfv_ctx *ctx, double dt)
+{
+    return launch_step_planes(ctx, ctx->state[ctx->cur], ctx->state[1 - ctx->cur], dt);
 }
 
 }  // namespace ggfv
