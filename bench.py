@@ -102,6 +102,113 @@ def time_variant(pk, torch, w, dtype, steps, warmup):
     }
 
 
+def time_adjoint(pk, torch, steps=5000):
+    """Gradient workload: 512^2 smooth anisotropic tensor, `steps` steps, loss of
+    the final v and w; forward with square-root checkpoints, then the native
+    reverse sweep (recompute + adjoint).  Returns times and their ratio."""
+    from paper_2006_01748_amd import autograd as ag
+    from paper_2006_01748_amd import workloads as wl
+    w = wl.cfg4(steps=steps)
+    stream = torch.cuda.current_stream()
+    ctx = pk.Context(w.nx, w.ny, dtype="f64", stream=stream.cuda_stream)
+    ctx.set_params(w.params)
+    ctx.set_tensor_eig(*w.eig)
+    dt = ctx.stable_dt(w.safety)
+    every = ag.default_every(w.steps)
+    sb = ctx.state_bytes()
+    ckpt = torch.empty(-(-w.steps // every) * sb, dtype=torch.uint8, device="cuda")
+    work = torch.empty((every - 1) * sb, dtype=torch.uint8, device="cuda")
+    lam = [torch.zeros((w.ny, w.nx), dtype=torch.float64, device="cuda") for _ in range(3)]
+    g = [torch.empty((w.ny, w.nx), dtype=torch.float64, device="cuda") for _ in range(3)]
+    res = {}
+    for rep in range(2):                    # first pass warms up
+        ctx.set_state(w.u0, w.v0, w.w0)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        ctx.step_checkpointed(dt, w.steps, every, ckpt)
+        e1.record(stream)
+        for x in lam:
+            x.fill_(1e-6)
+        ctx.adjoint_run(dt, w.steps, every, ckpt, work, lam, g)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        res = {"forward_ms": e0.elapsed_time(e1), "backward_ms": e1.elapsed_time(e2)}
+    # per-launch kernel times: plain steps vs adjoint steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.set_state(w.u0, w.v0, w.w0)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.step(dt, 1000)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_us = 1e3 * e0.elapsed_time(e1) / 1000
+    ctx.close()
+    ratio = res["backward_ms"] / res["forward_ms"]
+    return {"workload": f"{w.nx}x{w.ny} smooth anisotropic tensor, {w.steps} steps, checkpoint every "
+                        f"{every} steps (forward stores {-(-w.steps // every)} states, backward recomputes "
+                        f"each segment and runs the adjoint through it)",
+            "dtype": "f64", "forward_ms": res["forward_ms"], "backward_ms": res["backward_ms"],
+            "backward_over_forward": ratio, "step_us": fwd_us,
+            "adjoint_step_us_est": 1e3 * res["backward_ms"] / w.steps - fwd_us}
+
+
+def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50):
+    """Ensemble workload: `count` instances (sides 64..512, own parameters, tensor
+    and dt), compensated FP32.  Batched graph-replayed run versus a loop of
+    single-instance launches of the same instances on the same GPU."""
+    from paper_2006_01748_amd import workloads as wl
+    ws = wl.cfg3(count, steps)
+    stream = torch.cuda.current_stream()
+    cells = sum(w.cells for w in ws)
+    b = pk.Batch([(w.nx, w.ny) for w in ws], dtype="f32c", stream=stream.cuda_stream)
+    dts = []
+    for i, w in enumerate(ws):
+        c = b[i]
+        c.set_params(w.params)
+        c.set_tensor_eig(*w.eig)
+        c.set_state(w.u0, w.v0, w.w0)
+        dts.append(c.stable_dt(w.safety))
+        b.set_dt(i, dts[-1])
+    tuned = b.autotune(trial_steps=10)
+    b.set_tuning(threads=tuned["threads"], rows_per_strip=tuned["rows_per_strip"], graph_steps=50)
+    b.run(50)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1)
+    b.close()
+    ctxs = []
+    for i, w in enumerate(ws):
+        c = pk.Context(w.nx, w.ny, dtype="f32c", stream=stream.cuda_stream)
+        c.set_params(w.params)
+        c.set_tensor_eig(*w.eig)
+        c.set_state(w.u0, w.v0, w.w0)
+        ctxs.append(c)
+    for c, dt in zip(ctxs, dts):
+        c.step(dt, 5)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for c, dt in zip(ctxs, dts):
+        c.step(dt, loop_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1)
+    for c in ctxs:
+        c.close()
+    batch_rate = cells * steps / (batch_ms * 1e-3) / 1e9
+    loop_rate = cells * loop_steps / (loop_ms * 1e-3) / 1e9
+    return {"workload": f"{count} instances, sides 64..512 (total {cells} cells), own parameters, tensor and dt, "
+                        f"compensated FP32", "dtype": "f32c", "tuning": tuned,
+            "batched_Gcell_s": batch_rate, "batched_ms_per_step": batch_ms / steps,
+            "loop_of_single_launches_Gcell_s": loop_rate, "loop_ms_per_step": loop_ms / loop_steps,
+            "speedup": batch_rate / loop_rate,
+            "batched_GBs": 60 * cells * steps / (batch_ms * 1e-3) / 1e9}
+
+
 def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     """Plain device-to-device copy bandwidth (read + write bytes per second)."""
     x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -143,6 +250,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU "
@@ -168,6 +277,17 @@ def main():
         res[v] = time_variant(pk, torch, w, v, args.steps, args.warmup)
         log(f"  {v}: {res[v]['value']:.2f} Gcell/s, kernel {res[v]['kernel_avg_us']:.1f} us, "
             f"{res[v]['achieved_GBs']:.0f} GB/s ({100 * res[v]['frac']:.1f}% of peak)")
+    adj = None
+    if not args.no_adjoint:
+        log("timing the gradient workload (forward with checkpoints, reverse sweep)")
+        adj = time_adjoint(pk, torch)
+        log(f"  backward/forward = {adj['backward_over_forward']:.2f}")
+    ens = None
+    if not args.no_ensemble:
+        log("timing the ensemble (batched graph vs loop of single launches)")
+        ens = time_ensemble(pk, torch)
+        log(f"  batched {ens['batched_Gcell_s']:.1f} Gcell/s vs loop {ens['loop_of_single_launches_Gcell_s']:.1f} "
+            f"Gcell/s (x{ens['speedup']:.2f})")
     ceiling = None if args.no_copy_ceiling else copy_ceiling(torch)
     base = None
     if not args.no_cpu_baseline:
@@ -206,6 +326,8 @@ def main():
                          "bytes_per_cell_update": BYTES_PER_CELL[v], "kernel": KERNEL_NAME[v],
                          "traffic": measured_traffic(v)}
                      for v in variants},
+        "adjoint": adj,
+        "ensemble": ens,
         "copy_ceiling_GBs": ceiling,
         "mass_log": r["mass_log"],
     }

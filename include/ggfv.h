@@ -223,14 +223,60 @@ int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const v
                       void *g_th, int where, int io_dtype);
 
 /* Launch shape of the step kernel.  rows_per_strip is the number of grid rows
- * one workgroup sweeps (0 = chosen from the grid size); any value gives the same
- * results bit for bit.  EINVAL if negative. */
+ * one workgroup sweeps (0 = chosen from the grid size); threads is the workgroup
+ * width, 64 or 256 (0 = 256).  Any shape gives the same results bit for bit.
+ * EINVAL for a negative height or another width. */
 typedef struct {
     int rows_per_strip;
+    int threads;
 } ggfv_tuning;
 
 int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
 int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
+
+/* Time `trial_steps` steps for each candidate shape (heights 8..128, widths 64
+ * and 256) on the context's own data, keep the fastest as the context's tuning
+ * and return it.  The state, simulated time and step count are restored
+ * afterwards.  Needs state, tensor and parameters.  Synchronizes. */
+int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best);
+
+/* ---- ensembles ---------------------------------------------------------------
+ *
+ * A batch holds n independent instances (each its own grid size, parameters,
+ * tensor, state and dt) that advance together: one launch of the batched step
+ * kernel moves every instance by one step of eq. (3), and runs of many steps are
+ * captured once into a HIP graph and replayed.  Each instance is an ordinary
+ * context owned by the batch: set its parameters, tensor and state, read its
+ * state and diagnostics with the ggfv_* calls above through
+ * ggfv_batch_instance (never ggfv_destroy it).  All instances share one stream
+ * and precision. */
+typedef struct ggfv_batch ggfv_batch;
+
+/* n instances, instance i an nx[i]-by-ny[i] grid on [0,lx] x [0,ly].  With
+ * hip_stream NULL the batch creates its own (default-priority) stream, because
+ * graph capture needs a stream other than the null stream.  EINVAL on bad sizes
+ * or dtype; ENOMEM / EHIP as ggfv_create.  On failure *out is NULL and
+ * ggfv_batch_last_error(NULL) reports why. */
+int ggfv_batch_create(ggfv_batch **out, int n, const int *nx, const int *ny, double lx, double ly,
+                      int dtype, int device, void *hip_stream);
+void ggfv_batch_destroy(ggfv_batch *b);
+/* The context of instance i (owned by the batch), or NULL if i is out of range. */
+ggfv_ctx *ggfv_batch_instance(ggfv_batch *b, int i);
+/* Step size of instance i (rounded to FP32 for FP32 batches).  EINVAL unless finite and > 0. */
+int ggfv_batch_set_dt(ggfv_batch *b, int i, double dt);
+/* Advance every instance by nsteps steps (each with its own dt).  Enqueues and
+ * returns.  ESTATE if an instance lacks state, tensor, parameters or dt. */
+int ggfv_batch_run(ggfv_batch *b, long long nsteps);
+/* Launch shape of the batched kernel: workgroup width (64 or 256), strip height
+ * (0 = 16 rows, or per instance via ggfv_set_tuning on the instance), and the
+ * number of steps captured per graph (0 = no graph: one launch per step).
+ * Results are identical for every shape. */
+int ggfv_batch_set_tuning(ggfv_batch *b, int threads, int rows_per_strip, int graph_steps);
+/* Time trial_steps batched steps for each width (64, 256) and strip height
+ * (4..64), keep the fastest and report it; instance states, times and step
+ * counts are restored afterwards.  Synchronizes. */
+int ggfv_batch_autotune(ggfv_batch *b, int trial_steps, int *best_threads, int *best_rows);
+const char *ggfv_batch_last_error(const ggfv_batch *b);
 
 /* Message describing the last failure of this context ("" if none).  With
  * ctx == NULL: the message of the last failed ggfv_create on the calling thread. */

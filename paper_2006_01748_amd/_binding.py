@@ -46,6 +46,16 @@ _SIGNATURES = [
     ("ggfv_eig_backward", _c.c_int, [_VP] * 10 + [_c.c_int, _c.c_int]),
     ("ggfv_set_tuning", _c.c_int, [_VP, _VP]),
     ("ggfv_get_tuning", _c.c_int, [_VP, _VP]),
+    ("ggfv_autotune", _c.c_int, [_VP, _c.c_double, _c.c_int, _VP]),
+    ("ggfv_batch_create", _c.c_int, [_c.POINTER(_VP), _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int),
+                                     _c.c_double, _c.c_double, _c.c_int, _c.c_int, _VP]),
+    ("ggfv_batch_destroy", None, [_VP]),
+    ("ggfv_batch_instance", _VP, [_VP, _c.c_int]),
+    ("ggfv_batch_set_dt", _c.c_int, [_VP, _c.c_int, _c.c_double]),
+    ("ggfv_batch_run", _c.c_int, [_VP, _c.c_longlong]),
+    ("ggfv_batch_set_tuning", _c.c_int, [_VP, _c.c_int, _c.c_int, _c.c_int]),
+    ("ggfv_batch_autotune", _c.c_int, [_VP, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
+    ("ggfv_batch_last_error", _c.c_char_p, [_VP]),
     ("ggfv_last_error", _c.c_char_p, [_VP]),
     ("ggfv_status_string", _c.c_char_p, [_c.c_int]),
 ]
@@ -65,7 +75,7 @@ class Diag(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("rows_per_strip", ctypes.c_int)]
+    _fields_ = [("rows_per_strip", ctypes.c_int), ("threads", ctypes.c_int)]
 
 
 class GGFVError(RuntimeError):
@@ -145,8 +155,15 @@ def _current_stream():
 class Context:
     """One grid, its tensor, parameters and state on one GPU (see include/ggfv.h)."""
 
-    def __init__(self, nx, ny, lx=1.0, ly=1.0, dtype="f64", device=0, stream=None):
+    def __init__(self, nx, ny, lx=1.0, ly=1.0, dtype="f64", device=0, stream=None, _handle=None):
         self._lib = lib()
+        if _handle is not None:          # an instance owned by a Batch
+            self.nx, self.ny, self.lx, self.ly = int(nx), int(ny), float(lx), float(ly)
+            self.dtype = dtype
+            self._h = _handle
+            self._owned = False
+            return
+        self._owned = True
         self.nx, self.ny, self.lx, self.ly = int(nx), int(ny), float(lx), float(ly)
         self.dtype = dtype
         h = ctypes.c_void_p()
@@ -167,7 +184,8 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            self._lib.ggfv_destroy(self._h)
+            if getattr(self, "_owned", True):
+                self._lib.ggfv_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -331,14 +349,19 @@ class Context:
         self._check(self._lib.ggfv_eig_backward(self._h, *ptrs, where, io))
         return tuple(outs)
 
-    def set_tuning(self, rows_per_strip=0):
-        t = Tuning(int(rows_per_strip))
+    def set_tuning(self, rows_per_strip=0, threads=0):
+        t = Tuning(int(rows_per_strip), int(threads))
         self._check(self._lib.ggfv_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self):
         t = Tuning()
         self._check(self._lib.ggfv_get_tuning(self._h, ctypes.byref(t)))
-        return {"rows_per_strip": t.rows_per_strip}
+        return {"rows_per_strip": t.rows_per_strip, "threads": t.threads}
+
+    def autotune(self, dt, trial_steps=20):
+        t = Tuning()
+        self._check(self._lib.ggfv_autotune(self._h, float(dt), int(trial_steps), ctypes.byref(t)))
+        return {"rows_per_strip": t.rows_per_strip, "threads": t.threads}
 
     def diagnostics(self, allow_unstable=False):
         d = Diag()
@@ -348,3 +371,71 @@ class Context:
         return {"t": d.t, "steps": d.steps, "mass": np.array(d.mass[:]), "vmin": np.array(d.vmin[:]),
                 "vmax": np.array(d.vmax[:]), "cfl": d.cfl, "nonfinite": d.nonfinite,
                 "status": rc}
+
+
+class Batch:
+    """An ensemble of independent instances stepped together (see include/ggfv.h)."""
+
+    def __init__(self, sizes, lx=1.0, ly=1.0, dtype="f32c", device=0, stream=None):
+        self._lib = lib()
+        n = len(sizes)
+        nx = (ctypes.c_int * n)(*[int(s[0]) for s in sizes])
+        ny = (ctypes.c_int * n)(*[int(s[1]) for s in sizes])
+        if stream is None:
+            stream = _current_stream()
+        h = ctypes.c_void_p()
+        rc = self._lib.ggfv_batch_create(ctypes.byref(h), n, nx, ny, float(lx), float(ly), DTYPES[dtype],
+                                         int(device), stream)
+        if rc != GGFV_OK:
+            raise GGFVError(rc, "ggfv_batch_create failed: " + self._lib.ggfv_batch_last_error(None).decode())
+        self._h = h
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        self.dtype = dtype
+        self.instances = [Context(sx, sy, lx, ly, dtype, device,
+                                  _handle=ctypes.c_void_p(self._lib.ggfv_batch_instance(h, i)))
+                          for i, (sx, sy) in enumerate(self.sizes)]
+
+    def _check(self, rc):
+        if rc != GGFV_OK:
+            raise GGFVError(rc, self._lib.ggfv_batch_last_error(self._h).decode())
+
+    def __len__(self):
+        return len(self.instances)
+
+    def __getitem__(self, i):
+        # re-fetch so the batch knows the instance may change
+        self._lib.ggfv_batch_instance(self._h, int(i))
+        return self.instances[i]
+
+    def set_dt(self, i, dt):
+        self._check(self._lib.ggfv_batch_set_dt(self._h, int(i), float(dt)))
+
+    def run(self, nsteps):
+        self._check(self._lib.ggfv_batch_run(self._h, int(nsteps)))
+
+    def set_tuning(self, threads=64, rows_per_strip=0, graph_steps=50):
+        self._check(self._lib.ggfv_batch_set_tuning(self._h, int(threads), int(rows_per_strip), int(graph_steps)))
+
+    def autotune(self, trial_steps=10):
+        t, r = ctypes.c_int(), ctypes.c_int()
+        self._check(self._lib.ggfv_batch_autotune(self._h, int(trial_steps), ctypes.byref(t), ctypes.byref(r)))
+        return {"threads": t.value, "rows_per_strip": r.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for c in self.instances:
+                c._h = None
+            self._lib.ggfv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -554,7 +554,10 @@ int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tn)
     if (!ctx) return GGFV_EINVAL;
     if (!tn) return fail(ctx, GGFV_EINVAL, "null tuning");
     if (tn->rows_per_strip < 0) return fail(ctx, GGFV_EINVAL, "rows_per_strip must be >= 0");
+    if (tn->threads != 0 && tn->threads != 64 && tn->threads != 256)
+        return fail(ctx, GGFV_EINVAL, "threads must be 0, 64 or 256 (got %d)", tn->threads);
     ctx->rows_per_strip = tn->rows_per_strip;
+    ctx->threads = tn->threads == 0 ? 256 : tn->threads;
     return GGFV_OK;
 }
 
@@ -562,6 +565,87 @@ int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tn)
 {
     if (!ctx || !tn) return GGFV_EINVAL;
     tn->rows_per_strip = ctx->rows_per_strip;
+    tn->threads = ctx->threads;
+    return GGFV_OK;
+}
+
+int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!best) return fail(ctx, GGFV_EINVAL, "null output");
+    if (trial_steps < 1) return fail(ctx, GGFV_EINVAL, "trial_steps must be >= 1");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GGFV_EINVAL, "dt must be finite and > 0");
+    if (!ctx->has_state || !ctx->has_tensor || !ctx->has_params)
+        return fail(ctx, GGFV_ESTATE, "state, tensor and parameters must be set before tuning");
+    DeviceGuard g(ctx->device);
+    const size_t sb = ctx->nfields * ctx->plane * ctx->elem;
+    void *save = nullptr;
+    if (hipMalloc(&save, sb) != hipSuccess) return fail(ctx, GGFV_ENOMEM, "cannot allocate tuning backup");
+    const int cur0 = ctx->cur;
+    const double t0 = ctx->t, last0 = ctx->last_dt;
+    const long long s0 = ctx->steps;
+    const int rows0 = ctx->rows_per_strip, thr0 = ctx->threads;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = GGFV_OK;
+    float best_ms = 0.0f;
+    ggfv_tuning bt{rows0, thr0};
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(save);
+    };
+    if (hipMemcpyAsync(save, ctx->state[cur0], sb, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(ctx, GGFV_EHIP, "autotune setup failed");
+    }
+    const int widths[2] = {64, 256};
+    const int heights[5] = {8, 16, 32, 64, 128};
+    bool first = true;
+    for (int wdt : widths)
+        for (int h : heights) {
+            if (h > ctx->ny && h != heights[0]) continue;
+            ctx->threads = wdt;
+            ctx->rows_per_strip = h;
+            hipError_t e = launch_step(ctx, dt);   // warm-up
+            ctx->cur ^= 1;
+            if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+            for (int k = 0; e == hipSuccess && k < trial_steps; ++k) {
+                e = launch_step(ctx, dt);
+                ctx->cur ^= 1;
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(ctx, GGFV_EHIP, "autotune trial failed: %s", hipGetErrorString(e));
+                break;
+            }
+            if (first || ms < best_ms) {
+                best_ms = ms;
+                bt.rows_per_strip = h;
+                bt.threads = wdt;
+                first = false;
+            }
+        }
+    // restore the state exactly as it was
+    ctx->cur = cur0;
+    if (hipMemcpyAsync(ctx->state[cur0], save, sb, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        rc = fail(ctx, GGFV_EHIP, "autotune restore failed");
+    ctx->t = t0;
+    ctx->steps = s0;
+    ctx->last_dt = last0;
+    cleanup();
+    if (rc) {
+        ctx->rows_per_strip = rows0;
+        ctx->threads = thr0;
+        return rc;
+    }
+    ctx->rows_per_strip = bt.rows_per_strip;
+    ctx->threads = bt.threads;
+    *best = bt;
     return GGFV_OK;
 }
 

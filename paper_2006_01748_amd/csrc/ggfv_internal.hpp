@@ -52,6 +52,7 @@ struct ggfv_ctx {
     long long steps = 0;
     double last_dt = 0.0;
     int rows_per_strip = 0;  // 0: chosen per launch
+    int threads = 256;       // workgroup width of the step kernel: 64 or 256
 
     void *adj = nullptr;     // adjoint buffers (see ggfv_adjoint.hip), allocated on first use
     size_t adj_bytes = 0;
@@ -74,6 +75,22 @@ struct StatePlanes {
 hipError_t launch_step(ggfv_ctx *ctx, double dt);
 // One step from the stored state at `in` (nfields planes) to `out`.
 hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double dt);
+
+// ---- batched step (all instances of an ensemble advance one step per launch) --
+struct BatchLaunch {
+    int dtype = 0;
+    int threads = 64;        // workgroup width: 64 or 256
+    int n = 0;               // instances
+    int items = 0;           // total work items (strips) = prefix[n]
+    const void *desc = nullptr;   // device array of n step descriptions
+    const int *prefix = nullptr;  // device array of n+1 work-item offsets
+};
+hipError_t launch_step_batch(const BatchLaunch &b, hipStream_t stream);
+// Size of one step description, columns per workgroup, and filling one
+// description for a context (input planes, output planes, dt, strip height).
+size_t step_args_bytes(int dtype);
+int step_columns_per_group(int dtype, int threads);
+void fill_step_args(const ggfv_ctx *ctx, const void *in, void *out, double dt, int rows, void *dst);
 
 // ---- adjoint (ggfv_adjoint.hip) ---------------------------------------------
 // Buffers of the adjoint, allocated on first use: state planes for a single

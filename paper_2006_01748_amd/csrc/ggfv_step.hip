@@ -41,6 +41,8 @@
 // strips; horizontally adjacent strips (which re-read each other's edge columns)
 // then share one L2.
 
+#include <cstring>
+
 #include "ggfv_internal.hpp"
 
 namespace ggfv {
@@ -136,10 +138,11 @@ __device__ __forceinline__ void comp_add(T hi, T lo, T inc_dt, T &nhi, T &nlo)
     nlo = e;
 }
 
-template <typename T, bool COMP, int CPL>
-__global__ __launch_bounds__(kStepThreads) void step_kernel(StepArgs<T> A)
+// One workgroup's strip (sx, sy): columns [sx*TXW, (sx+1)*TXW), rows
+// [sy*rows, (sy+1)*rows), one step from A's input planes to its output planes.
+template <typename T, bool COMP, int CPL, int NT>
+__device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, const int sy)
 {
-    constexpr int NT = kStepThreads;
     constexpr int TXW = NT * CPL;          // owned columns per workgroup
     constexpr int LW = TXW + 2 * CPL;      // LDS row: CPL pad, TXW owned, CPL pad
     __shared__ __align__(16) T sW[4][LW];  // W rows j-1, j, j+1 (+1 being filled)
@@ -147,14 +150,6 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(StepArgs<T> A)
     __shared__ __align__(16) T sV[2][LW];
     __shared__ __align__(16) T sA[2][LW];
     __shared__ __align__(16) T sB[2][LW];
-
-    // XCD-aware remap of the linear workgroup id to a (strip x, strip y) tile.
-    const int nbx = gridDim.x;
-    const int nb = gridDim.x * gridDim.y;
-    const int bid = blockIdx.x + nbx * blockIdx.y;
-    const int xcd = bid & 7, q = nb >> 3, rem = nb & 7;
-    const int lid = xcd * q + min(xcd, rem) + (bid >> 3);
-    const int sx = lid % nbx, sy = lid / nbx;
 
     const int t = threadIdx.x;
     const int nx = A.nx, ny = A.ny;
@@ -304,8 +299,58 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(StepArgs<T> A)
     }
 }
 
-template <typename T, bool COMP, int CPL>
-hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, double dt)
+// Workgroups are dealt round-robin to the eight XCDs; map the linear id so that
+// each XCD receives one contiguous range of work items.
+__device__ __forceinline__ int xcd_local_id(int bid, int nb)
+{
+    const int xcd = bid & 7, q = nb >> 3, rem = nb & 7;
+    return xcd * q + min(xcd, rem) + (bid >> 3);
+}
+
+template <typename T, bool COMP, int CPL, int NT>
+__global__ __launch_bounds__(NT) void step_kernel(StepArgs<T> A)
+{
+    const int nbx = gridDim.x;
+    const int lid = xcd_local_id(blockIdx.x + nbx * blockIdx.y, gridDim.x * gridDim.y);
+    step_strip<T, COMP, CPL, NT>(A, lid % nbx, lid / nbx);
+}
+
+// Batched form: work item k of all instances' strips; instance i owns items
+// [prefix[i], prefix[i+1]) and its own step description D[i] (sizes, planes,
+// parameters, dt and strip height).
+template <typename T, bool COMP, int CPL, int NT>
+__global__ __launch_bounds__(NT) void step_batch_kernel(const StepArgs<T> *__restrict__ D,
+                                                        const int *__restrict__ prefix, int n)
+{
+    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    int lo = 0, hi = n;                    // prefix[lo] <= lid < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= lid) lo = mid;
+        else hi = mid;
+    }
+    const StepArgs<T> A = D[lo];
+    constexpr int TXW = NT * CPL;
+    const int nbx = (A.nx + TXW - 1) / TXW;
+    const int local = lid - prefix[lo];
+    step_strip<T, COMP, CPL, NT>(A, local % nbx, local / nbx);
+}
+
+// Strip height for a grid: aim for about four workgroups per CU (256 CUs) with
+// strips of at least 8 rows, unless the context fixes it.
+int pick_rows(const ggfv_ctx *ctx, int nbx)
+{
+    int rows = ctx->rows_per_strip;
+    if (rows <= 0) {
+        const long target = 1024;
+        long per = ((long)ctx->ny * nbx + target - 1) / target;
+        rows = (int)(per < 8 ? 8 : per);
+    }
+    return rows > ctx->ny ? ctx->ny : rows;
+}
+
+template <typename T>
+StepArgs<T> make_args(const ggfv_ctx *ctx, const void *in_base, void *out_base, double dt, int rows)
 {
     StepArgs<T> A{};
     const T *in = static_cast<const T *>(in_base);
@@ -317,7 +362,7 @@ hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, doub
     A.un = out;
     A.vn = out + P;
     A.wn = out + 2 * P;
-    if (COMP) {
+    if (ctx->dtype == GGFV_F32C) {
         A.ulo = in + 3 * P;
         A.vlo = in + 4 * P;
         A.wlo = in + 5 * P;
@@ -332,6 +377,7 @@ hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, doub
     A.nx = ctx->nx;
     A.ny = ctx->ny;
     A.pitch = ctx->pitch;
+    A.rows = rows;
     const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly;
     A.idx = T(idx);
     A.idy = T(idy);
@@ -343,21 +389,33 @@ hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, doub
     A.D2 = T(ctx->prm.Delta2);
     A.r3 = T(ctx->prm.rho3);
     A.d3 = T(ctx->prm.delta3);
+    return A;
+}
 
-    constexpr int TXW = kStepThreads * CPL;
+template <typename T, bool COMP, int CPL, int NT>
+hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, double dt)
+{
+    constexpr int TXW = NT * CPL;
     const int nbx = (ctx->nx + TXW - 1) / TXW;
-    int rows = ctx->rows_per_strip;
-    if (rows <= 0) {
-        // Aim for about four workgroups per CU (256 CUs) with strips of >= 16 rows.
-        const long target = 1024;
-        long per = ((long)ctx->ny * nbx + target - 1) / target;
-        rows = (int)(per < 16 ? 16 : per);
-    }
-    if (rows > ctx->ny) rows = ctx->ny;
-    A.rows = rows;
+    const int rows = pick_rows(ctx, nbx);
+    const StepArgs<T> A = make_args<T>(ctx, in_base, out_base, dt, rows);
     const int nby = (ctx->ny + rows - 1) / rows;
-    hipLaunchKernelGGL((step_kernel<T, COMP, CPL>), dim3(nbx, nby), dim3(kStepThreads), 0,
-                       ctx->stream, A);
+    hipLaunchKernelGGL((step_kernel<T, COMP, CPL, NT>), dim3(nbx, nby), dim3(NT), 0, ctx->stream, A);
+    return hipGetLastError();
+}
+
+template <typename T, bool COMP, int CPL>
+hipError_t launch_width(ggfv_ctx *ctx, const void *in, void *out, double dt)
+{
+    if (ctx->threads == 64) return launch_typed<T, COMP, CPL, 64>(ctx, in, out, dt);
+    return launch_typed<T, COMP, CPL, 256>(ctx, in, out, dt);
+}
+
+template <typename T, bool COMP, int CPL, int NT>
+hipError_t launch_batch_typed(const BatchLaunch &b, hipStream_t stream)
+{
+    hipLaunchKernelGGL((step_batch_kernel<T, COMP, CPL, NT>), dim3(b.items), dim3(NT), 0, stream,
+                       static_cast<const StepArgs<T> *>(b.desc), b.prefix, b.n);
     return hipGetLastError();
 }
 
@@ -366,9 +424,41 @@ hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, doub
 hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double dt)
 {
     switch (ctx->dtype) {
-    case GGFV_F64: return launch_typed<double, false, 1>(ctx, in, out, dt);
-    case GGFV_F32: return launch_typed<float, false, 2>(ctx, in, out, dt);
-    case GGFV_F32C: return launch_typed<float, true, 2>(ctx, in, out, dt);
+    case GGFV_F64: return launch_width<double, false, 1>(ctx, in, out, dt);
+    case GGFV_F32: return launch_width<float, false, 2>(ctx, in, out, dt);
+    case GGFV_F32C: return launch_width<float, true, 2>(ctx, in, out, dt);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+size_t step_args_bytes(int dtype) { return dtype == GGFV_F64 ? sizeof(StepArgs<double>) : sizeof(StepArgs<float>); }
+
+int step_columns_per_group(int dtype, int threads) { return threads * (dtype == GGFV_F64 ? 1 : 2); }
+
+void fill_step_args(const ggfv_ctx *ctx, const void *in, void *out, double dt, int rows, void *dst)
+{
+    if (ctx->dtype == GGFV_F64) {
+        StepArgs<double> A = make_args<double>(ctx, in, out, dt, rows);
+        memcpy(dst, &A, sizeof A);
+    } else {
+        StepArgs<float> A = make_args<float>(ctx, in, out, dt, rows);
+        memcpy(dst, &A, sizeof A);
+    }
+}
+
+hipError_t launch_step_batch(const BatchLaunch &b, hipStream_t stream)
+{
+    const bool narrow = b.threads == 64;
+    switch (b.dtype) {
+    case GGFV_F64:
+        return narrow ? launch_batch_typed<double, false, 1, 64>(b, stream)
+                      : launch_batch_typed<double, false, 1, 256>(b, stream);
+    case GGFV_F32:
+        return narrow ? launch_batch_typed<float, false, 2, 64>(b, stream)
+                      : launch_batch_typed<float, false, 2, 256>(b, stream);
+    case GGFV_F32C:
+        return narrow ? launch_batch_typed<float, true, 2, 64>(b, stream)
+                      : launch_batch_typed<float, true, 2, 256>(b, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -151,7 +151,7 @@ def _autograd_gradient(case):
     vt, wt = (torch.from_numpy(x).to(dev) for x in case["target"])
     loss = ag.mismatch_loss(v, ww, vt, wt, w.lx / w.nx, w.ly / w.ny)
     loss.backward()
-    return (float(loss), params.grad.numpy().copy(), l1.grad.cpu().numpy(), l2.grad.cpu().numpy(),
+    return (float(loss.detach()), params.grad.numpy().copy(), l1.grad.cpu().numpy(), l2.grad.cpu().numpy(),
             th.grad.cpu().numpy())
 
 
@@ -252,4 +252,4 @@ def test_f32c_gradients_stated_tolerance():
     errs = [abs(params.grad[k].item() - gp[k]) / abs(gp[k]) for k in range(5)]
     errs += [float(np.linalg.norm(x.grad.cpu().numpy() - r) / np.linalg.norm(r)) for x, r in zip(t, ref)]
     print(f"f32c gradient rel errors: {['%.2e' % e for e in errs]}")
-    assert max(errs) <= 1e-3
+    assert max(errs) <= 2e-5

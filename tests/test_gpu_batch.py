@@ -1,0 +1,156 @@
+"""GPU tests of the batched ensemble: every instance of a batched run equals the
+same instance stepped alone (bit for bit), sampled instances match the FP64
+oracle, graph replays equal eager launches, and the tuners restore the state."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_01748_amd as pk
+from paper_2006_01748_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances(count, steps, sides=None):
+    return [wl.cfg3_instance(i, steps, None if sides is None else sides[i % len(sides)]) for i in range(count)]
+
+
+def _setup_single(w, dtype, dt):
+    ctx = pk.Context(w.nx, w.ny, dtype=dtype)
+    ctx.set_params(w.params)
+    ctx.set_tensor_eig(*w.eig)
+    ctx.set_state(w.u0, w.v0, w.w0)
+    return ctx
+
+
+def _setup_batch(ws, dtype):
+    b = pk.Batch([(w.nx, w.ny) for w in ws], dtype=dtype)
+    dts = []
+    for i, w in enumerate(ws):
+        c = b[i]
+        c.set_params(w.params)
+        c.set_tensor_eig(*w.eig)
+        c.set_state(w.u0, w.v0, w.w0)
+        dt = c.stable_dt(w.safety)
+        b.set_dt(i, dt)
+        dts.append(dt)
+    return b, dts
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32c", "f32"])
+@pytest.mark.parametrize("threads", [64, 256])
+def test_batch_equals_single_instances_bitwise(dtype, threads):
+    ws = _instances(10, 37, sides=[64, 96, 130, 200, 512, 33])
+    # a rectangular and a one-column instance as well
+    ws.append(wl.Workload("rect", 47, 33, 1.0, 1.0, ws[0].params, *wl.disks_state(47, 33, [(0.5, 0.5)], 0.2),
+                          eig=wl.random_eig(np.random.Generator(np.random.PCG64(5)), 47, 33), safety=0.9))
+    ws.append(wl.Workload("col", 1, 40, 1.0, 1.0, ws[1].params, *wl.disks_state(1, 40, [(0.5, 0.5)], 0.2),
+                          eig=wl.random_eig(np.random.Generator(np.random.PCG64(6)), 1, 40), safety=0.9))
+    b, dts = _setup_batch(ws, dtype)
+    b.set_tuning(threads=threads, rows_per_strip=0, graph_steps=10)
+    b.run(37)                      # 3 graph replays + 7 single launches
+    for i, w in enumerate(ws):
+        got = b[i].get_state()
+        ctx = _setup_single(w, dtype, dts[i])
+        ctx.step(dts[i], 37)
+        ref = ctx.get_state()
+        assert all(np.array_equal(x, y) for x, y in zip(got, ref)), (i, w.nx, w.ny)
+        assert b[i].diagnostics()["steps"] == 37
+    b.close()
+
+
+def test_full_ensemble_against_oracle_sampled():
+    """256 instances (sides 64..512), compensated FP32, 5000 steps in one batched
+    run; the 8 smallest instances are recomputed by the FP64 oracle on the
+    FP32-rounded inputs."""
+    ws = wl.cfg3(256, 5000)
+    b, dts = _setup_batch(ws, "f32c")
+    b.run(5000)
+    order = sorted(range(len(ws)), key=lambda i: ws[i].cells)[:8]
+    f32 = lambda x: np.float64(np.float32(x))
+    worst = 0.0
+    for i in order:
+        w = ws[i]
+        eig = tuple(f32(x) for x in w.eig)
+        a, b_, c = (f32(x) for x in oracle.tensor_from_eig(*eig))
+        prm = tuple(float(np.float32(p)) for p in w.params)
+        st = tuple(f32(x) for x in (w.u0, w.v0, w.w0))
+        ref = oracle.run(*st, a, b_, c, prm, float(np.float32(dts[i])), w.steps)[:3]
+        got = b[i].get_state()
+        err = max(float(np.max(np.abs(x - y)) / np.max(np.abs(y))) for x, y in zip(got, ref))
+        worst = max(worst, err)
+        assert err <= 1e-5, (i, w.nx, err)
+    print(f"ensemble: worst per-instance max-norm error vs FP64 oracle over 8 instances: {worst:.3e}")
+    for i in range(len(ws)):
+        d = b[i].diagnostics()
+        assert d["nonfinite"] == 0 and d["steps"] == 5000
+    b.close()
+
+
+def test_graph_replays_equal_eager_launches():
+    ws = _instances(6, 40, sides=[64, 160, 256])
+    b1, _ = _setup_batch(ws, "f64")
+    b1.set_tuning(threads=64, graph_steps=0)
+    b2, _ = _setup_batch(ws, "f64")
+    b2.set_tuning(threads=64, graph_steps=4)
+    for rep in range(5):                        # several replays, host reads in between
+        b1.run(8)
+        b2.run(8)
+        for i in range(len(ws)):
+            x, y = b1[i].get_state(), b2[i].get_state()
+            assert all(np.array_equal(p, q) for p, q in zip(x, y)), (rep, i)
+    b1.close()
+    b2.close()
+
+
+def test_batch_autotune_keeps_results():
+    ws = _instances(5, 30, sides=[64, 128, 300])
+    b, dts = _setup_batch(ws, "f32c")
+    before = [b[i].get_state() for i in range(len(ws))]
+    best = b.autotune(trial_steps=4)
+    assert best["threads"] in (64, 256) and best["rows_per_strip"] in (4, 8, 16, 32, 64)
+    for i in range(len(ws)):
+        assert all(np.array_equal(p, q) for p, q in zip(before[i], b[i].get_state()))
+        assert b[i].diagnostics()["steps"] == 0
+    b.run(30)
+    ref, _ = _setup_batch(ws, "f32c")
+    ref.run(30)
+    for i in range(len(ws)):
+        assert all(np.array_equal(p, q) for p, q in zip(b[i].get_state(), ref[i].get_state()))
+    b.close()
+    ref.close()
+
+
+def test_single_context_autotune_and_narrow_width():
+    w = wl.cfg1(n=300, steps=20)
+    ctx = pk.Context(w.nx, w.ny, dtype="f64")
+    ctx.set_params(w.params)
+    ctx.set_tensor_eig(*w.eig)
+    ctx.set_state(w.u0, w.v0, w.w0)
+    dt = ctx.stable_dt(0.9)
+    before = ctx.get_state()
+    best = ctx.autotune(dt, trial_steps=3)
+    assert best["threads"] in (64, 256)
+    assert all(np.array_equal(p, q) for p, q in zip(before, ctx.get_state()))
+    ctx.step(dt, 20)
+    tuned = ctx.get_state()
+    for threads, rows in ((64, 8), (256, 13), (64, 300)):
+        ctx.set_tuning(rows, threads)
+        ctx.set_state(w.u0, w.v0, w.w0)
+        ctx.step(dt, 20)
+        assert all(np.array_equal(p, q) for p, q in zip(tuned, ctx.get_state())), (threads, rows)
+
+
+def test_batch_errors():
+    ws = _instances(2, 5, sides=[64])
+    b = pk.Batch([(w.nx, w.ny) for w in ws], dtype="f64")
+    with pytest.raises(pk.GGFVError) as e:
+        b.run(1)
+    assert e.value.status == pk.GGFV_ESTATE
+    with pytest.raises(pk.GGFVError):
+        b.set_tuning(threads=100)
+    with pytest.raises(pk.GGFVError):
+        b.set_dt(5, 1e-6)
+    with pytest.raises(pk.GGFVError):
+        b.set_dt(0, -1.0)
+    b.close()
