@@ -159,7 +159,8 @@ def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50):
     single-instance launches of the same instances on the same GPU."""
     from paper_2006_01748_amd import workloads as wl
     ws = wl.cfg3(count, steps)
-    stream = torch.cuda.current_stream()
+    # graph capture needs a stream other than the null stream: time on our own
+    stream = torch.cuda.Stream()
     cells = sum(w.cells for w in ws)
     b = pk.Batch([(w.nx, w.ny) for w in ws], dtype="f32c", stream=stream.cuda_stream)
     dts = []

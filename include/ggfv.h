@@ -224,7 +224,8 @@ int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const v
 
 /* Launch shape of the step kernel.  rows_per_strip is the number of grid rows
  * one workgroup sweeps (0 = chosen from the grid size); threads is the workgroup
- * width, 64 or 256 (0 = 256).  Any shape gives the same results bit for bit.
+ * width, 64 or 256 (0 = chosen from the grid size: 256 from 4M cells up, else
+ * 64).  Any shape gives the same results bit for bit.
  * EINVAL for a negative height or another width. */
 typedef struct {
     int rows_per_strip;
@@ -234,7 +235,7 @@ typedef struct {
 int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
 int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
 
-/* Time `trial_steps` steps for each candidate shape (heights 8..128, widths 64
+/* Time `trial_steps` steps for each candidate shape (heights 2..128, widths 64
  * and 256) on the context's own data, keep the fastest as the context's tuning
  * and return it.  The state, simulated time and step count are restored
  * afterwards.  Needs state, tensor and parameters.  Synchronizes. */

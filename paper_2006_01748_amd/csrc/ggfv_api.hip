@@ -557,7 +557,7 @@ int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tn)
     if (tn->threads != 0 && tn->threads != 64 && tn->threads != 256)
         return fail(ctx, GGFV_EINVAL, "threads must be 0, 64 or 256 (got %d)", tn->threads);
     ctx->rows_per_strip = tn->rows_per_strip;
-    ctx->threads = tn->threads == 0 ? 256 : tn->threads;
+    ctx->threads = tn->threads;
     return GGFV_OK;
 }
 
@@ -600,7 +600,7 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
         return fail(ctx, GGFV_EHIP, "autotune setup failed");
     }
     const int widths[2] = {64, 256};
-    const int heights[5] = {8, 16, 32, 64, 128};
+    const int heights[7] = {2, 4, 8, 16, 32, 64, 128};
     bool first = true;
     for (int wdt : widths)
         for (int h : heights) {

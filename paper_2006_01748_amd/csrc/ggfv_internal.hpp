@@ -52,7 +52,7 @@ struct ggfv_ctx {
     long long steps = 0;
     double last_dt = 0.0;
     int rows_per_strip = 0;  // 0: chosen per launch
-    int threads = 256;       // workgroup width of the step kernel: 64 or 256
+    int threads = 0;         // workgroup width of the step kernel: 64, 256, or 0 (by grid size)
 
     void *adj = nullptr;     // adjoint buffers (see ggfv_adjoint.hip), allocated on first use
     size_t adj_bytes = 0;

@@ -336,15 +336,24 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const StepArgs<T> *__res
     step_strip<T, COMP, CPL, NT>(A, local % nbx, local / nbx);
 }
 
-// Strip height for a grid: aim for about four workgroups per CU (256 CUs) with
-// strips of at least 8 rows, unless the context fixes it.
-int pick_rows(const ggfv_ctx *ctx, int nbx)
+// Default launch shape.  Large grids (>= 4M cells) use 256-thread workgroups
+// and about four workgroups per CU (256 CUs) with strips of >= 8 rows; smaller
+// grids use one-wave workgroups and shorter strips so that ~2048 workgroups
+// still cover the chip.  A context may fix either choice (ggfv_set_tuning).
+int pick_threads(const ggfv_ctx *ctx)
+{
+    if (ctx->threads == 64 || ctx->threads == 256) return ctx->threads;
+    return (long)ctx->nx * ctx->ny >= (1L << 22) ? 256 : 64;
+}
+
+int pick_rows(const ggfv_ctx *ctx, int nbx, int threads)
 {
     int rows = ctx->rows_per_strip;
     if (rows <= 0) {
-        const long target = 1024;
+        const long target = threads == 256 ? 1024 : 2048;
+        const int floor_rows = threads == 256 ? 8 : 4;
         long per = ((long)ctx->ny * nbx + target - 1) / target;
-        rows = (int)(per < 8 ? 8 : per);
+        rows = (int)(per < floor_rows ? floor_rows : per);
     }
     return rows > ctx->ny ? ctx->ny : rows;
 }
@@ -397,7 +406,7 @@ hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, doub
 {
     constexpr int TXW = NT * CPL;
     const int nbx = (ctx->nx + TXW - 1) / TXW;
-    const int rows = pick_rows(ctx, nbx);
+    const int rows = pick_rows(ctx, nbx, NT);
     const StepArgs<T> A = make_args<T>(ctx, in_base, out_base, dt, rows);
     const int nby = (ctx->ny + rows - 1) / rows;
     hipLaunchKernelGGL((step_kernel<T, COMP, CPL, NT>), dim3(nbx, nby), dim3(NT), 0, ctx->stream, A);
@@ -407,7 +416,7 @@ hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, doub
 template <typename T, bool COMP, int CPL>
 hipError_t launch_width(ggfv_ctx *ctx, const void *in, void *out, double dt)
 {
-    if (ctx->threads == 64) return launch_typed<T, COMP, CPL, 64>(ctx, in, out, dt);
+    if (pick_threads(ctx) == 64) return launch_typed<T, COMP, CPL, 64>(ctx, in, out, dt);
     return launch_typed<T, COMP, CPL, 256>(ctx, in, out, dt);
 }
 
