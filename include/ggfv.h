@@ -222,22 +222,28 @@ int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const v
                       const void *g_a, const void *g_b, const void *g_c, void *g_l1, void *g_l2,
                       void *g_th, int where, int io_dtype);
 
-/* Launch shape of the step kernel.  rows_per_strip is the number of grid rows
- * one workgroup sweeps (0 = chosen from the grid size); threads is the workgroup
- * width, 64 or 256 (0 = chosen from the grid size: 256 from 4M cells up, else
- * 64).  Any shape gives the same results bit for bit.
- * EINVAL for a negative height or another width. */
+/* Launch shape of the step.  rows_per_strip is the number of grid rows one
+ * workgroup sweeps (0 = chosen from the grid size).  threads is the workgroup
+ * width, 64, 128 or 256 (0 = chosen from the grid size); fused launches use 64
+ * or 128 (256 acts as 128, and depth 4 always uses 64).  fused_steps (1..4, 0 =
+ * 1) is the number of time steps computed per launch: the old state is read
+ * from HBM once, the intermediate levels stay on chip, and only the last level
+ * is written, so HBM traffic per step falls by that factor; a run of n steps
+ * uses n / fused_steps fused launches and single steps for the remainder.
+ * Every shape gives the same results bit for bit.  EINVAL for values outside
+ * these sets. */
 typedef struct {
     int rows_per_strip;
     int threads;
+    int fused_steps;
 } ggfv_tuning;
 
 int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
 int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
 
-/* Time `trial_steps` steps for each candidate shape (heights 2..128, widths 64
- * and 256) on the context's own data, keep the fastest as the context's tuning
- * and return it.  The state, simulated time and step count are restored
+/* Time `trial_steps` steps for each candidate shape (fused depths 1..4, widths
+ * 64, 128, 256, strip heights from 2 to 128 and the default) on the context's
+ * own data, keep the fastest per step as the context's tuning and return it.  The state, simulated time and step count are restored
  * afterwards.  Needs state, tensor and parameters.  Synchronizes. */
 int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best);
 

@@ -337,15 +337,14 @@ int ggfv_step_checkpointed(ggfv_ctx *ctx, double dt, long long nsteps, long long
         return fail(ctx, GGFV_EINVAL, "checkpoint buffer holds %lld bytes, %lld needed", ckpt_bytes, nck * sb);
     DeviceGuard g(ctx->device);
     const double dt_used = (ctx->dtype == GGFV_F64) ? dt : (double)(float)dt;
-    for (long long s = 0; s < nsteps; ++s) {
-        if (s % every == 0)
-            GGFV_HIP(ctx, hipMemcpyAsync(static_cast<char *>(ckpt) + (s / every) * sb, ctx->state[ctx->cur],
-                                         sb, hipMemcpyDeviceToDevice, ctx->stream));
-        GGFV_HIP(ctx, launch_step(ctx, dt));
-        ctx->cur ^= 1;
-        ctx->t += dt_used;
-        ctx->steps += 1;
+    for (long long s = 0; s < nsteps; s += every) {
+        GGFV_HIP(ctx, hipMemcpyAsync(static_cast<char *>(ckpt) + (s / every) * sb, ctx->state[ctx->cur], sb,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+        const long long n = (nsteps - s < every) ? nsteps - s : every;
+        GGFV_HIP(ctx, advance_steps(ctx, dt, n));
     }
+    ctx->t += dt_used * (double)nsteps;
+    ctx->steps += nsteps;
     ctx->last_dt = dt_used;
     return GGFV_OK;
 }
@@ -539,12 +538,9 @@ int ggfv_step(ggfv_ctx *ctx, double dt, long long nsteps)
     if (nsteps == 0) return GGFV_OK;
     DeviceGuard g(ctx->device);
     const double dt_used = (ctx->dtype == GGFV_F64) ? dt : (double)(float)dt;
-    for (long long s = 0; s < nsteps; ++s) {
-        GGFV_HIP(ctx, launch_step(ctx, dt));
-        ctx->cur ^= 1;
-        ctx->t += dt_used;
-        ctx->steps += 1;
-    }
+    GGFV_HIP(ctx, advance_steps(ctx, dt, nsteps));
+    ctx->t += dt_used * (double)nsteps;
+    ctx->steps += nsteps;
     ctx->last_dt = dt_used;
     return GGFV_OK;
 }
@@ -554,10 +550,13 @@ int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tn)
     if (!ctx) return GGFV_EINVAL;
     if (!tn) return fail(ctx, GGFV_EINVAL, "null tuning");
     if (tn->rows_per_strip < 0) return fail(ctx, GGFV_EINVAL, "rows_per_strip must be >= 0");
-    if (tn->threads != 0 && tn->threads != 64 && tn->threads != 256)
-        return fail(ctx, GGFV_EINVAL, "threads must be 0, 64 or 256 (got %d)", tn->threads);
+    if (tn->threads != 0 && tn->threads != 64 && tn->threads != 128 && tn->threads != 256)
+        return fail(ctx, GGFV_EINVAL, "threads must be 0, 64, 128 or 256 (got %d)", tn->threads);
+    if (tn->fused_steps < 0 || tn->fused_steps > 4)
+        return fail(ctx, GGFV_EINVAL, "fused_steps must be 0..4 (got %d)", tn->fused_steps);
     ctx->rows_per_strip = tn->rows_per_strip;
     ctx->threads = tn->threads;
+    ctx->fused_steps = tn->fused_steps < 1 ? 1 : tn->fused_steps;
     return GGFV_OK;
 }
 
@@ -566,6 +565,7 @@ int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tn)
     if (!ctx || !tn) return GGFV_EINVAL;
     tn->rows_per_strip = ctx->rows_per_strip;
     tn->threads = ctx->threads;
+    tn->fused_steps = ctx->fused_steps;
     return GGFV_OK;
 }
 
@@ -584,11 +584,11 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
     const int cur0 = ctx->cur;
     const double t0 = ctx->t, last0 = ctx->last_dt;
     const long long s0 = ctx->steps;
-    const int rows0 = ctx->rows_per_strip, thr0 = ctx->threads;
+    const int rows0 = ctx->rows_per_strip, thr0 = ctx->threads, fus0 = ctx->fused_steps;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = GGFV_OK;
     float best_ms = 0.0f;
-    ggfv_tuning bt{rows0, thr0};
+    ggfv_tuning bt{rows0, thr0, fus0};
     auto cleanup = [&]() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -599,36 +599,40 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
         cleanup();
         return fail(ctx, GGFV_EHIP, "autotune setup failed");
     }
-    const int widths[2] = {64, 256};
-    const int heights[7] = {2, 4, 8, 16, 32, 64, 128};
+    const int heights[8] = {0, 2, 4, 8, 16, 32, 64, 128};
+    const int widths[3] = {64, 128, 256};
     bool first = true;
-    for (int wdt : widths)
-        for (int h : heights) {
-            if (h > ctx->ny && h != heights[0]) continue;
-            ctx->threads = wdt;
-            ctx->rows_per_strip = h;
-            hipError_t e = launch_step(ctx, dt);   // warm-up
-            ctx->cur ^= 1;
-            if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
-            for (int k = 0; e == hipSuccess && k < trial_steps; ++k) {
-                e = launch_step(ctx, dt);
-                ctx->cur ^= 1;
+    for (int K = 1; K <= 4 && rc == GGFV_OK; ++K)
+        for (int wdt : widths)
+            for (int h : heights) {
+                if (K > 1 && wdt == 256) continue;        // fused widths are 64 and 128
+                if (K == 4 && wdt != 64) continue;
+                if (h > ctx->ny) continue;
+                if (K > 1 && h != 0 && h < 4 * K) continue;
+                ctx->threads = wdt;
+                ctx->rows_per_strip = h;
+                ctx->fused_steps = K;
+                const long long n = (long long)trial_steps * K;
+                hipError_t e = advance_steps(ctx, dt, K);       // warm-up
+                if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+                if (e == hipSuccess) e = advance_steps(ctx, dt, n);
+                if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    rc = fail(ctx, GGFV_EHIP, "autotune trial failed: %s", hipGetErrorString(e));
+                    break;
+                }
+                const float per_step = ms / (float)n;
+                if (first || per_step < best_ms) {
+                    best_ms = per_step;
+                    bt.rows_per_strip = h;
+                    bt.threads = wdt;
+                    bt.fused_steps = K;
+                    first = false;
+                }
             }
-            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                rc = fail(ctx, GGFV_EHIP, "autotune trial failed: %s", hipGetErrorString(e));
-                break;
-            }
-            if (first || ms < best_ms) {
-                best_ms = ms;
-                bt.rows_per_strip = h;
-                bt.threads = wdt;
-                first = false;
-            }
-        }
     // restore the state exactly as it was
     ctx->cur = cur0;
     if (hipMemcpyAsync(ctx->state[cur0], save, sb, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
@@ -641,10 +645,12 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
     if (rc) {
         ctx->rows_per_strip = rows0;
         ctx->threads = thr0;
+        ctx->fused_steps = fus0;
         return rc;
     }
     ctx->rows_per_strip = bt.rows_per_strip;
     ctx->threads = bt.threads;
+    ctx->fused_steps = bt.fused_steps;
     *best = bt;
     return GGFV_OK;
 }

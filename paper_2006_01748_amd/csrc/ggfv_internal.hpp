@@ -52,7 +52,8 @@ struct ggfv_ctx {
     long long steps = 0;
     double last_dt = 0.0;
     int rows_per_strip = 0;  // 0: chosen per launch
-    int threads = 0;         // workgroup width of the step kernel: 64, 256, or 0 (by grid size)
+    int threads = 0;         // workgroup width of the step kernel: 64, 128, 256, or 0 (by grid size)
+    int fused_steps = 1;     // time steps per launch (1..4)
 
     void *adj = nullptr;     // adjoint buffers (see ggfv_adjoint.hip), allocated on first use
     size_t adj_bytes = 0;
@@ -75,6 +76,11 @@ struct StatePlanes {
 hipError_t launch_step(ggfv_ctx *ctx, double dt);
 // One step from the stored state at `in` (nfields planes) to `out`.
 hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double dt);
+// K (2..4) steps fused into one launch, from `in` to `out` (ggfv_fused.hip).
+hipError_t launch_step_fused(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);
+// n steps of the context's current state with its tuning (fused launches plus
+// single steps for the remainder); flips ctx->cur once per launch.
+hipError_t advance_steps(ggfv_ctx *ctx, double dt, long long n);
 
 // ---- batched step (all instances of an ensemble advance one step per launch) --
 struct BatchLaunch {

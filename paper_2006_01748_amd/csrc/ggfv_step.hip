@@ -43,25 +43,10 @@
 
 #include <cstring>
 
-#include "ggfv_internal.hpp"
+#include "ggfv_step_common.hpp"
 
 namespace ggfv {
 namespace {
-
-template <typename T, int N>
-struct alignas(sizeof(T) * N) VecN {
-    T v[N];
-};
-
-template <typename T>
-struct StepArgs {
-    const T *u, *v, *w, *ulo, *vlo, *wlo;   // old level (lo only if compensated)
-    T *un, *vn, *wn, *unlo, *vnlo, *wnlo;   // new level
-    const T *a, *b, *c;
-    int nx, ny, pitch, rows;
-    T idx, idy, hx, hy, dt;
-    T d1, r2, D2, r3, d3;
-};
 
 // Values of one row that a thread needs: its own CPL columns of every field.
 template <typename T, bool COMP, int CPL>
@@ -71,32 +56,6 @@ struct Row {
     // halo column value (only meaningful in the two halo threads)
     T hW, hU, hV, ha, hb;
 };
-
-template <typename T, int CPL>
-__device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&out)[CPL])
-{
-    VecN<T, CPL> x = *reinterpret_cast<const VecN<T, CPL> *>(p);
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) out[k] = x.v[k];
-}
-
-template <typename T, int CPL>
-__device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&in)[CPL])
-{
-    VecN<T, CPL> x;
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) x.v[k] = in[k];
-    *reinterpret_cast<VecN<T, CPL> *>(p) = x;
-}
-
-template <typename T, int CPL>
-__device__ __forceinline__ void lds_store_vec(T *p, const T (&in)[CPL])
-{
-    VecN<T, CPL> x;
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) x.v[k] = in[k];
-    *reinterpret_cast<VecN<T, CPL> *>(p) = x;
-}
 
 // Load row `jr` (already clamped into [0, ny)) for the thread's columns starting
 // at `col` (clamped so the vector stays inside the padded row), plus the halo
@@ -124,18 +83,6 @@ __device__ __forceinline__ void load_row(const StepArgs<T> &A, int jr, int col, 
         r.ha = A.a[base + hcol];
         r.hb = A.b[base + hcol];
     }
-}
-
-// x + inc with the compensated pair (hi, lo): returns new (hi, lo).
-template <typename T>
-__device__ __forceinline__ void comp_add(T hi, T lo, T inc_dt, T &nhi, T &nlo)
-{
-    const T d = inc_dt + lo;
-    const T s = hi + d;
-    const T bb = s - hi;
-    const T e = (hi - (s - bb)) + (d - bb);
-    nhi = s;
-    nlo = e;
 }
 
 // One workgroup's strip (sx, sy): columns [sx*TXW, (sx+1)*TXW), rows
@@ -299,14 +246,6 @@ __device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, c
     }
 }
 
-// Workgroups are dealt round-robin to the eight XCDs; map the linear id so that
-// each XCD receives one contiguous range of work items.
-__device__ __forceinline__ int xcd_local_id(int bid, int nb)
-{
-    const int xcd = bid & 7, q = nb >> 3, rem = nb & 7;
-    return xcd * q + min(xcd, rem) + (bid >> 3);
-}
-
 template <typename T, bool COMP, int CPL, int NT>
 __global__ __launch_bounds__(NT) void step_kernel(StepArgs<T> A)
 {
@@ -342,7 +281,7 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const StepArgs<T> *__res
 // still cover the chip.  A context may fix either choice (ggfv_set_tuning).
 int pick_threads(const ggfv_ctx *ctx)
 {
-    if (ctx->threads == 64 || ctx->threads == 256) return ctx->threads;
+    if (ctx->threads == 64 || ctx->threads == 128 || ctx->threads == 256) return ctx->threads;
     return (long)ctx->nx * ctx->ny >= (1L << 22) ? 256 : 64;
 }
 
@@ -350,55 +289,12 @@ int pick_rows(const ggfv_ctx *ctx, int nbx, int threads)
 {
     int rows = ctx->rows_per_strip;
     if (rows <= 0) {
-        const long target = threads == 256 ? 1024 : 2048;
-        const int floor_rows = threads == 256 ? 8 : 4;
+        const long target = threads == 64 ? 2048 : 1024;
+        const int floor_rows = threads == 64 ? 4 : 8;
         long per = ((long)ctx->ny * nbx + target - 1) / target;
         rows = (int)(per < floor_rows ? floor_rows : per);
     }
     return rows > ctx->ny ? ctx->ny : rows;
-}
-
-template <typename T>
-StepArgs<T> make_args(const ggfv_ctx *ctx, const void *in_base, void *out_base, double dt, int rows)
-{
-    StepArgs<T> A{};
-    const T *in = static_cast<const T *>(in_base);
-    T *out = static_cast<T *>(out_base);
-    const size_t P = ctx->plane;
-    A.u = in;
-    A.v = in + P;
-    A.w = in + 2 * P;
-    A.un = out;
-    A.vn = out + P;
-    A.wn = out + 2 * P;
-    if (ctx->dtype == GGFV_F32C) {
-        A.ulo = in + 3 * P;
-        A.vlo = in + 4 * P;
-        A.wlo = in + 5 * P;
-        A.unlo = out + 3 * P;
-        A.vnlo = out + 4 * P;
-        A.wnlo = out + 5 * P;
-    }
-    const T *tn = static_cast<const T *>(ctx->tensor);
-    A.a = tn;
-    A.b = tn + P;
-    A.c = tn + 2 * P;
-    A.nx = ctx->nx;
-    A.ny = ctx->ny;
-    A.pitch = ctx->pitch;
-    A.rows = rows;
-    const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly;
-    A.idx = T(idx);
-    A.idy = T(idy);
-    A.hx = T(0.5 * idx);
-    A.hy = T(0.5 * idy);
-    A.dt = T(dt);
-    A.d1 = T(ctx->prm.delta1);
-    A.r2 = T(ctx->prm.rho2);
-    A.D2 = T(ctx->prm.Delta2);
-    A.r3 = T(ctx->prm.rho3);
-    A.d3 = T(ctx->prm.delta3);
-    return A;
 }
 
 template <typename T, bool COMP, int CPL, int NT>
@@ -416,7 +312,9 @@ hipError_t launch_typed(ggfv_ctx *ctx, const void *in_base, void *out_base, doub
 template <typename T, bool COMP, int CPL>
 hipError_t launch_width(ggfv_ctx *ctx, const void *in, void *out, double dt)
 {
-    if (pick_threads(ctx) == 64) return launch_typed<T, COMP, CPL, 64>(ctx, in, out, dt);
+    const int w = pick_threads(ctx);
+    if (w == 64) return launch_typed<T, COMP, CPL, 64>(ctx, in, out, dt);
+    if (w == 128) return launch_typed<T, COMP, CPL, 128>(ctx, in, out, dt);
     return launch_typed<T, COMP, CPL, 256>(ctx, in, out, dt);
 }
 
@@ -475,6 +373,23 @@ hipError_t launch_step_batch(const BatchLaunch &b, hipStream_t stream)
 hipError_t launch_step(ggfv_ctx *ctx, double dt)
 {
     return launch_step_planes(ctx, ctx->state[ctx->cur], ctx->state[1 - ctx->cur], dt);
+}
+
+hipError_t advance_steps(ggfv_ctx *ctx, double dt, long long n)
+{
+    const int K = ctx->fused_steps > 1 ? ctx->fused_steps : 1;
+    hipError_t e = hipSuccess;
+    if (K > 1) {
+        for (; n >= K && e == hipSuccess; n -= K) {
+            e = launch_step_fused(ctx, ctx->state[ctx->cur], ctx->state[1 - ctx->cur], dt, K);
+            ctx->cur ^= 1;
+        }
+    }
+    for (; n > 0 && e == hipSuccess; --n) {
+        e = launch_step(ctx, dt);
+        ctx->cur ^= 1;
+    }
+    return e;
 }
 
 }  // namespace ggfv

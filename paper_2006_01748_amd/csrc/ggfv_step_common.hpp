@@ -1,0 +1,124 @@
+// ggfv_step_common.hpp -- device helpers shared by the single-step and the
+// fused multi-step kernels: the step description, vector row access, the
+// compensated update and the XCD-aware work order.
+#pragma once
+
+#include "ggfv_internal.hpp"
+
+namespace ggfv {
+namespace {
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) VecN {
+    T v[N];
+};
+
+template <typename T>
+struct StepArgs {
+    const T *u, *v, *w, *ulo, *vlo, *wlo;   // old level (lo only if compensated)
+    T *un, *vn, *wn, *unlo, *vnlo, *wnlo;   // new level
+    const T *a, *b, *c;
+    int nx, ny, pitch, rows;
+    T idx, idy, hx, hy, dt;
+    T d1, r2, D2, r3, d3;
+};
+
+template <typename T, int CPL>
+__device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&out)[CPL])
+{
+    VecN<T, CPL> x = *reinterpret_cast<const VecN<T, CPL> *>(p);
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) out[k] = x.v[k];
+}
+
+// Output rows are written with non-temporal stores: the next step reads them
+// again, but the state of a large grid does not fit in any cache level, and
+// streaming stores keep the caches for the input rows' halos.
+template <typename T, int CPL>
+__device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&in)[CPL])
+{
+    if constexpr (CPL == 1) {
+        __builtin_nontemporal_store(in[0], p);
+    } else {
+        typedef T vec_t __attribute__((ext_vector_type(CPL)));
+        vec_t x;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) x[k] = in[k];
+        __builtin_nontemporal_store(x, reinterpret_cast<vec_t *>(p));
+    }
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ void lds_store_vec(T *p, const T (&in)[CPL])
+{
+    VecN<T, CPL> x;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) x.v[k] = in[k];
+    *reinterpret_cast<VecN<T, CPL> *>(p) = x;
+}
+
+// x + inc with the compensated pair (hi, lo): returns new (hi, lo).
+template <typename T>
+__device__ __forceinline__ void comp_add(T hi, T lo, T inc_dt, T &nhi, T &nlo)
+{
+    const T d = inc_dt + lo;
+    const T s = hi + d;
+    const T bb = s - hi;
+    const T e = (hi - (s - bb)) + (d - bb);
+    nhi = s;
+    nlo = e;
+}
+
+// Workgroups are dealt round-robin to the eight XCDs; map the linear id so that
+// each XCD receives one contiguous range of work items.
+__device__ __forceinline__ int xcd_local_id(int bid, int nb)
+{
+    const int xcd = bid & 7, q = nb >> 3, rem = nb & 7;
+    return xcd * q + min(xcd, rem) + (bid >> 3);
+}
+
+template <typename T>
+StepArgs<T> make_args(const ggfv_ctx *ctx, const void *in_base, void *out_base, double dt, int rows)
+{
+    StepArgs<T> A{};
+    const T *in = static_cast<const T *>(in_base);
+    T *out = static_cast<T *>(out_base);
+    const size_t P = ctx->plane;
+    A.u = in;
+    A.v = in + P;
+    A.w = in + 2 * P;
+    A.un = out;
+    A.vn = out + P;
+    A.wn = out + 2 * P;
+    if (ctx->dtype == GGFV_F32C) {
+        A.ulo = in + 3 * P;
+        A.vlo = in + 4 * P;
+        A.wlo = in + 5 * P;
+        A.unlo = out + 3 * P;
+        A.vnlo = out + 4 * P;
+        A.wnlo = out + 5 * P;
+    }
+    const T *tn = static_cast<const T *>(ctx->tensor);
+    A.a = tn;
+    A.b = tn + P;
+    A.c = tn + 2 * P;
+    A.nx = ctx->nx;
+    A.ny = ctx->ny;
+    A.pitch = ctx->pitch;
+    A.rows = rows;
+    const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly;
+    A.idx = T(idx);
+    A.idy = T(idy);
+    A.hx = T(0.5 * idx);
+    A.hy = T(0.5 * idy);
+    A.dt = T(dt);
+    A.d1 = T(ctx->prm.delta1);
+    A.r2 = T(ctx->prm.rho2);
+    A.D2 = T(ctx->prm.Delta2);
+    A.r3 = T(ctx->prm.rho3);
+    A.d3 = T(ctx->prm.delta3);
+    return A;
+}
+
+}  // namespace
+}  // namespace ggfv

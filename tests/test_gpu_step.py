@@ -339,3 +339,67 @@ def test_error_paths():
     with pytest.raises(pk.GGFVError) as e:
         ctx.diagnostics()
     assert e.value.status == pk.GGFV_EUNSTABLE
+
+
+# ---------------------------------------------------------------------------
+# several steps fused per launch: identical bits to single steps
+
+@pytest.mark.parametrize("dtype", ["f64", "f32c", "f32"])
+@pytest.mark.parametrize("K,threads", [(2, 64), (2, 128), (3, 64), (3, 128), (4, 64)])
+def test_fused_steps_bitwise(dtype, K, threads):
+    shapes = [(300, 77), (1, 50), (50, 1), (513, 130), (3, 700), (129, 129)]
+    for (nx, ny) in shapes:
+        g = rng(nx * 13 + ny + K)
+        a, b, c = wl.random_abc(g, nx, ny)
+        u, v, w = wl.random_state(g, nx, ny)
+        ctx = gpu_ctx(nx, ny, dtype, PRM, (u, v, w), abc=(a, b, c))
+        dt = ctx.stable_dt(0.9)
+        n = 4 * K + 1                              # fused launches plus a single-step remainder
+        ctx.step(dt, n)
+        ref = ctx.get_state()
+        for rows in (0, 5 * K, 37):
+            ctx.set_tuning(rows, threads, K)
+            ctx.set_state(u, v, w)
+            ctx.step(dt, n)
+            got = ctx.get_state()
+            assert all(np.array_equal(x, y) for x, y in zip(got, ref)), (nx, ny, rows)
+        ctx.close()
+
+
+def test_fused_full_size_patches_and_checkpoints():
+    """4096^2 layered tissue with three steps per launch, 60 steps, sampled
+    windows against the oracle; checkpointed stepping with fusion keeps the
+    same states."""
+    torch = pytest.importorskip("torch")
+    w = wl.cfg2(steps=60)
+    a, b, c = oracle.tensor_from_eig(*w.eig)
+    ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), eig=w.eig)
+    ctx.set_tuning(0, 128, 3)
+    dt = ctx.stable_dt(0.9)
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    n = w.nx
+    for (j0, j1, i0, i1) in [(0, 30, 0, 30), (n - 30, n, 1000, 1030), (2000, 2030, n - 30, n)]:
+        ref = _patch_reference(w, a, b, c, dt, w.steps, j0, j1, i0, i1)
+        for s_, r in zip((x[j0:j1, i0:i1] for x in got), ref):
+            assert np.max(np.abs(s_ - r)) <= 1e-12 * max(np.max(np.abs(r)), 1.0)
+    # checkpointed run with fusion: same final state, and checkpoint 1 equals the
+    # state after `every` single steps
+    every = 7
+    ckpt = torch.empty(-(-w.steps // every) * ctx.state_bytes(), dtype=torch.uint8, device="cuda")
+    ctx.set_state(w.u0, w.v0, w.w0)
+    ctx.step_checkpointed(dt, w.steps, every, ckpt)
+    assert all(np.array_equal(x, y) for x, y in zip(ctx.get_state(), got))
+    ctx.close()
+
+
+def test_autotune_picks_a_valid_shape_and_keeps_state():
+    w = wl.cfg1(n=512, steps=10)
+    ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), eig=w.eig)
+    dt = ctx.stable_dt(0.9)
+    before = ctx.get_state()
+    best = ctx.autotune(dt, trial_steps=4)
+    assert best["fused_steps"] in (1, 2, 3, 4) and best["threads"] in (64, 128, 256)
+    assert ctx.get_tuning() == best
+    assert all(np.array_equal(p, q) for p, q in zip(before, ctx.get_state()))
+    assert ctx.diagnostics()["steps"] == 0
