@@ -31,6 +31,16 @@ BYTES_PER_CELL = {"f64": 72, "f32c": 60, "f32": 36}
 KERNEL_NAME = {"f64": "step_kernel<double, false, 1>", "f32c": "step_kernel<float, true, 2>",
                "f32": "step_kernel<float, false, 2>"}
 METRIC = "Gcell-updates/s + % HBM peak, 4096² aniso FV step FP32/FP64; adjoint/fwd ratio"
+# Algorithmic floating-point operations per cell-update (each face flux counted
+# once, shared by its two cells): x/y faces of W 2 x 10, tangential differences
+# 4, divergence of W 5, faces of V 2 x 6, divergence of V 5, reactions 14,
+# Euler updates 6.  The library evaluates them without FMA contraction, so each
+# is one vector operation.
+FLOPS_PER_CELL = 66
+# MI355X vector FP64 (and non-packed FP32) rate without FMA: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz = 39.3e12 operations per second (78.6 TFLOP/s counts an FMA
+# as two operations).
+PEAK_VALU_TFLOPS = 39.3
 MASS_EVERY = 500
 
 
@@ -52,17 +62,44 @@ def measured_traffic(variant):
     return None if t is None else t["read"] + t["write"]
 
 
+def roofline_of(variant, r):
+    """Roofline of the kernel that dominates a timed run.  A single-step launch
+    moves BYTES_PER_CELL bytes per cell and is HBM-bound; a fused launch reads
+    and writes the same bytes for K steps and is bound by vector arithmetic, so
+    it is placed against the non-FMA vector rate (FLOPS_PER_CELL per
+    cell-update), with its HBM figures beside it."""
+    if r["fused_steps"] == 1:
+        return {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": measured_traffic(variant),
+                "kernel": KERNEL_NAME[variant], "kernel_avg_us": r["kernel_avg_us"],
+                "bytes_per_cell_update": BYTES_PER_CELL[variant]}
+    K = r["fused_steps"]
+    return {"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": None,
+            "kernel": f"fused_kernel<{'double' if variant == 'f64' else 'float'}, {str(variant == 'f32c').lower()}, "
+                      f"{1 if variant == 'f64' else 2}, {64 if (r['tuning']['threads'] == 64 or K == 4) else 128}, {K}>",
+            "kernel_avg_us": r["kernel_avg_us"], "steps_per_launch": K,
+            "flops_per_cell_update": FLOPS_PER_CELL,
+            "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_effective_GBs": r["effective_GBs"],
+            "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_variant(pk, torch, w, dtype, steps, warmup):
+def time_variant(pk, torch, w, dtype, steps, warmup, tune):
+    """Time `steps` steps (after `warmup`) of the workload with the default
+    single-step shape, or with the shape the autotuner picks (tune=True: the
+    search runs before the timed region, on the same data, and restores it)."""
     stream = torch.cuda.current_stream()
     ctx = pk.Context(w.nx, w.ny, w.lx, w.ly, dtype=dtype, stream=stream.cuda_stream)
     ctx.set_params(w.params)
     ctx.set_tensor_eig(*w.eig)
     ctx.set_state(w.u0, w.v0, w.w0)
     dt = ctx.stable_dt(w.safety)
+    tuning = ctx.autotune(dt, trial_steps=12) if tune else ctx.get_tuning()
+    K = max(1, tuning["fused_steps"])
     ctx.step(dt, warmup)
     torch.cuda.synchronize()
     segs = []
@@ -89,16 +126,20 @@ def time_variant(pk, torch, w, dtype, steps, warmup):
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_end)
     step_ms = sum(a.elapsed_time(b) for a, b, _ in segs)
-    kernel_us = 1e3 * step_ms / steps
+    launches = sum(n // K + n % K for _, _, n in segs)
+    kernel_us = 1e3 * step_ms / launches          # average launch (K steps when fused)
     cells = w.nx * w.ny
     value = cells * steps / (total_ms * 1e-3) / 1e9
-    achieved = BYTES_PER_CELL[dtype] * cells / (kernel_us * 1e-6) / 1e9
     d = ctx.diagnostics()
     ctx.close()
+    per_launch_bytes = BYTES_PER_CELL[dtype] * cells
     return {
         "value": value, "ms_per_step": total_ms / steps, "kernel_avg_us": kernel_us,
-        "wall_s": wall, "dt": dt, "achieved_GBs": achieved,
-        "frac": achieved / PEAK_HBM_GBS, "mass_log": masses, "cfl": d["cfl"],
+        "wall_s": wall, "dt": dt, "tuning": tuning, "fused_steps": K,
+        "achieved_GBs": per_launch_bytes / (kernel_us * 1e-6) / 1e9,
+        "effective_GBs": K * per_launch_bytes / (kernel_us * 1e-6) / 1e9,
+        "achieved_TFLOPs": FLOPS_PER_CELL * K * cells / (kernel_us * 1e-6) / 1e12,
+        "mass_log": masses, "cfl": d["cfl"],
     }
 
 
@@ -253,6 +294,7 @@ def main():
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU "
@@ -272,12 +314,19 @@ def main():
     log(f"generating {args.n}x{args.n} layered-tissue workload")
     w = wl.cfg2(n=args.n)
     variants = [v for v in args.variants.split(",") if v]
-    res = {}
+    res, single = {}, {}
     for v in variants:
-        log(f"timing {v}: {args.warmup} warm-up + {args.steps} timed steps")
-        res[v] = time_variant(pk, torch, w, v, args.steps, args.warmup)
-        log(f"  {v}: {res[v]['value']:.2f} Gcell/s, kernel {res[v]['kernel_avg_us']:.1f} us, "
-            f"{res[v]['achieved_GBs']:.0f} GB/s ({100 * res[v]['frac']:.1f}% of peak)")
+        log(f"timing {v}, single-step kernel: {args.warmup} warm-up + {args.steps} timed steps")
+        single[v] = time_variant(pk, torch, w, v, args.steps, args.warmup, tune=False)
+        log(f"  {v} single-step: {single[v]['value']:.2f} Gcell/s, kernel {single[v]['kernel_avg_us']:.1f} us, "
+            f"{single[v]['achieved_GBs']:.0f} GB/s ({100 * single[v]['achieved_GBs'] / PEAK_HBM_GBS:.1f}% of peak)")
+        if not args.no_tune:
+            log(f"timing {v}, autotuned shape")
+            res[v] = time_variant(pk, torch, w, v, args.steps, args.warmup, tune=True)
+            log(f"  {v} tuned {res[v]['tuning']}: {res[v]['value']:.2f} Gcell/s, launch {res[v]['kernel_avg_us']:.1f} us "
+                f"({res[v]['fused_steps']} steps), effective {res[v]['effective_GBs']:.0f} GB/s")
+        else:
+            res[v] = single[v]
     adj = None
     if not args.no_adjoint:
         log("timing the gradient workload (forward with checkpoints, reverse sweep)")
@@ -316,16 +365,20 @@ def main():
                         f"stability bound, masses every {MASS_EVERY} steps",
             "grid": [w.nx, w.ny], "params": list(w.params), "dt": r["dt"],
         },
-        "roofline": {
-            "bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": r["frac"], "traffic": measured_traffic(head), "kernel": KERNEL_NAME[head],
-            "kernel_avg_us": r["kernel_avg_us"], "bytes_per_cell_update": BYTES_PER_CELL[head],
-        },
+        "roofline": roofline_of(head, r),
+        "single_step_kernel": {
+            "kernel": KERNEL_NAME[head], "value": single[head]["value"],
+            "kernel_avg_us": single[head]["kernel_avg_us"], "bound": "hbm",
+            "achieved": single[head]["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": single[head]["achieved_GBs"] / PEAK_HBM_GBS, "traffic": measured_traffic(head),
+            "bytes_per_cell_update": BYTES_PER_CELL[head]},
         "cpu_baseline": base,
-        "variants": {v: {"value": res[v]["value"], "kernel_avg_us": res[v]["kernel_avg_us"],
-                         "achieved_GBs": res[v]["achieved_GBs"], "frac": res[v]["frac"],
-                         "bytes_per_cell_update": BYTES_PER_CELL[v], "kernel": KERNEL_NAME[v],
-                         "traffic": measured_traffic(v)}
+        "variants": {v: {"tuned": res[v]["tuning"], "value": res[v]["value"],
+                         "launch_avg_us": res[v]["kernel_avg_us"], "roofline": roofline_of(v, res[v]),
+                         "single_step": {"value": single[v]["value"], "kernel_avg_us": single[v]["kernel_avg_us"],
+                                         "achieved_GBs": single[v]["achieved_GBs"],
+                                         "frac": single[v]["achieved_GBs"] / PEAK_HBM_GBS,
+                                         "traffic": measured_traffic(v)}}
                      for v in variants},
         "adjoint": adj,
         "ensemble": ens,
