@@ -88,7 +88,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_variant(pk, torch, w, dtype, steps, warmup, tune):
+def time_variant(pk, torch, w, dtype, steps, warmup, tune, force=None):
     """Time `steps` steps (after `warmup`) of the workload with the default
     single-step shape, or with the shape the autotuner picks (tune=True: the
     search runs before the timed region, on the same data, and restores it)."""
@@ -98,7 +98,11 @@ def time_variant(pk, torch, w, dtype, steps, warmup, tune):
     ctx.set_tensor_eig(*w.eig)
     ctx.set_state(w.u0, w.v0, w.w0)
     dt = ctx.stable_dt(w.safety)
-    tuning = ctx.autotune(dt, trial_steps=12) if tune else ctx.get_tuning()
+    if force is not None:
+        ctx.set_tuning(*force)
+        tuning = ctx.get_tuning()
+    else:
+        tuning = ctx.autotune(dt, trial_steps=12) if tune else ctx.get_tuning()
     K = max(1, tuning["fused_steps"])
     ctx.step(dt, warmup)
     torch.cuda.synchronize()
@@ -295,6 +299,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
+    ap.add_argument("--force-tuning", default="",
+                    help="ROWS,THREADS,FUSED: use this launch shape instead of the autotuner (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU "
@@ -322,7 +328,8 @@ def main():
             f"{single[v]['achieved_GBs']:.0f} GB/s ({100 * single[v]['achieved_GBs'] / PEAK_HBM_GBS:.1f}% of peak)")
         if not args.no_tune:
             log(f"timing {v}, autotuned shape")
-            res[v] = time_variant(pk, torch, w, v, args.steps, args.warmup, tune=True)
+            force = tuple(int(x) for x in args.force_tuning.split(",")) if args.force_tuning else None
+            res[v] = time_variant(pk, torch, w, v, args.steps, args.warmup, tune=True, force=force)
             log(f"  {v} tuned {res[v]['tuning']}: {res[v]['value']:.2f} Gcell/s, launch {res[v]['kernel_avg_us']:.1f} us "
                 f"({res[v]['fused_steps']} steps), effective {res[v]['effective_GBs']:.0f} GB/s")
         else:
