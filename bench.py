@@ -44,21 +44,23 @@ PEAK_VALU_TFLOPS = 39.3
 MASS_EVERY = 500
 
 
-def measured_traffic(variant):
+def measured_traffic(variant, kernel="single"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when the step kernel source changed since the counters were taken."""
+    when a step kernel source changed since the counters were taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     try:
         with open(os.path.join(here, "profiles", "step_kernel_traffic.json")) as f:
             data = json.load(f)
-        with open(os.path.join(here, data["kernel_source"]), "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in data["kernel_sources"]:
+            with open(os.path.join(here, src), "rb") as f:
+                h.update(f.read())
     except (OSError, KeyError, ValueError):
         return None
-    if digest != data.get("kernel_source_sha256"):
+    if h.hexdigest() != data.get("kernel_sources_sha256"):
         return None
-    t = data["bytes_per_launch"].get(variant)
+    t = data["bytes_per_launch"].get(f"{variant}/{kernel}")
     return None if t is None else t["read"] + t["write"]
 
 
@@ -75,7 +77,7 @@ def roofline_of(variant, r):
                 "bytes_per_cell_update": BYTES_PER_CELL[variant]}
     K = r["fused_steps"]
     return {"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": None,
+            "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": measured_traffic(variant, f"fused{K}"),
             "kernel": f"fused_kernel<{'double' if variant == 'f64' else 'float'}, {str(variant == 'f32c').lower()}, "
                       f"{1 if variant == 'f64' else 2}, {64 if (r['tuning']['threads'] == 64 or K == 4) else 128}, {K}>",
             "kernel_avg_us": r["kernel_avg_us"], "steps_per_launch": K,
@@ -198,7 +200,7 @@ def time_adjoint(pk, torch, steps=5000):
             "adjoint_step_us_est": 1e3 * res["backward_ms"] / w.steps - fwd_us}
 
 
-def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50):
+def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50, force=None):
     """Ensemble workload: `count` instances (sides 64..512, own parameters, tensor
     and dt), compensated FP32.  Batched graph-replayed run versus a loop of
     single-instance launches of the same instances on the same GPU."""
@@ -216,7 +218,7 @@ def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50):
         c.set_state(w.u0, w.v0, w.w0)
         dts.append(c.stable_dt(w.safety))
         b.set_dt(i, dts[-1])
-    tuned = b.autotune(trial_steps=10)
+    tuned = b.autotune(trial_steps=10) if force is None else {"threads": force[0], "rows_per_strip": force[1]}
     b.set_tuning(threads=tuned["threads"], rows_per_strip=tuned["rows_per_strip"], graph_steps=50)
     b.run(50)
     torch.cuda.synchronize()
@@ -300,7 +302,10 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
     ap.add_argument("--force-tuning", default="",
-                    help="ROWS,THREADS,FUSED: use this launch shape instead of the autotuner (profiling)")
+                    help="VARIANT=ROWS,THREADS,FUSED[;...]: use these launch shapes instead of the autotuner "
+                         "(reproducible profiling)")
+    ap.add_argument("--ensemble-tuning", default="",
+                    help="THREADS,ROWS: batched launch shape instead of the batch autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU "
@@ -328,7 +333,8 @@ def main():
             f"{single[v]['achieved_GBs']:.0f} GB/s ({100 * single[v]['achieved_GBs'] / PEAK_HBM_GBS:.1f}% of peak)")
         if not args.no_tune:
             log(f"timing {v}, autotuned shape")
-            force = tuple(int(x) for x in args.force_tuning.split(",")) if args.force_tuning else None
+            forced = dict(item.split("=") for item in args.force_tuning.split(";") if item)
+            force = tuple(int(x) for x in forced[v].split(",")) if v in forced else None
             res[v] = time_variant(pk, torch, w, v, args.steps, args.warmup, tune=True, force=force)
             log(f"  {v} tuned {res[v]['tuning']}: {res[v]['value']:.2f} Gcell/s, launch {res[v]['kernel_avg_us']:.1f} us "
                 f"({res[v]['fused_steps']} steps), effective {res[v]['effective_GBs']:.0f} GB/s")
@@ -342,7 +348,8 @@ def main():
     ens = None
     if not args.no_ensemble:
         log("timing the ensemble (batched graph vs loop of single launches)")
-        ens = time_ensemble(pk, torch)
+        ens = time_ensemble(pk, torch, force=tuple(int(x) for x in args.ensemble_tuning.split(","))
+                            if args.ensemble_tuning else None)
         log(f"  batched {ens['batched_Gcell_s']:.1f} Gcell/s vs loop {ens['loop_of_single_launches_Gcell_s']:.1f} "
             f"Gcell/s (x{ens['speedup']:.2f})")
     ceiling = None if args.no_copy_ceiling else copy_ceiling(torch)
