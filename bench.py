@@ -70,16 +70,21 @@ def roofline_of(variant, r):
     and writes the same bytes for K steps and is bound by vector arithmetic, so
     it is placed against the non-FMA vector rate (FLOPS_PER_CELL per
     cell-update), with its HBM figures beside it."""
-    if r["fused_steps"] == 1:
+    if r["fused_steps"] == 1 and not r["tuning"].get("lane_shift"):
         return {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": measured_traffic(variant),
                 "kernel": KERNEL_NAME[variant], "kernel_avg_us": r["kernel_avg_us"],
                 "bytes_per_cell_update": BYTES_PER_CELL[variant]}
     K = r["fused_steps"]
+    if r["tuning"].get("lane_shift"):
+        kname = f"fused_dpp_kernel<{'double' if variant == 'f64' else 'float'}, {str(variant == 'f32c').lower()}, " \
+                f"{1 if variant == 'f64' else 2}, {K}>"
+    else:
+        kname = f"fused_kernel<{'double' if variant == 'f64' else 'float'}, {str(variant == 'f32c').lower()}, " \
+                f"{1 if variant == 'f64' else 2}, {64 if (r['tuning']['threads'] == 64 or K == 4) else 128}, {K}>"
     return {"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
             "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": measured_traffic(variant, f"fused{K}"),
-            "kernel": f"fused_kernel<{'double' if variant == 'f64' else 'float'}, {str(variant == 'f32c').lower()}, "
-                      f"{1 if variant == 'f64' else 2}, {64 if (r['tuning']['threads'] == 64 or K == 4) else 128}, {K}>",
+            "kernel": kname,
             "kernel_avg_us": r["kernel_avg_us"], "steps_per_launch": K,
             "flops_per_cell_update": FLOPS_PER_CELL,
             "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_effective_GBs": r["effective_GBs"],

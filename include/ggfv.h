@@ -230,20 +230,24 @@ int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const v
  * from HBM once, the intermediate levels stay on chip, and only the last level
  * is written, so HBM traffic per step falls by that factor; a run of n steps
  * uses n / fused_steps fused launches and single steps for the remainder.
- * Every shape gives the same results bit for bit.  EINVAL for values outside
- * these sets. */
+ * lane_shift = 1 selects the one-wave kernels that keep the rows of every time
+ * level in registers and exchange x-neighbours by lane shifts (threads is then
+ * ignored; fused_steps 1..4 applies).  Every shape gives the same results bit
+ * for bit.  EINVAL for values outside these sets. */
 typedef struct {
     int rows_per_strip;
     int threads;
     int fused_steps;
+    int lane_shift;
 } ggfv_tuning;
 
 int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
 int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
 
 /* Time `trial_steps` steps for each candidate shape (fused depths 1..4, widths
- * 64, 128, 256, strip heights from 2 to 128 and the default) on the context's
- * own data, keep the fastest per step as the context's tuning and return it.  The state, simulated time and step count are restored
+ * 64, 128, 256 and the lane-shift kernels, strip heights from 2 to 128 and the
+ * default) on the context's own data, keep the fastest per step as the
+ * context's tuning and return it.  The state, simulated time and step count are restored
  * afterwards.  Needs state, tensor and parameters.  Synchronizes. */
 int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best);
 

@@ -75,7 +75,8 @@ class Diag(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("rows_per_strip", ctypes.c_int), ("threads", ctypes.c_int), ("fused_steps", ctypes.c_int)]
+    _fields_ = [("rows_per_strip", ctypes.c_int), ("threads", ctypes.c_int), ("fused_steps", ctypes.c_int),
+                ("lane_shift", ctypes.c_int)]
 
 
 class GGFVError(RuntimeError):
@@ -349,19 +350,21 @@ class Context:
         self._check(self._lib.ggfv_eig_backward(self._h, *ptrs, where, io))
         return tuple(outs)
 
-    def set_tuning(self, rows_per_strip=0, threads=0, fused_steps=1):
-        t = Tuning(int(rows_per_strip), int(threads), int(fused_steps))
+    def set_tuning(self, rows_per_strip=0, threads=0, fused_steps=1, lane_shift=0):
+        t = Tuning(int(rows_per_strip), int(threads), int(fused_steps), int(lane_shift))
         self._check(self._lib.ggfv_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self):
         t = Tuning()
         self._check(self._lib.ggfv_get_tuning(self._h, ctypes.byref(t)))
-        return {"rows_per_strip": t.rows_per_strip, "threads": t.threads, "fused_steps": t.fused_steps}
+        return {"rows_per_strip": t.rows_per_strip, "threads": t.threads, "fused_steps": t.fused_steps,
+                "lane_shift": t.lane_shift}
 
     def autotune(self, dt, trial_steps=20):
         t = Tuning()
         self._check(self._lib.ggfv_autotune(self._h, float(dt), int(trial_steps), ctypes.byref(t)))
-        return {"rows_per_strip": t.rows_per_strip, "threads": t.threads, "fused_steps": t.fused_steps}
+        return {"rows_per_strip": t.rows_per_strip, "threads": t.threads, "fused_steps": t.fused_steps,
+                "lane_shift": t.lane_shift}
 
     def diagnostics(self, allow_unstable=False):
         d = Diag()

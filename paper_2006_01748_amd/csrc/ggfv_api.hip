@@ -554,9 +554,12 @@ int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tn)
         return fail(ctx, GGFV_EINVAL, "threads must be 0, 64, 128 or 256 (got %d)", tn->threads);
     if (tn->fused_steps < 0 || tn->fused_steps > 4)
         return fail(ctx, GGFV_EINVAL, "fused_steps must be 0..4 (got %d)", tn->fused_steps);
+    if (tn->lane_shift != 0 && tn->lane_shift != 1)
+        return fail(ctx, GGFV_EINVAL, "lane_shift must be 0 or 1 (got %d)", tn->lane_shift);
     ctx->rows_per_strip = tn->rows_per_strip;
     ctx->threads = tn->threads;
     ctx->fused_steps = tn->fused_steps < 1 ? 1 : tn->fused_steps;
+    ctx->lane_shift = tn->lane_shift;
     return GGFV_OK;
 }
 
@@ -566,6 +569,7 @@ int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tn)
     tn->rows_per_strip = ctx->rows_per_strip;
     tn->threads = ctx->threads;
     tn->fused_steps = ctx->fused_steps;
+    tn->lane_shift = ctx->lane_shift;
     return GGFV_OK;
 }
 
@@ -584,11 +588,11 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
     const int cur0 = ctx->cur;
     const double t0 = ctx->t, last0 = ctx->last_dt;
     const long long s0 = ctx->steps;
-    const int rows0 = ctx->rows_per_strip, thr0 = ctx->threads, fus0 = ctx->fused_steps;
+    const int rows0 = ctx->rows_per_strip, thr0 = ctx->threads, fus0 = ctx->fused_steps, lan0 = ctx->lane_shift;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = GGFV_OK;
     float best_ms = 0.0f;
-    ggfv_tuning bt{rows0, thr0, fus0};
+    ggfv_tuning bt{rows0, thr0, fus0, lan0};
     auto cleanup = [&]() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -600,18 +604,21 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
         return fail(ctx, GGFV_EHIP, "autotune setup failed");
     }
     const int heights[8] = {0, 2, 4, 8, 16, 32, 64, 128};
-    const int widths[3] = {64, 128, 256};
+    const int widths[4] = {64, 128, 256, 0};     // 0: lane-shift kernels
     bool first = true;
     for (int K = 1; K <= 4 && rc == GGFV_OK; ++K)
         for (int wdt : widths)
             for (int h : heights) {
-                if (K > 1 && wdt == 256) continue;        // fused widths are 64 and 128
-                if (K == 4 && wdt != 64) continue;
+                const bool lanes = wdt == 0;
+                if (!lanes && K > 1 && wdt == 256) continue;   // fused LDS widths are 64 and 128
+                if (!lanes && K == 4 && wdt != 64) continue;
                 if (h > ctx->ny) continue;
                 if (K > 1 && h != 0 && h < 4 * K) continue;
-                ctx->threads = wdt;
+                if (lanes && h != 0 && h < 8) continue;
+                ctx->threads = lanes ? 64 : wdt;
                 ctx->rows_per_strip = h;
                 ctx->fused_steps = K;
+                ctx->lane_shift = lanes ? 1 : 0;
                 const long long n = (long long)trial_steps * K;
                 hipError_t e = advance_steps(ctx, dt, K);       // warm-up
                 if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
@@ -628,8 +635,9 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
                 if (first || per_step < best_ms) {
                     best_ms = per_step;
                     bt.rows_per_strip = h;
-                    bt.threads = wdt;
+                    bt.threads = ctx->threads;
                     bt.fused_steps = K;
+                    bt.lane_shift = ctx->lane_shift;
                     first = false;
                 }
             }
@@ -646,11 +654,13 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
         ctx->rows_per_strip = rows0;
         ctx->threads = thr0;
         ctx->fused_steps = fus0;
+        ctx->lane_shift = lan0;
         return rc;
     }
     ctx->rows_per_strip = bt.rows_per_strip;
     ctx->threads = bt.threads;
     ctx->fused_steps = bt.fused_steps;
+    ctx->lane_shift = bt.lane_shift;
     *best = bt;
     return GGFV_OK;
 }

@@ -54,6 +54,7 @@ struct ggfv_ctx {
     int rows_per_strip = 0;  // 0: chosen per launch
     int threads = 0;         // workgroup width of the step kernel: 64, 128, 256, or 0 (by grid size)
     int fused_steps = 1;     // time steps per launch (1..4)
+    int lane_shift = 0;      // 1: one-wave register/lane-shift kernels (ggfv_fused_dpp.hip)
 
     void *adj = nullptr;     // adjoint buffers (see ggfv_adjoint.hip), allocated on first use
     size_t adj_bytes = 0;
@@ -78,6 +79,8 @@ hipError_t launch_step(ggfv_ctx *ctx, double dt);
 hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double dt);
 // K (2..4) steps fused into one launch, from `in` to `out` (ggfv_fused.hip).
 hipError_t launch_step_fused(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);
+// K (1..4) steps per launch with rows in registers and lane shifts (ggfv_fused_dpp.hip).
+hipError_t launch_step_fused_dpp(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);
 // n steps of the context's current state with its tuning (fused launches plus
 // single steps for the remainder); flips ctx->cur once per launch.
 hipError_t advance_steps(ggfv_ctx *ctx, double dt, long long n);

@@ -379,6 +379,17 @@ hipError_t advance_steps(ggfv_ctx *ctx, double dt, long long n)
 {
     const int K = ctx->fused_steps > 1 ? ctx->fused_steps : 1;
     hipError_t e = hipSuccess;
+    if (ctx->lane_shift) {
+        for (; n >= K && e == hipSuccess; n -= K) {
+            e = launch_step_fused_dpp(ctx, ctx->state[ctx->cur], ctx->state[1 - ctx->cur], dt, K);
+            ctx->cur ^= 1;
+        }
+        for (; n > 0 && e == hipSuccess; --n) {
+            e = launch_step_fused_dpp(ctx, ctx->state[ctx->cur], ctx->state[1 - ctx->cur], dt, 1);
+            ctx->cur ^= 1;
+        }
+        return e;
+    }
     if (K > 1) {
         for (; n >= K && e == hipSuccess; n -= K) {
             e = launch_step_fused(ctx, ctx->state[ctx->cur], ctx->state[1 - ctx->cur], dt, K);

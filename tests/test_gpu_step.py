@@ -366,6 +366,54 @@ def test_fused_steps_bitwise(dtype, K, threads):
         ctx.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32c", "f32"])
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_lane_shift_steps_bitwise(dtype, K):
+    """The one-wave kernels with register rows and lane shifts give the bits of
+    single steps, for every fused depth, strip height and ragged shape (widths
+    spanning several waves, one column, one row)."""
+    shapes = [(300, 77), (1, 50), (50, 1), (513, 130), (3, 700), (129, 129), (125, 9)]
+    for (nx, ny) in shapes:
+        g = rng(nx * 17 + ny + K)
+        a, b, c = wl.random_abc(g, nx, ny)
+        u, v, w = wl.random_state(g, nx, ny)
+        ctx = gpu_ctx(nx, ny, dtype, PRM, (u, v, w), abc=(a, b, c))
+        dt = ctx.stable_dt(0.9)
+        n = 3 * K + 2 if K > 1 else 5             # fused launches plus single-step remainder
+        ctx.step(dt, n)
+        ref = ctx.get_state()
+        for rows in (0, 1, 3, 2 * K + 1, 37):
+            ctx.set_tuning(rows, 0, K, lane_shift=1)
+            ctx.set_state(u, v, w)
+            ctx.step(dt, n)
+            got = ctx.get_state()
+            for name, x, y in zip("uvw", got, ref):
+                if not np.array_equal(x, y):
+                    bad = np.argwhere(x != y)
+                    raise AssertionError(f"{name} differs at {len(bad)} cells, first {bad[:4].tolist()} "
+                                         f"(shape {nx}x{ny}, rows {rows})")
+            assert ctx.get_tuning()["lane_shift"] == 1
+        ctx.close()
+
+
+def test_lane_shift_full_size_against_oracle_patches():
+    """4096^2 layered tissue, four steps per launch on the lane-shift kernels,
+    40 steps; windows at corners and edges against the oracle."""
+    w = wl.cfg2(steps=40)
+    a, b, c = oracle.tensor_from_eig(*w.eig)
+    ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), eig=w.eig)
+    ctx.set_tuning(0, 0, 4, lane_shift=1)
+    dt = ctx.stable_dt(0.9)
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    n = w.nx
+    for (j0, j1, i0, i1) in [(0, 30, 0, 30), (n - 30, n, n - 30, n), (2000, 2030, 55, 85)]:
+        ref = _patch_reference(w, a, b, c, dt, w.steps, j0, j1, i0, i1)
+        for s_, r in zip((x[j0:j1, i0:i1] for x in got), ref):
+            assert np.max(np.abs(s_ - r)) <= 1e-12 * max(np.max(np.abs(r)), 1.0)
+    ctx.close()
+
+
 def test_fused_full_size_patches_and_checkpoints():
     """4096^2 layered tissue with three steps per launch, 60 steps, sampled
     windows against the oracle; checkpointed stepping with fusion keeps the
