@@ -3,29 +3,33 @@
 // DPP lane shifts.
 //
 // A wave of 64 lanes owns 64*CPL adjacent columns (lane l: columns e0 + l*CPL +
-// k) and sweeps a strip upwards like the LDS-ring variant (ggfv_fused.hip), but:
-//   * every lane keeps the rows it needs of each time level in its own
-//     registers (rings of 4 rows for w, 3 for u, v and the low words), so no LDS
-//     traffic and no barriers are needed for the state;
-//   * the x-neighbour values come from the neighbouring lane through a DPP
-//     wave shift (v_mov_dpp wave_shl/wave_shr), a modifier of an ordinary VALU
-//     move;
-//   * each x-face flux is evaluated once, by the cell on its left, and the cell
-//     on its right receives it through a lane shift; both see the same bits;
-//   * the tensor rows (needed by all levels, 2K+1 rows deep) sit in a per-lane
-//     LDS ring, each lane reading only what it wrote.
-// The lanes at the two ends of the wave receive no neighbour; they are outside
+// k) and sweeps a strip upwards.  Level s = 1..K computes row q = r - 2s + 1 at
+// iteration r from rows q-1, q, q+1 of level s-1 (level 0 is the old state,
+// requested one iteration ahead).  Compared with the LDS-ring variant
+// (ggfv_fused.hip):
+//   * every lane keeps the rows it needs of each level in registers, so the
+//     state needs no LDS and no barriers;
+//   * the levels of one iteration run from K down to 1, so that level s has
+//     consumed a row of level s-1 before level s-1 overwrites it: w needs a ring
+//     of 3 rows, u, v and the low words a ring of 2;
+//   * x-neighbours come from the neighbouring lane through a DPP wave shift;
+//     each x-face flux is evaluated once, by the cell on its left, and the cell
+//     on its right receives it by a shift; b*dw/dy is shifted as one product;
+//   * the x-difference of w of row q+1 and its right-lane neighbour are kept
+//     for the next row, where they belong to the row being computed;
+//   * the tensor rows (needed by all levels, 2K rows deep) sit in a per-lane LDS
+//     ring, each lane reading only what it wrote, stored as the half face sums
+//     (a_i + a_i+1)/2 and (c_j + c_j+1)/2 that the fluxes use, plus b;
+//   * the mirrored rows of the no-flux boundary (row -1 = row 0, row ny = row
+//     ny-1) are written into the rings, so rows need no per-row selects.
+// Each level starts one row early (a warm-up row) to produce its carried south
+// face, and one row before that it takes the x-difference of its first row.
+// The lanes at the two ends of the wave receive no neighbour; they lie outside
 // the valid columns of every level above the old state (the valid range shrinks
 // by one column per level on each side), so what they compute is discarded.
 //
-// Schedule.  At iteration r the old-state row r+1 is requested (it is first
-// used one iteration later), and level s = 1..K computes row q = r - 2s + 1
-// from rows q-1, q, q+1 of level s-1.  Level s starts one row early (a warm-up
-// row) to produce its carried south-face flux, as in the other kernels.  The row
-// loop is unrolled by 12 so that every register-ring slot (row mod 4, row mod 3)
-// is a compile-time constant.
-//
-// The arithmetic per cell is the single-step kernel's, in the same order, so K
+// The arithmetic per cell is the single-step kernel's, in the same order (the
+// shared sums and products are the same operations on the same operands), so K
 // fused steps equal K single steps bit for bit.
 
 #include "ggfv_step_common.hpp"
@@ -34,20 +38,21 @@ namespace ggfv {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kPeriod = 6;    // row-loop unroll: lcm of the ring lengths 3 and 2
 
 // DPP wave shifts.  0x138: wave_shr:1 (lane l receives lane l-1); 0x130:
-// wave_shl:1 (lane l receives lane l+1).  A lane without a source keeps its own
-// value (old operand); such lanes are never used.
+// wave_shl:1 (lane l receives lane l+1).  A lane without a source receives 0
+// (bound_ctrl); such lanes are never used.
 //
 // A shift must run with every lane of the wave active: a lane reading from a
-// lane that is masked off does not receive that lane's value.  The compiler may
-// sink a move whose result is only used under a per-lane condition into that
-// condition's branch; the empty volatile asm on the result keeps the move at
-// its place in the (wave-uniform) control flow.
+// lane that is masked off does not receive that lane's value.  All shifts here
+// sit in wave-uniform control flow, and the empty volatile asm on the result
+// keeps the compiler from sinking a shift into a per-lane branch of a later
+// select.
 template <int CTRL>
-__device__ __forceinline__ int dpp_move_bits(int v)
+__device__ __forceinline__ int dpp_bits(int v)
 {
-    int r = __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+    int r = __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
     asm volatile("" : "+v"(r));
     return r;
 }
@@ -55,15 +60,15 @@ __device__ __forceinline__ int dpp_move_bits(int v)
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float x)
 {
-    return __int_as_float(dpp_move_bits<CTRL>(__float_as_int(x)));
+    return __int_as_float(dpp_bits<CTRL>(__float_as_int(x)));
 }
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x)
 {
     const long long v = __double_as_longlong(x);
-    const int nlo = dpp_move_bits<CTRL>((int)(v & 0xffffffffLL));
-    const int nhi = dpp_move_bits<CTRL>((int)(v >> 32));
+    const int nlo = dpp_bits<CTRL>((int)(v & 0xffffffffLL));
+    const int nhi = dpp_bits<CTRL>((int)(v >> 32));
     return __longlong_as_double(((long long)nhi << 32) | (long long)(unsigned)nlo);
 }
 
@@ -75,206 +80,244 @@ __device__ __forceinline__ T from_right(T x) { return dpp_move<0x130>(x); }
 constexpr int pmod(int x, int m) { return ((x % m) + m) % m; }
 
 template <typename T, bool COMP, int CPL, int K>
-struct DppState {
-    T W[K][4][CPL];               // level s rows, slot = row mod 4
-    T U[K][3][CPL];               // slot = row mod 3
-    T V[K][3][CPL];
-    T Wl[COMP ? K : 1][3][CPL];   // low words of the compensated state
-    T Ul[COMP ? K : 1][3][CPL];
-    T Vl[COMP ? K : 1][3][CPL];
-    T FYs[K][CPL], GYs[K][CPL];   // carried south faces per level
-    T ta[CPL], tb[CPL], tc[CPL];  // tensor row in flight (written to LDS next iteration)
+struct LaneRows {
+    // input rows of level s (output rows of level s-1) at index s-1
+    T W[K][3][CPL];               // slot = row mod 3
+    T U[K][2][CPL], V[K][2][CPL]; // slot = row mod 2
+    T Wl[COMP ? K : 1][2][CPL], Ul[COMP ? K : 1][2][CPL], Vl[COMP ? K : 1][2][CPL];
+    T TX[K][CPL];                 // x-difference of w of the next row of level s
+    T WR[K];                      // its w one column right of the lane's last column
+    T FYs[K][CPL], GYs[K][CPL];   // carried south faces
+    T ta[CPL], tb[CPL], tc[CPL];  // tensor row in flight
+    T cprev[CPL];                 // c of the previous tensor row
 };
 
-struct DppGeom {
-    int nx, ny, j0, j1, o0, e0, lane, cbase, lcol, last0;
-    int lo[5], re[5], hi[5];      // per level 1..K: first swept row, first real row, end
-    int outw;
+template <int K>
+struct LaneGeom {
+    int nx, ny, own, cbase, lcol, last0;
+    int lo[K + 1], re[K + 1], hi[K + 1];   // per level: warm-up row, first real row, end
+    bool store_ok;                         // the lane's columns are outputs of this workgroup
 };
 
-template <typename T, bool COMP, int CPL, int K, int RT>
-struct TensorLds {
-    T a[RT][kWave * CPL], b[RT][kWave * CPL], c[RT][kWave * CPL];
+template <typename T, int CPL, int RT>
+struct TensorRing {
+    T hA[RT][kWave * CPL];        // (a_i + a_i+1) / 2
+    T B[RT][kWave * CPL];         // b
+    T hC[RT][kWave * CPL];        // (c_j + c_j+1) / 2
 };
 
-template <typename T, bool COMP, int CPL, int K, int PH, int RT>
-__device__ __forceinline__ void dpp_iter(const StepArgs<T> &A, const DppGeom &g, DppState<T, COMP, CPL, K> &S,
-                                         TensorLds<T, COMP, CPL, K, RT> &L, const int r, const int r_start,
-                                         const int r_end)
+template <int CPL>
+struct ColumnMasks {
+    bool ve[CPL];                 // column >= 0 and its east face inside the domain
+    bool he[CPL];                 // column has an east neighbour
+    bool hw0;                     // the first column has a west neighbour
+    bool inside[CPL];             // column < nx
+};
+
+template <int RT>
+__device__ __forceinline__ int tslot(int row) { return ((row % RT) + RT) % RT; }
+
+// x-difference of w along one row (mirrored at the domain edges) and the raw
+// right-lane neighbour of the last column.
+template <typename T, int CPL>
+__device__ __forceinline__ void x_difference(const T (&X)[CPL], const ColumnMasks<CPL> &m, const T hx,
+                                             T (&TXo)[CPL], T &WRo)
 {
-    if (r < r_start || r > r_end) return;
-    const int own = g.lane * CPL;
-    const T half = T(0.5), one = T(1);
-    auto cl = [&](int j) { return j < 0 ? 0 : (j >= g.ny ? g.ny - 1 : j); };
-    auto tslot = [&](int row) { return ((row % RT) + RT) % RT; };
-
-    // The tensor row r arrived in registers during the previous iteration: store
-    // it in the lane's LDS ring.  Then request old-state row r+1 (state straight
-    // into the level-0 ring slots, tensor into the in-flight registers).
-    if (r >= r_start + 1 && r <= g.last0) {
-        const int ts = tslot(r);
+    const T WLs = from_left(X[CPL - 1]);
+    const T WRs = from_right(X[0]);
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            L.a[ts][own + k] = S.ta[k];
-            L.b[ts][own + k] = S.tb[k];
-            L.c[ts][own + k] = S.tc[k];
-        }
+    for (int k = 0; k < CPL; ++k) {
+        const T wl = k > 0 ? X[k > 0 ? k - 1 : 0] : (m.hw0 ? WLs : X[0]);
+        const T nb = k + 1 < CPL ? X[k + 1 < CPL ? k + 1 : k] : WRs;
+        const T wr = m.he[k] ? nb : X[k];
+        TXo[k] = (wr - wl) * hx;
     }
-    if (r + 1 <= g.last0) {
-        const size_t base = (size_t)cl(r + 1) * A.pitch + g.lcol;
-        constexpr int w1 = pmod(PH + 1, 4), u1 = pmod(PH + 1, 3);
-        load_vec<T, CPL>(A.w + base, S.W[0][w1]);
-        load_vec<T, CPL>(A.u + base, S.U[0][u1]);
-        load_vec<T, CPL>(A.v + base, S.V[0][u1]);
-        if constexpr (COMP) {
-            load_vec<T, CPL>(A.wlo + base, S.Wl[0][u1]);
-            load_vec<T, CPL>(A.ulo + base, S.Ul[0][u1]);
-            load_vec<T, CPL>(A.vlo + base, S.Vl[0][u1]);
-        }
-        load_vec<T, CPL>(A.a + base, S.ta);
-        load_vec<T, CPL>(A.b + base, S.tb);
-        load_vec<T, CPL>(A.c + base, S.tc);
+    WRo = WRs;
+}
+
+template <typename T, bool COMP, int CPL, int K, int PH, int S, int RT>
+__device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL> &m,
+                                          LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RT> &L, const int r)
+{
+    const int q = r - 2 * S + 1;
+    if (q < g.lo[S] - 1 || q > g.hi[S]) return;                  // uniform
+    constexpr int m3 = pmod(PH - 2 * S, 3), q3 = pmod(PH - 2 * S + 1, 3), p3 = pmod(PH - 2 * S + 2, 3);
+    constexpr int q2 = pmod(PH + 1, 2), p2 = pmod(PH, 2);       // rows q and q +- 1
+    constexpr int I = S - 1;
+
+    if (q == g.lo[S] - 1) {                  // x-difference of the first row
+        x_difference<T, CPL>(R.W[I][p3], m, A.hx, R.TX[I], R.WR[I]);
+        return;
     }
-
+    if (q == g.hi[S]) {                      // mirror row ny for level S+1
+        if constexpr (S < K) {
+            if (q == g.ny) {
 #pragma unroll
-    for (int s = 1; s <= K; ++s) {
-        const int q = r - 2 * s + 1;
-        if (q < g.lo[s] || q >= g.hi[s]) continue;              // uniform
-        const bool real = q >= g.re[s];
-        const bool has_n = q + 1 < g.ny;
-        const bool has_s = q > 0;
-        const int src = s - 1;
-        // ring slots of rows q-1, q, q+1 (r = PH mod 12, q = r + 1 - 2s)
-        const int sq4 = pmod(PH + 1 - 2 * s, 4), sp4 = pmod(PH + 2 - 2 * s, 4), sm4 = pmod(PH - 2 * s, 4);
-        const int sq3 = pmod(PH + 1 - 2 * s, 3), sp3 = pmod(PH + 2 - 2 * s, 3);
-        const int tq = tslot(q), tp = tslot(has_n ? q + 1 : q);
-
-        T W0[CPL], Wp[CPL], Wm[CPL], U0[CPL], Up[CPL], V0[CPL], Vp[CPL], A0[CPL], B0[CPL], Bp[CPL], C0[CPL],
-            Cp[CPL], TY[CPL];
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            W0[k] = S.W[src][sq4][k];
-            Wp[k] = has_n ? S.W[src][sp4][k] : W0[k];
-            Wm[k] = real ? (has_s ? S.W[src][sm4][k] : W0[k]) : T(0);
-            U0[k] = S.U[src][sq3][k];
-            V0[k] = S.V[src][sq3][k];
-            Up[k] = has_n ? S.U[src][sp3][k] : U0[k];
-            Vp[k] = has_n ? S.V[src][sp3][k] : V0[k];
-            A0[k] = L.a[tq][own + k];
-            B0[k] = L.b[tq][own + k];
-            C0[k] = L.c[tq][own + k];
-            Bp[k] = L.b[tp][own + k];
-            Cp[k] = L.c[tp][own + k];
-            TY[k] = (Wp[k] - Wm[k]) * A.hy;
-        }
-        // right neighbours of every column (lane shift for the last column)
-        T WR[CPL], aR[CPL], bR[CPL], tyR[CPL], UR[CPL], VR[CPL], WL[CPL], WLn[CPL], WRn[CPL];
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            if (k + 1 < CPL) {
-                WR[k] = W0[k + 1];
-                aR[k] = A0[k + 1];
-                bR[k] = B0[k + 1];
-                tyR[k] = TY[k + 1];
-                UR[k] = U0[k + 1];
-                VR[k] = V0[k + 1];
-                WRn[k] = Wp[k + 1];
-            } else {
-                WR[k] = from_right(W0[0]);
-                aR[k] = from_right(A0[0]);
-                bR[k] = from_right(B0[0]);
-                tyR[k] = from_right(TY[0]);
-                UR[k] = from_right(U0[0]);
-                VR[k] = from_right(V0[0]);
-                WRn[k] = from_right(Wp[0]);
-            }
-            if (k > 0) {
-                WL[k] = W0[k - 1];
-                WLn[k] = Wp[k - 1];
-            } else {
-                WL[k] = from_left(W0[CPL - 1]);
-                WLn[k] = from_left(Wp[CPL - 1]);
-            }
-        }
-        // east faces of every column
-        T FXe[CPL], GXe[CPL];
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            const int i = g.cbase + k;
-            const bool has_e = i + 1 < g.nx;
-            FXe[k] = has_e ? half * (A0[k] + aR[k]) * ((WR[k] - W0[k]) * A.idx) + half * (B0[k] * TY[k] + bR[k] * tyR[k])
-                           : T(0);
-            GXe[k] = has_e ? (one - half * (U0[k] + UR[k])) * ((VR[k] - V0[k]) * A.idx) : T(0);
-        }
-        // west faces of the first column come from the lane on the left; the
-        // shifts run outside any per-lane condition (a ?: operand is evaluated
-        // conditionally)
-        const T FXl = from_left(FXe[CPL - 1]), GXl = from_left(GXe[CPL - 1]);
-        T ou[CPL], ov[CPL], ow[CPL], oul[CPL], ovl[CPL], owl[CPL];
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            const int i = g.cbase + k;
-            const bool has_w = i > 0, has_e = i + 1 < g.nx;
-            const T FXw = has_w ? (k > 0 ? FXe[k - 1] : FXl) : T(0);
-            const T GXw = has_w ? (k > 0 ? GXe[k - 1] : GXl) : T(0);
-            // mirrored neighbours for the tangential differences
-            const T wl = has_w ? WL[k] : W0[k], wr = has_e ? WR[k] : W0[k];
-            const T wln = has_w ? WLn[k] : Wp[k], wrn = has_e ? WRn[k] : Wp[k];
-            const T txc = (wr - wl) * A.hx;
-            const T txn = (wrn - wln) * A.hx;
-            const T Wc = W0[k], Wn = Wp[k], Uc = U0[k], Vc = V0[k];
-            const T FYn = has_n ? half * (C0[k] + Cp[k]) * ((Wn - Wc) * A.idy) + half * (B0[k] * txc + Bp[k] * txn)
-                                : T(0);
-            const T GYn = has_n ? (one - half * (Uc + Up[k])) * ((Vp[k] - Vc) * A.idy) : T(0);
-            const T divW = (FXe[k] - FXw) * A.idx + (FYn - S.FYs[src][k]) * A.idy;
-            const T divV = (GXe[k] - GXw) * A.idx + (GYn - S.GYs[src][k]) * A.idy;
-            const T fu = Uc * (one - Uc) - (A.d1 * Uc) * Wc;
-            const T fv = (A.r2 * Vc) * (one - Vc) + A.D2 * divV;
-            const T fw = (A.r3 * Vc - A.d3 * Wc) + divW;
-            const bool inside = i < g.nx;
-            if constexpr (COMP) {
-                T h, l;
-                comp_add(Uc, S.Ul[src][sq3][k], A.dt * fu, h, l);
-                ou[k] = inside ? h : T(0);
-                oul[k] = inside ? l : T(0);
-                comp_add(Vc, S.Vl[src][sq3][k], A.dt * fv, h, l);
-                ov[k] = inside ? h : T(0);
-                ovl[k] = inside ? l : T(0);
-                comp_add(Wc, S.Wl[src][sq3][k], A.dt * fw, h, l);
-                ow[k] = inside ? h : T(0);
-                owl[k] = inside ? l : T(0);
-            } else {
-                ou[k] = inside ? Uc + A.dt * fu : T(0);
-                ov[k] = inside ? Vc + A.dt * fv : T(0);
-                ow[k] = inside ? Wc + A.dt * fw : T(0);
-            }
-            S.FYs[src][k] = FYn;
-            S.GYs[src][k] = GYn;
-        }
-        if (!real) continue;
-        if (s < K) {
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                S.W[s][sq4][k] = ow[k];
-                S.U[s][sq3][k] = ou[k];
-                S.V[s][sq3][k] = ov[k];
-                if constexpr (COMP) {
-                    S.Wl[s][sq3][k] = owl[k];
-                    S.Ul[s][sq3][k] = oul[k];
-                    S.Vl[s][sq3][k] = ovl[k];
+                for (int k = 0; k < CPL; ++k) {
+                    R.W[S][q3][k] = R.W[S][m3][k];
+                    R.U[S][q2][k] = R.U[S][p2][k];
+                    R.V[S][q2][k] = R.V[S][p2][k];
                 }
             }
-        } else if (g.cbase >= g.o0 && g.cbase < g.o0 + g.outw && g.cbase < A.pitch) {
-            const size_t o = (size_t)q * A.pitch + g.cbase;
-            store_vec<T, CPL>(A.un + o, ou);
-            store_vec<T, CPL>(A.vn + o, ov);
-            store_vec<T, CPL>(A.wn + o, ow);
+        }
+        return;
+    }
+
+    const T half = T(0.5), one = T(1);
+    const bool real = q >= g.re[S];
+    const bool has_n = q + 1 < g.ny;
+    const int ts = tslot<RT>(q), tp = tslot<RT>(q + 1);
+
+    T W0[CPL], Wp[CPL], U0[CPL], V0[CPL], TY[CPL], BT[CPL], B0[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        W0[k] = R.W[I][q3][k];
+        Wp[k] = R.W[I][p3][k];
+        U0[k] = R.U[I][q2][k];
+        V0[k] = R.V[I][q2][k];
+        B0[k] = L.B[ts][g.own + k];
+        TY[k] = (Wp[k] - R.W[I][m3][k]) * A.hy;
+        BT[k] = B0[k] * TY[k];
+    }
+    // shifts: b*ty, u and v from the right; x-difference of row q+1
+    const T btR = from_right(BT[0]), uR = from_right(U0[0]), vR = from_right(V0[0]);
+    T TXn[CPL], WRn;
+    x_difference<T, CPL>(Wp, m, A.hx, TXn, WRn);
+
+    // east faces of every column
+    T FXe[CPL], GXe[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int k1 = k + 1 < CPL ? k + 1 : k;
+        const T wr = k + 1 < CPL ? W0[k1] : R.WR[I];
+        const T btr = k + 1 < CPL ? BT[k1] : btR;
+        const T ur = k + 1 < CPL ? U0[k1] : uR;
+        const T vr = k + 1 < CPL ? V0[k1] : vR;
+        const T hA = L.hA[ts][g.own + k];
+        FXe[k] = m.ve[k] ? hA * ((wr - W0[k]) * A.idx) + half * (BT[k] + btr) : T(0);
+        GXe[k] = m.ve[k] ? (one - half * (U0[k] + ur)) * ((vr - V0[k]) * A.idx) : T(0);
+    }
+    // west face of the first column: the left lane's last east face (0 left of
+    // column 0, where that face lies outside the domain)
+    const T FXl = from_left(FXe[CPL - 1]), GXl = from_left(GXe[CPL - 1]);
+
+    T ou[CPL], ov[CPL], ow[CPL], oul[CPL], ovl[CPL], owl[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const T Up = R.U[I][p2][k], Vp = R.V[I][p2][k];
+        const T Bp = L.B[tp][g.own + k], hC = L.hC[ts][g.own + k];
+        const T FXw = k > 0 ? FXe[k > 0 ? k - 1 : 0] : FXl;
+        const T GXw = k > 0 ? GXe[k > 0 ? k - 1 : 0] : GXl;
+        const T Wc = W0[k], Uc = U0[k], Vc = V0[k];
+        const T FYn = has_n ? hC * ((Wp[k] - Wc) * A.idy) + half * (B0[k] * R.TX[I][k] + Bp * TXn[k]) : T(0);
+        const T GYn = has_n ? (one - half * (Uc + Up)) * ((Vp - Vc) * A.idy) : T(0);
+        const T divW = (FXe[k] - FXw) * A.idx + (FYn - R.FYs[I][k]) * A.idy;
+        const T divV = (GXe[k] - GXw) * A.idx + (GYn - R.GYs[I][k]) * A.idy;
+        const T fu = Uc * (one - Uc) - (A.d1 * Uc) * Wc;
+        const T fv = (A.r2 * Vc) * (one - Vc) + A.D2 * divV;
+        const T fw = (A.r3 * Vc - A.d3 * Wc) + divW;
+        if constexpr (COMP) {
+            comp_add(Uc, R.Ul[I][q2][k], A.dt * fu, ou[k], oul[k]);
+            comp_add(Vc, R.Vl[I][q2][k], A.dt * fv, ov[k], ovl[k]);
+            comp_add(Wc, R.Wl[I][q2][k], A.dt * fw, ow[k], owl[k]);
+        } else {
+            ou[k] = Uc + A.dt * fu;
+            ov[k] = Vc + A.dt * fv;
+            ow[k] = Wc + A.dt * fw;
+        }
+        R.FYs[I][k] = FYn;
+        R.GYs[I][k] = GYn;
+        R.TX[I][k] = TXn[k];
+    }
+    R.WR[I] = WRn;
+
+    // A warm-up row's result is written into the ring like any other: the only
+    // reader of that ring row is the next level's warm-up row, as the south
+    // neighbour whose flux it discards.
+    if constexpr (S < K) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            R.W[S][q3][k] = ow[k];
+            R.U[S][q2][k] = ou[k];
+            R.V[S][q2][k] = ov[k];
             if constexpr (COMP) {
-                store_vec<T, CPL>(A.unlo + o, oul);
-                store_vec<T, CPL>(A.vnlo + o, ovl);
-                store_vec<T, CPL>(A.wnlo + o, owl);
+                R.Wl[S][q2][k] = owl[k];
+                R.Ul[S][q2][k] = oul[k];
+                R.Vl[S][q2][k] = ovl[k];
             }
         }
+        if (q == 0) {                        // mirror row -1 for level S+1
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) R.W[S][m3][k] = ow[k];
+        }
+    } else if (real && g.store_ok) {
+        // columns past nx (row padding) are written as zeros
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            ou[k] = m.inside[k] ? ou[k] : T(0);
+            ov[k] = m.inside[k] ? ov[k] : T(0);
+            ow[k] = m.inside[k] ? ow[k] : T(0);
+            if constexpr (COMP) {
+                oul[k] = m.inside[k] ? oul[k] : T(0);
+                ovl[k] = m.inside[k] ? ovl[k] : T(0);
+                owl[k] = m.inside[k] ? owl[k] : T(0);
+            }
+        }
+        const size_t o = (size_t)q * A.pitch + g.cbase;
+        store_vec<T, CPL>(A.un + o, ou);
+        store_vec<T, CPL>(A.vn + o, ov);
+        store_vec<T, CPL>(A.wn + o, ow);
+        if constexpr (COMP) {
+            store_vec<T, CPL>(A.unlo + o, oul);
+            store_vec<T, CPL>(A.vnlo + o, ovl);
+            store_vec<T, CPL>(A.wnlo + o, owl);
+        }
+    }
+}
+
+template <typename T, bool COMP, int CPL, int K, int PH, int RT>
+__device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL> &m,
+                                          LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RT> &L, const int r,
+                                          const int r_start, const int r_end)
+{
+    if (r < r_start || r > r_end) return;                        // uniform
+    if constexpr (K >= 4) level_row<T, COMP, CPL, K, PH, 4, RT>(A, g, m, R, L, r);
+    if constexpr (K >= 3) level_row<T, COMP, CPL, K, PH, 3, RT>(A, g, m, R, L, r);
+    if constexpr (K >= 2) level_row<T, COMP, CPL, K, PH, 2, RT>(A, g, m, R, L, r);
+
+    // tensor row r (requested one iteration ago) into the ring; the c face sum
+    // of row r-1 needs row r
+    if (r >= r_start + 1 && r <= g.last0) {
+        const T half = T(0.5);
+        const T aRs = from_right(R.ta[0]);
+        const int ts = tslot<RT>(r), tm = tslot<RT>(r - 1);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            const T ar = k + 1 < CPL ? R.ta[k + 1 < CPL ? k + 1 : k] : aRs;
+            L.hA[ts][g.own + k] = half * (R.ta[k] + ar);
+            L.B[ts][g.own + k] = R.tb[k];
+            L.hC[tm][g.own + k] = half * (R.cprev[k] + R.tc[k]);
+            R.cprev[k] = R.tc[k];
+        }
+    }
+    level_row<T, COMP, CPL, K, PH, 1, RT>(A, g, m, R, L, r);
+
+    // request old-state row r+1 (clamped: rows -1 and ny load their mirrors)
+    if (r + 1 <= g.last0) {
+        const int row = min(max(r + 1, 0), g.ny - 1);
+        const size_t base = (size_t)row * A.pitch + g.lcol;
+        constexpr int w1 = pmod(PH + 1, 3), u1 = pmod(PH + 1, 2);
+        load_vec<T, CPL>(A.w + base, R.W[0][w1]);
+        load_vec<T, CPL>(A.u + base, R.U[0][u1]);
+        load_vec<T, CPL>(A.v + base, R.V[0][u1]);
+        if constexpr (COMP) {
+            load_vec<T, CPL>(A.wlo + base, R.Wl[0][u1]);
+            load_vec<T, CPL>(A.ulo + base, R.Ul[0][u1]);
+            load_vec<T, CPL>(A.vlo + base, R.Vl[0][u1]);
+        }
+        load_vec<T, CPL>(A.a + base, R.ta);
+        load_vec<T, CPL>(A.b + base, R.tb);
+        load_vec<T, CPL>(A.c + base, R.tc);
     }
 }
 
@@ -284,57 +327,78 @@ __global__ __launch_bounds__(kWave) void fused_dpp_kernel(StepArgs<T> A)
     constexpr int TXW = kWave * CPL;
     constexpr int H = (K + CPL - 1) / CPL * CPL;
     constexpr int OUTW = TXW - 2 * H;
-    constexpr int RT = 2 * K + 1;
+    constexpr int RT = 2 * K;
     static_assert(K >= 1 && K <= 4, "fused depth 1..4");
-    __shared__ TensorLds<T, COMP, CPL, K, RT> L;
+    __shared__ TensorRing<T, CPL, RT> L;
 
     const int nbx = gridDim.x;
     const int lid = xcd_local_id(blockIdx.x + nbx * blockIdx.y, gridDim.x * gridDim.y);
     const int sx = lid % nbx, sy = lid / nbx;
-    DppGeom g;
+    const int o0 = sx * OUTW, e0 = o0 - H;
+    LaneGeom<K> g;
     g.nx = A.nx;
     g.ny = A.ny;
-    g.o0 = sx * OUTW;
-    g.e0 = g.o0 - H;
-    g.outw = OUTW;
-    g.j0 = sy * A.rows;
-    g.j1 = min(g.ny, g.j0 + A.rows);
-    g.lane = threadIdx.x;
-    g.cbase = g.e0 + g.lane * CPL;
+    g.own = threadIdx.x * CPL;
+    g.cbase = e0 + (int)threadIdx.x * CPL;
     g.lcol = min(max(g.cbase, 0), A.pitch - CPL);
+    g.store_ok = g.cbase >= o0 && g.cbase < o0 + OUTW && g.cbase < A.pitch;
+    const int j0 = sy * A.rows, j1 = min(g.ny, j0 + A.rows);
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
-        g.lo[s] = max(0, g.j0 - (K - s) - 1);
-        g.re[s] = max(0, g.j0 - (K - s));
-        g.hi[s] = min(g.ny, g.j1 + (K - s));
+        g.lo[s] = max(0, j0 - (K - s) - 1);
+        g.re[s] = max(0, j0 - (K - s));
+        g.hi[s] = min(g.ny, j1 + (K - s));
     }
-    g.last0 = g.hi[1];                     // last old-state row needed (clamped on load)
-    const int r_begin = g.lo[1] + 1;       // level 1 computes q = r - 1
-    const int r_end = g.hi[K] - 1 + 2 * K - 1;
-    const int r_start = r_begin - 4;       // four load-only iterations fill the rings
-
-    DppState<T, COMP, CPL, K> S;
+    g.lo[0] = g.re[0] = g.hi[0] = 0;
+    g.last0 = g.hi[1];                     // last old-state row level 1 reads
+    ColumnMasks<CPL> m;
 #pragma unroll
-    for (int s = 0; s < K; ++s)
+    for (int k = 0; k < CPL; ++k) {
+        const int i = g.cbase + k;
+        m.ve[k] = i >= 0 && i + 1 < g.nx;
+        m.he[k] = i + 1 < g.nx;
+        m.inside[k] = i < g.nx;
+    }
+    m.hw0 = g.cbase > 0;
+
+    LaneRows<T, COMP, CPL, K> R;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-            S.FYs[s][k] = T(0);
-            S.GYs[s][k] = T(0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) R.W[s][j][k] = T(0);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                R.U[s][j][k] = T(0);
+                R.V[s][j][k] = T(0);
+                if constexpr (COMP) {
+                    R.Wl[s][j][k] = T(0);
+                    R.Ul[s][j][k] = T(0);
+                    R.Vl[s][j][k] = T(0);
+                }
+            }
+            R.TX[s][k] = T(0);
+            R.FYs[s][k] = T(0);
+            R.GYs[s][k] = T(0);
         }
-    const int r0 = r_start - pmod(r_start, 12);
-    for (int rb = r0; rb <= r_end; rb += 12) {
-        dpp_iter<T, COMP, CPL, K, 0, RT>(A, g, S, L, rb + 0, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 1, RT>(A, g, S, L, rb + 1, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 2, RT>(A, g, S, L, rb + 2, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 3, RT>(A, g, S, L, rb + 3, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 4, RT>(A, g, S, L, rb + 4, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 5, RT>(A, g, S, L, rb + 5, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 6, RT>(A, g, S, L, rb + 6, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 7, RT>(A, g, S, L, rb + 7, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 8, RT>(A, g, S, L, rb + 8, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 9, RT>(A, g, S, L, rb + 9, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 10, RT>(A, g, S, L, rb + 10, r_start, r_end);
-        dpp_iter<T, COMP, CPL, K, 11, RT>(A, g, S, L, rb + 11, r_start, r_end);
+        R.WR[s] = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) R.ta[k] = R.tb[k] = R.tc[k] = R.cprev[k] = T(0);
+
+    // two load-only iterations: rows lo[1]-1 (row -1 mirrors row 0) and lo[1];
+    // level 1 takes the x-difference of row lo[1] at r = lo[1]
+    const int r_start = g.lo[1] - 2;
+    const int r_end = g.hi[K] + 2 * K - 2;
+    const int r0 = r_start - pmod(r_start, kPeriod);
+    for (int rb = r0; rb <= r_end; rb += kPeriod) {
+        lane_iter<T, COMP, CPL, K, 0, RT>(A, g, m, R, L, rb + 0, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 1, RT>(A, g, m, R, L, rb + 1, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 2, RT>(A, g, m, R, L, rb + 2, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 3, RT>(A, g, m, R, L, rb + 3, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 4, RT>(A, g, m, R, L, rb + 4, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 5, RT>(A, g, m, R, L, rb + 5, r_start, r_end);
     }
 }
 
@@ -348,7 +412,7 @@ hipError_t launch_dpp_typed(ggfv_ctx *ctx, const void *in, void *out, double dt)
     int rows = ctx->rows_per_strip;
     if (rows <= 0) {
         // one-wave workgroups: aim for about 16 per CU on 256 CUs, tall enough
-        // to amortise the 3K-row pipeline fill
+        // to amortise the 2K-row pipeline fill
         const long target = 4096;
         long per = ((long)ctx->ny * nbx + target - 1) / target;
         const int floor_rows = 8 * K;
