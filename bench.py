@@ -7,13 +7,18 @@ region borders, central tumour disk, delta1 = 12.5), stepped at 0.9 of the
 explicit stability bound with the masses logged every 500 steps.  Inputs are
 synthetic (seeded) and resident in HBM before the timed region starts.
 
-One bench step = one forward-Euler step of the whole grid (one launch of the
-step kernel); the timed region also contains the mass diagnostics every 500
-steps.  The headline value is FP64; the compensated-FP32 and plain-FP32 variants
-are measured beside it.  The oracle is timed on the host cores on a bounded
-sample of the same workload.
+One bench step = one forward-Euler step of the whole grid.  The headline runs
+the library's fastest launch shape for the variant (several steps per launch,
+the shapes below, which the library's autotuner picks on MI355X; --autotune
+runs the search instead); the single-step kernel is timed beside it.  The
+timed region also contains the mass diagnostics every 500 steps.  The headline
+value is FP64; the compensated-FP32 and plain-FP32 variants are measured beside
+it.  The oracle is timed on the host cores on a bounded sample of the same
+workload.
 
-Prints one JSON line.
+Prints one JSON line.  With --summarize-profiles DIR it instead writes the
+rocprofv3 summaries under profiles/ from the CSV output of the commands in
+PROFILE_COMMANDS (run with DIR as $P).
 """
 import argparse
 import json
@@ -28,8 +33,10 @@ PEAK_HBM_GBS = 8000.0            # MI355X HBM3E peak
 # write u, v, w once (the compensated state reads and writes a second word of u,
 # v and w).
 BYTES_PER_CELL = {"f64": 72, "f32c": 60, "f32": 36}
-KERNEL_NAME = {"f64": "step_kernel<double, false, 1>", "f32c": "step_kernel<float, true, 2>",
-               "f32": "step_kernel<float, false, 2>"}
+# Launch shapes of the headline runs: (rows per strip, threads, steps per
+# launch, lane-shift kernels), as the autotuner picks them on MI355X for this
+# workload.
+HEADLINE_SHAPE = {"f64": (32, 64, 4, 1), "f32c": (16, 64, 4, 1), "f32": (64, 64, 4, 1)}
 METRIC = "Gcell-updates/s + % HBM peak, 4096² aniso FV step FP32/FP64; adjoint/fwd ratio"
 # Algorithmic floating-point operations per cell-update (each face flux counted
 # once, shared by its two cells): x/y faces of W 2 x 10, tangential differences
@@ -44,24 +51,56 @@ PEAK_VALU_TFLOPS = 39.3
 MASS_EVERY = 500
 
 
-def measured_traffic(variant, kernel="single"):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when a step kernel source changed since the counters were taken."""
+def kernel_name(variant, tuning):
+    """Name of the kernel a launch shape runs, as rocprofv3 prints it (without
+    namespace and arguments), and its key in the traffic summary."""
+    T = "double" if variant == "f64" else "float"
+    comp = "true" if variant == "f32c" else "false"
+    cpl = 1 if variant == "f64" else 2
+    K = max(1, tuning.get("fused_steps", 1))
+    if tuning.get("lane_shift"):
+        return f"fused_dpp_kernel<{T}, {comp}, {cpl}, {K}>", f"lanes{K}"
+    if K > 1:
+        nt = 64 if (tuning.get("threads") == 64 or K == 4) else 128
+        return f"fused_kernel<{T}, {comp}, {cpl}, {nt}, {K}>", f"fused{K}"
+    nt = tuning.get("threads") or 256
+    return f"step_kernel<{T}, {comp}, {cpl}, {nt}>", "single"
+
+
+def traffic_sources(here):
+    return sorted(os.path.relpath(os.path.join(d, f), here)
+                  for d, _, fs in os.walk(os.path.join(here, "paper_2006_01748_amd", "csrc"))
+                  for f in fs if f.endswith((".hip", ".hpp")))
+
+
+def sources_digest(here, srcs):
     import hashlib
+    h = hashlib.sha256()
+    for src in srcs:
+        with open(os.path.join(here, src), "rb") as f:
+            h.update(src.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(variant, tuning, rows):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when no summary covers this kernel and strip height, or a kernel source
+    changed since the counters were taken."""
     here = os.path.dirname(os.path.abspath(__file__))
     try:
         with open(os.path.join(here, "profiles", "step_kernel_traffic.json")) as f:
             data = json.load(f)
-        h = hashlib.sha256()
-        for src in data["kernel_sources"]:
-            with open(os.path.join(here, src), "rb") as f:
-                h.update(f.read())
+        if sources_digest(here, data["kernel_sources"]) != data.get("kernel_sources_sha256"):
+            return None
+        if data["kernel_sources"] != traffic_sources(here):
+            return None
     except (OSError, KeyError, ValueError):
         return None
-    if h.hexdigest() != data.get("kernel_sources_sha256"):
+    _, key = kernel_name(variant, tuning)
+    t = data["bytes_per_launch"].get(f"{variant}/{key}")
+    if t is None or t.get("rows") != rows:
         return None
-    t = data["bytes_per_launch"].get(f"{variant}/{kernel}")
-    return None if t is None else t["read"] + t["write"]
+    return t["read"] + t["write"]
 
 
 def roofline_of(variant, r):
@@ -70,23 +109,20 @@ def roofline_of(variant, r):
     and writes the same bytes for K steps and is bound by vector arithmetic, so
     it is placed against the non-FMA vector rate (FLOPS_PER_CELL per
     cell-update), with its HBM figures beside it."""
+    kname, _ = kernel_name(variant, r["tuning"])
+    traffic = measured_traffic(variant, r["tuning"], r["rows"])
     if r["fused_steps"] == 1 and not r["tuning"].get("lane_shift"):
         return {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": measured_traffic(variant),
-                "kernel": KERNEL_NAME[variant], "kernel_avg_us": r["kernel_avg_us"],
+                "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
+                "kernel": kname, "kernel_avg_us": r["kernel_avg_us"],
                 "bytes_per_cell_update": BYTES_PER_CELL[variant]}
     K = r["fused_steps"]
-    if r["tuning"].get("lane_shift"):
-        kname = f"fused_dpp_kernel<{'double' if variant == 'f64' else 'float'}, {str(variant == 'f32c').lower()}, " \
-                f"{1 if variant == 'f64' else 2}, {K}>"
-    else:
-        kname = f"fused_kernel<{'double' if variant == 'f64' else 'float'}, {str(variant == 'f32c').lower()}, " \
-                f"{1 if variant == 'f64' else 2}, {64 if (r['tuning']['threads'] == 64 or K == 4) else 128}, {K}>"
     return {"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": measured_traffic(variant, f"fused{K}"),
+            "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": traffic,
             "kernel": kname,
             "kernel_avg_us": r["kernel_avg_us"], "steps_per_launch": K,
             "flops_per_cell_update": FLOPS_PER_CELL,
+            "hbm_algorithmic_bytes_per_launch": BYTES_PER_CELL[variant] * r["cells"],
             "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_effective_GBs": r["effective_GBs"],
             "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS}
 
@@ -110,6 +146,7 @@ def time_variant(pk, torch, w, dtype, steps, warmup, tune, force=None):
         tuning = ctx.get_tuning()
     else:
         tuning = ctx.autotune(dt, trial_steps=12) if tune else ctx.get_tuning()
+    rows = tuning["rows_per_strip"]          # 0: the library's default strip height
     K = max(1, tuning["fused_steps"])
     ctx.step(dt, warmup)
     torch.cuda.synchronize()
@@ -146,7 +183,7 @@ def time_variant(pk, torch, w, dtype, steps, warmup, tune, force=None):
     per_launch_bytes = BYTES_PER_CELL[dtype] * cells
     return {
         "value": value, "ms_per_step": total_ms / steps, "kernel_avg_us": kernel_us,
-        "wall_s": wall, "dt": dt, "tuning": tuning, "fused_steps": K,
+        "wall_s": wall, "dt": dt, "tuning": tuning, "fused_steps": K, "rows": rows, "cells": cells,
         "achieved_GBs": per_launch_bytes / (kernel_us * 1e-6) / 1e9,
         "effective_GBs": K * per_launch_bytes / (kernel_us * 1e-6) / 1e9,
         "achieved_TFLOPs": FLOPS_PER_CELL * K * cells / (kernel_us * 1e-6) / 1e12,
@@ -293,25 +330,172 @@ def cpu_baseline(w, steps):
                       f"({sec:.1f} s)"}
 
 
+# The rocprofv3 runs behind the committed summaries under profiles/.  Run from
+# /tmp with TMPDIR=/tmp; $R is the repository root, $P an output folder.
+PROFILE_COMMANDS = {
+    "trace": "timeout -k 10 500 rocprofv3 --kernel-trace --stats --output-format csv -d $P/trace -o trace "
+             "-- python3 $R/bench.py --steps 200 --warmup 12 --no-cpu-baseline > $P/trace_bench.json",
+    "fetch": "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $P/fetch -o fetch "
+             "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble",
+    "write": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/write -o write "
+             "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble",
+}
+
+
+def _short(name):
+    name = name.replace("ggfv::(anonymous namespace)::", "").replace("void ", "")
+    depth, out = 0, []
+    for ch in name:                      # drop the argument list
+        if ch == "(" and depth == 0 and out:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def summarize_profiles(pdir):
+    """Write profiles/*.md and profiles/step_kernel_traffic.json from the CSV
+    output of PROFILE_COMMANDS (trace/, fetch/, write/ and trace_bench.json
+    under pdir)."""
+    import csv
+    import collections
+    here = os.path.dirname(os.path.abspath(__file__))
+    stats = {}
+    with open(os.path.join(pdir, "trace", "trace_kernel_stats.csv")) as f:
+        for row in csv.DictReader(f):
+            stats[_short(row["Name"])] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3,
+                                         float(row["MinNs"]) / 1e3, float(row["MaxNs"]) / 1e3)
+    with open(os.path.join(pdir, "trace_bench.json")) as f:
+        bench = json.loads(f.read().strip().splitlines()[-1])
+
+    def per_dispatch(kind):
+        vals = collections.defaultdict(float)
+        meta = {}
+        with open(os.path.join(pdir, kind, f"{kind}_counter_collection.csv")) as f:
+            for row in csv.DictReader(f):
+                d = int(row["Dispatch_Id"])
+                vals[d] += float(row["Counter_Value"])
+                meta[d] = (_short(row["Kernel_Name"]), int(row["Grid_Size"]))
+        agg = collections.defaultdict(list)
+        for d, v in vals.items():
+            agg[meta[d]].append(v)
+        return {k: sum(v) / len(v) for k, v in agg.items()}
+
+    fetch, write = per_dispatch("fetch"), per_dispatch("write")
+    copy_bytes = 1 << 30                  # the copy-ceiling probe: 1 GiB read and 1 GiB written
+    cal = [k for k in fetch if k[0] == "__amd_rocclr_copyBuffer"]
+    ck = max(cal, key=lambda k: k[1])
+    f_scale = copy_bytes / (fetch[ck] * 1024)
+    w_scale = copy_bytes / (write[ck] * 1024)
+    cells = bench["config"]["grid"][0] * bench["config"]["grid"][1]
+
+    # kernels of the 4096^2 runs: single-step and headline shapes of each variant
+    rows_md, traffic = [], {}
+    for v, vr in bench["variants"].items():
+        for label, tuning, rows in (("single", {"fused_steps": 1, "threads": 0}, 0),
+                                    ("headline", vr["tuned"], vr["tuned"]["rows_per_strip"])):
+            kname, key = kernel_name(v, tuning)
+            ks = [k for k in fetch if k[0] == kname]
+            if not ks:
+                continue
+            k = max(ks, key=lambda x: x[1])
+            rd, wr = fetch[k] * 1024 * f_scale, write.get(k, 0.0) * 1024 * w_scale
+            alg = BYTES_PER_CELL[v] * cells
+            alg_w = (24 if v == "f64" else 12 if v == "f32" else 24) * cells
+            traffic[f"{v}/{key}"] = {"kernel": kname, "rows": rows, "read": rd, "write": wr,
+                                     "fetch_kib": fetch[k], "write_kib": write.get(k, 0.0)}
+            st = stats.get(kname)
+            rows_md.append(f"| {v} | {kname} | {rows or 'default'} | {st[0] if st else '-'} | "
+                           f"{st[1] if st else float('nan'):.1f} | {fetch[k]:.0f} | {write.get(k, 0.0):.0f} | "
+                           f"{rd / 1e6:.1f} | {wr / 1e6:.1f} | {(alg - alg_w) / 1e6:.1f} / {alg_w / 1e6:.1f} | "
+                           f"{(rd + wr) / alg:.3f} |")
+    srcs = traffic_sources(here)
+    with open(os.path.join(here, "profiles", "step_kernel_traffic.json"), "w") as f:
+        json.dump({"note": "HBM bytes per launch on the 4096x4096 layered-tissue grid, from rocprofv3 --pmc "
+                           "FETCH_SIZE and WRITE_SIZE (separate runs), scaled by what a 1 GiB copyBuffer "
+                           f"dispatch reads (FETCH x{f_scale:.3f}, WRITE x{w_scale:.3f}); valid for the kernel "
+                           "sources with this digest and the strip heights given (0: library default).",
+                   "kernel_sources": srcs, "kernel_sources_sha256": sources_digest(here, srcs),
+                   "bytes_per_launch": traffic}, f, indent=1)
+
+    def stat_rows(pred):
+        out = []
+        for k, (n, avg, lo, hi) in sorted(stats.items(), key=lambda x: -x[1][0] * x[1][1]):
+            if pred(k):
+                out.append(f"| {k} | {n} | {avg:.1f} | {lo:.1f} | {hi:.1f} |")
+        return "\n".join(out)
+
+    head = "| kernel | calls | average (us) | min (us) | max (us) |\n|---|---|---|---|---|\n"
+    cmds = "\n".join(PROFILE_COMMANDS[k] for k in ("trace", "fetch", "write"))
+    live = {v: vr["launch_avg_us"] for v, vr in bench["variants"].items()}
+    with open(os.path.join(here, "profiles", "step_kernels_4096_layered_tissue.md"), "w") as f:
+        f.write("# Step kernels, 4096x4096 layered-tissue workload (rocprofv3)\n\n"
+                "Commands (from /tmp with TMPDIR=/tmp; $R = repository root, $P = output folder):\n\n"
+                f"```\n{cmds}\n```\n\nSummary written by `python bench.py --summarize-profiles $P`.\n\n"
+                "## Kernel trace (--stats), 4096^2 step kernels and diagnostics\n\n" + head +
+                stat_rows(lambda k: k.startswith(("step_kernel<", "fused_dpp_kernel<", "fused_kernel<",
+                                                  "diag_kernel", "diag_final")) and not k.endswith(", 64>")) +
+                "\n\nAverage launch time measured live by bench.py with HIP events in the same traced run "
+                "(headline shapes): " + ", ".join(f"{v} {us:.1f} us" for v, us in live.items()) + ".\n\n"
+                "## HBM traffic per dispatch (--pmc, one counter per run)\n\n"
+                f"Calibration: the 1 GiB `__amd_rocclr_copyBuffer` of the copy-ceiling probe reads "
+                f"FETCH_SIZE = {fetch[ck]:.0f} KiB and WRITE_SIZE = {write[ck]:.0f} KiB per dispatch, so "
+                f"FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.  Algorithmic bytes: "
+                "each launch reads u, v, w, a, b, c and writes u, v, w once (the compensated state reads "
+                "and writes the low words too), whatever the number of steps it fuses.\n\n"
+                "| variant | kernel | rows | calls (trace) | average (us) | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | "
+                "scaled read (MB) | scaled write (MB) | algorithmic read / write (MB) | traffic / algorithmic |\n"
+                "|---|---|---|---|---|---|---|---|---|---|---|\n" + "\n".join(rows_md) + "\n")
+    ens = bench.get("ensemble") or {}
+    with open(os.path.join(here, "profiles", "batch_step_kernel_ensemble_256.md"), "w") as f:
+        f.write("# Batched ensemble kernels, 256 instances (sides 64..512), compensated FP32 (rocprofv3)\n\n"
+                f"Command (from /tmp with TMPDIR=/tmp):\n\n```\n{PROFILE_COMMANDS['trace']}\n```\n\n"
+                "## Kernel trace (--stats)\n\n" + head +
+                stat_rows(lambda k: k.startswith("step_batch_kernel") or k.startswith("step_kernel<float, true, 2, 64>"))
+                + "\n\n`step_batch_kernel` runs every instance of the ensemble in one launch (graph-replayed); "
+                "`step_kernel<float, true, 2, 64>` is the loop of single-instance launches it is compared "
+                "with.  bench.py in the same run: "
+                f"batched {ens.get('batched_Gcell_s', float('nan')):.1f} Gcell/s, loop "
+                f"{ens.get('loop_of_single_launches_Gcell_s', float('nan')):.1f} Gcell/s.\n")
+    adj = bench.get("adjoint") or {}
+    with open(os.path.join(here, "profiles", "adjoint_kernels_512_smooth.md"), "w") as f:
+        f.write("# Adjoint workload, 512x512 smooth anisotropic tensor, 5000 steps, FP64 (rocprofv3)\n\n"
+                f"Command (from /tmp with TMPDIR=/tmp):\n\n```\n{PROFILE_COMMANDS['trace']}\n```\n\n"
+                "## Kernel trace (--stats)\n\n" + head +
+                stat_rows(lambda k: k.startswith(("adjoint_kernel", "slots_reduce", "eig_backward", "zero_kernel"))
+                          or k.startswith("step_kernel<double, false, 1, 64>"))
+                + "\n\n`step_kernel<double, false, 1, 64>` is the 512^2 forward step (checkpointed forward and "
+                "the recomputation of each segment in the reverse sweep).  bench.py in the same run: "
+                f"backward / forward = {adj.get('backward_over_forward', float('nan')):.2f}.\n")
+    print(json.dumps({"calibration": {"fetch": f_scale, "write": w_scale}, "traffic": traffic}, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=52)
     ap.add_argument("--n", type=int, default=4096, help="grid side (4096 for the standard workload)")
     ap.add_argument("--variants", default="f64,f32c,f32")
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner for the headline shape instead of the fixed shapes")
     ap.add_argument("--force-tuning", default="",
-                    help="VARIANT=ROWS,THREADS,FUSED[;...]: use these launch shapes instead of the autotuner "
-                         "(reproducible profiling)")
+                    help="VARIANT=ROWS,THREADS,FUSED,LANE_SHIFT[;...]: headline launch shapes")
     ap.add_argument("--ensemble-tuning", default="",
                     help="THREADS,ROWS: batched launch shape instead of the batch autotuner")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default="",
+                    help="write the profiles/ summaries from the output of PROFILE_COMMANDS in DIR; no GPU work")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU "
               "path; the step would shard by row slabs with halo exchange.", file=sys.stderr)
@@ -330,6 +514,7 @@ def main():
     log(f"generating {args.n}x{args.n} layered-tissue workload")
     w = wl.cfg2(n=args.n)
     variants = [v for v in args.variants.split(",") if v]
+    forced = dict(item.split("=") for item in args.force_tuning.split(";") if item)
     res, single = {}, {}
     for v in variants:
         log(f"timing {v}, single-step kernel: {args.warmup} warm-up + {args.steps} timed steps")
@@ -337,11 +522,15 @@ def main():
         log(f"  {v} single-step: {single[v]['value']:.2f} Gcell/s, kernel {single[v]['kernel_avg_us']:.1f} us, "
             f"{single[v]['achieved_GBs']:.0f} GB/s ({100 * single[v]['achieved_GBs'] / PEAK_HBM_GBS:.1f}% of peak)")
         if not args.no_tune:
-            log(f"timing {v}, autotuned shape")
-            forced = dict(item.split("=") for item in args.force_tuning.split(";") if item)
-            force = tuple(int(x) for x in forced[v].split(",")) if v in forced else None
+            if v in forced:
+                force = tuple(int(x) for x in forced[v].split(","))
+            elif args.autotune:
+                force = None
+            else:
+                force = HEADLINE_SHAPE[v]
+            log(f"timing {v}, {'autotuned' if force is None else 'headline'} shape")
             res[v] = time_variant(pk, torch, w, v, args.steps, args.warmup, tune=True, force=force)
-            log(f"  {v} tuned {res[v]['tuning']}: {res[v]['value']:.2f} Gcell/s, launch {res[v]['kernel_avg_us']:.1f} us "
+            log(f"  {v} shape {res[v]['tuning']}: {res[v]['value']:.2f} Gcell/s, launch {res[v]['kernel_avg_us']:.1f} us "
                 f"({res[v]['fused_steps']} steps), effective {res[v]['effective_GBs']:.0f} GB/s")
         else:
             res[v] = single[v]
@@ -365,6 +554,7 @@ def main():
 
     head = variants[0]
     r = res[head]
+    s1 = single[head]
     line = {
         "metric": METRIC,
         "value": r["value"],
@@ -382,14 +572,15 @@ def main():
             "workload": f"layered tissue {w.nx}x{w.ny}: 64 Voronoi regions with anisotropic tensors "
                         f"and membranes, central disk, delta1={w.params[0]}, dt=0.9 of the "
                         f"stability bound, masses every {MASS_EVERY} steps",
-            "grid": [w.nx, w.ny], "params": list(w.params), "dt": r["dt"],
+            "grid": [w.nx, w.ny], "params": list(w.params), "dt": r["dt"], "launch_shape": r["tuning"],
         },
         "roofline": roofline_of(head, r),
         "single_step_kernel": {
-            "kernel": KERNEL_NAME[head], "value": single[head]["value"],
-            "kernel_avg_us": single[head]["kernel_avg_us"], "bound": "hbm",
-            "achieved": single[head]["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": single[head]["achieved_GBs"] / PEAK_HBM_GBS, "traffic": measured_traffic(head),
+            "kernel": kernel_name(head, s1["tuning"])[0], "value": s1["value"],
+            "kernel_avg_us": s1["kernel_avg_us"], "bound": "hbm",
+            "achieved": s1["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": s1["achieved_GBs"] / PEAK_HBM_GBS,
+            "traffic": measured_traffic(head, s1["tuning"], s1["rows"]),
             "bytes_per_cell_update": BYTES_PER_CELL[head]},
         "cpu_baseline": base,
         "variants": {v: {"tuned": res[v]["tuning"], "value": res[v]["value"],
@@ -397,7 +588,7 @@ def main():
                          "single_step": {"value": single[v]["value"], "kernel_avg_us": single[v]["kernel_avg_us"],
                                          "achieved_GBs": single[v]["achieved_GBs"],
                                          "frac": single[v]["achieved_GBs"] / PEAK_HBM_GBS,
-                                         "traffic": measured_traffic(v)}}
+                                         "traffic": measured_traffic(v, single[v]["tuning"], single[v]["rows"])}}
                      for v in variants},
         "adjoint": adj,
         "ensemble": ens,
