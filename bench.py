@@ -260,9 +260,13 @@ def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50, force=None):
         c.set_state(w.u0, w.v0, w.w0)
         dts.append(c.stable_dt(w.safety))
         b.set_dt(i, dts[-1])
-    tuned = b.autotune(trial_steps=10) if force is None else {"threads": force[0], "rows_per_strip": force[1]}
-    b.set_tuning(threads=tuned["threads"], rows_per_strip=tuned["rows_per_strip"], graph_steps=50)
-    b.run(50)
+    if force is None:
+        tuned = b.autotune(trial_steps=12)
+    else:
+        tuned = {"threads": force[0], "rows_per_strip": force[1], "fused_steps": force[2] if len(force) > 2 else 1}
+    b.set_tuning(threads=tuned["threads"], rows_per_strip=tuned["rows_per_strip"], graph_steps=48,
+                 fused_steps=tuned["fused_steps"])
+    b.run(48)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -489,7 +493,7 @@ def main():
     ap.add_argument("--force-tuning", default="",
                     help="VARIANT=ROWS,THREADS,FUSED,LANE_SHIFT[;...]: headline launch shapes")
     ap.add_argument("--ensemble-tuning", default="",
-                    help="THREADS,ROWS: batched launch shape instead of the batch autotuner")
+                    help="THREADS,ROWS[,FUSED]: batched launch shape instead of the batch autotuner")
     ap.add_argument("--summarize-profiles", metavar="DIR", default="",
                     help="write the profiles/ summaries from the output of PROFILE_COMMANDS in DIR; no GPU work")
     args = ap.parse_args()

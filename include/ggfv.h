@@ -254,8 +254,9 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best);
 /* ---- ensembles ---------------------------------------------------------------
  *
  * A batch holds n independent instances (each its own grid size, parameters,
- * tensor, state and dt) that advance together: one launch of the batched step
- * kernel moves every instance by one step of eq. (3), and runs of many steps are
+ * tensor, state and dt) that advance together: one launch of a batched kernel
+ * moves every instance by one step of eq. (3) (single-step kernel) or by K steps
+ * (lane-shift kernel, ggfv_batch_set_fused_steps), and runs of many steps are
  * captured once into a HIP graph and replayed.  Each instance is an ordinary
  * context owned by the batch: set its parameters, tensor and state, read its
  * state and diagnostics with the ggfv_* calls above through
@@ -278,13 +279,24 @@ int ggfv_batch_set_dt(ggfv_batch *b, int i, double dt);
 /* Advance every instance by nsteps steps (each with its own dt).  Enqueues and
  * returns.  ESTATE if an instance lacks state, tensor, parameters or dt. */
 int ggfv_batch_run(ggfv_batch *b, long long nsteps);
-/* Launch shape of the batched kernel: workgroup width (64 or 256), strip height
- * (0 = 16 rows, or per instance via ggfv_set_tuning on the instance), and the
- * number of steps captured per graph (0 = no graph: one launch per step).
- * Results are identical for every shape. */
+/* Launch shape of the batched kernels: workgroup width of the single-step kernel
+ * (64 or 256), strip height (0 = 16 rows, or per instance via ggfv_set_tuning on
+ * the instance), and about how many steps a graph holds (it holds an even number
+ * of launches, at least two; 0 = no graph).  Results are identical for every
+ * shape. */
 int ggfv_batch_set_tuning(ggfv_batch *b, int threads, int rows_per_strip, int graph_steps);
-/* Time trial_steps batched steps for each width (64, 256) and strip height
- * (4..64), keep the fastest and report it; instance states, times and step
+/* Steps per launch: 1 = the single-step kernel; 2..4 = the lane-shift kernel with
+ * that many time levels per launch (a run whose step count is not a multiple
+ * finishes with single steps).  Results are identical bit for bit.  EINVAL
+ * outside 1..4. */
+int ggfv_batch_set_fused_steps(ggfv_batch *b, int fused_steps);
+/* The current launch shape (any output pointer may be NULL). */
+int ggfv_batch_get_tuning(const ggfv_batch *b, int *threads, int *rows_per_strip, int *graph_steps,
+                          int *fused_steps);
+/* Time about trial_steps batched steps for each candidate (single-step kernel at
+ * widths 64 and 256, lane-shift kernel at 2..4 steps per launch) and strip height
+ * (4..64), keep the fastest per step and report its width and height (the steps
+ * per launch through ggfv_batch_get_tuning); instance states, times and step
  * counts are restored afterwards.  Synchronizes. */
 int ggfv_batch_autotune(ggfv_batch *b, int trial_steps, int *best_threads, int *best_rows);
 const char *ggfv_batch_last_error(const ggfv_batch *b);

@@ -55,6 +55,9 @@ _SIGNATURES = [
     ("ggfv_batch_run", _c.c_int, [_VP, _c.c_longlong]),
     ("ggfv_batch_set_tuning", _c.c_int, [_VP, _c.c_int, _c.c_int, _c.c_int]),
     ("ggfv_batch_autotune", _c.c_int, [_VP, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
+    ("ggfv_batch_set_fused_steps", _c.c_int, [_VP, _c.c_int]),
+    ("ggfv_batch_get_tuning", _c.c_int, [_VP, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int),
+                                         _c.POINTER(_c.c_int)]),
     ("ggfv_batch_last_error", _c.c_char_p, [_VP]),
     ("ggfv_last_error", _c.c_char_p, [_VP]),
     ("ggfv_status_string", _c.c_char_p, [_c.c_int]),
@@ -416,13 +419,21 @@ class Batch:
     def run(self, nsteps):
         self._check(self._lib.ggfv_batch_run(self._h, int(nsteps)))
 
-    def set_tuning(self, threads=64, rows_per_strip=0, graph_steps=50):
+    def set_tuning(self, threads=64, rows_per_strip=0, graph_steps=50, fused_steps=None):
         self._check(self._lib.ggfv_batch_set_tuning(self._h, int(threads), int(rows_per_strip), int(graph_steps)))
+        if fused_steps is not None:
+            self._check(self._lib.ggfv_batch_set_fused_steps(self._h, int(fused_steps)))
+
+    def get_tuning(self):
+        v = [ctypes.c_int() for _ in range(4)]
+        self._check(self._lib.ggfv_batch_get_tuning(self._h, *(ctypes.byref(x) for x in v)))
+        return {"threads": v[0].value, "rows_per_strip": v[1].value, "graph_steps": v[2].value,
+                "fused_steps": v[3].value}
 
     def autotune(self, trial_steps=10):
         t, r = ctypes.c_int(), ctypes.c_int()
         self._check(self._lib.ggfv_batch_autotune(self._h, int(trial_steps), ctypes.byref(t), ctypes.byref(r)))
-        return {"threads": t.value, "rows_per_strip": r.value}
+        return {"threads": t.value, "rows_per_strip": r.value, "fused_steps": self.get_tuning()["fused_steps"]}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,13 +1,14 @@
 // ggfv_batch.hip -- ensembles of independent instances stepped together.
 //
 // Every instance is an ordinary context (own grid, tensor, parameters, state,
-// dt).  One launch of the batched step kernel advances all of them by one step:
-// the work items are the strips of all instances (instance i owns the items
-// [prefix[i], prefix[i+1])), and each instance's step description (planes, sizes,
-// coefficients, dt, strip height) is read from a device array.  Two description
-// arrays alternate, because each step swaps every instance's input and output
-// planes.  Runs of many steps are captured once into a HIP graph of
-// `graph_steps` launches (an even number, so the planes are back in place after
+// dt).  One launch of a batched kernel advances all of them: the single-step
+// kernel by one step, the lane-shift kernel by `fused` steps.  The work items
+// are the strips of all instances (instance i owns the items [prefix[i],
+// prefix[i+1]) of the kernel's own work table), and each instance's step
+// description (planes, sizes, coefficients, dt, strip height) is read from a
+// device array.  Two description arrays alternate, because each launch swaps
+// every instance's input and output planes.  Runs are captured once into a HIP
+// graph of an even number of launches (so the planes are back in place after
 // every replay) and replayed.  Only kernel nodes are captured.
 
 #include <cmath>
@@ -30,21 +31,24 @@ struct ggfv_batch {
     bool own_stream = false;
     std::vector<ggfv_ctx *> inst;
     std::vector<double> dt;
-    int threads = 64;
+    int threads = 64;              // width of the single-step kernel
+    int fused = 1;                 // 1: single-step kernel; 2..4: lane-shift kernel, steps per launch
     int rows = 0;                  // 0: 16 rows unless the instance fixes its own
     int graph_steps = 50;
-    // host images and device copies of the two description arrays and the prefix
+    // host images and device copies of the two description arrays and of the
+    // work tables of the single-step (index 0) and lane-shift (index 1) kernels
     std::vector<unsigned char> hdesc[2];
-    std::vector<int> hprefix;
+    std::vector<int> hprefix[2];
     void *ddesc[2] = {nullptr, nullptr};
-    int *dprefix = nullptr;
+    int *dprefix = nullptr;        // 2 * (n + 1) ints: both work tables
     size_t desc_cap = 0;
     int prefix_cap = 0;
     bool dirty = true;
     std::vector<int> cur_at_build;
-    int items = 0;
+    int items[2] = {0, 0};
     hipGraphExec_t exec = nullptr;
-    int exec_steps = 0;
+    int exec_launches = 0;         // launches in the graph
+    int exec_fused = 0;            // steps per launch in the graph
     std::string err;
 };
 
@@ -85,7 +89,8 @@ void drop_graph(ggfv_batch *b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
-    b->exec_steps = 0;
+    b->exec_launches = 0;
+    b->exec_fused = 0;
 }
 
 // (Re)build both description arrays and the prefix for the instances' current
@@ -96,25 +101,31 @@ int build(ggfv_batch *b)
     for (int i = 0; same && i < b->n; ++i) same = b->cur_at_build[i] == b->inst[i]->cur;
     if (same) return GGFV_OK;
     const size_t sz = step_args_bytes(b->dtype);
-    const int cols = step_columns_per_group(b->dtype, b->threads);
+    // columns per workgroup of the single-step and of the lane-shift kernel
+    const int cols[2] = {step_columns_per_group(b->dtype, b->threads),
+                         lane_shift_columns_per_group(b->dtype, b->fused)};
     for (int p = 0; p < 2; ++p) b->hdesc[p].assign(sz * b->n, 0);
-    b->hprefix.assign(b->n + 1, 0);
+    for (int k = 0; k < 2; ++k) b->hprefix[k].assign(b->n + 1, 0);
     b->cur_at_build.assign(b->n, 0);
-    long long items = 0;
+    long long items[2] = {0, 0};
     for (int i = 0; i < b->n; ++i) {
         ggfv_ctx *c = b->inst[i];
         const int rows = rows_of(b, c);
         const double dt = b->dtype == GGFV_F64 ? b->dt[i] : (double)(float)b->dt[i];
         fill_step_args(c, c->state[c->cur], c->state[1 - c->cur], dt, rows, &b->hdesc[0][sz * i]);
         fill_step_args(c, c->state[1 - c->cur], c->state[c->cur], dt, rows, &b->hdesc[1][sz * i]);
-        const long long strips = (long long)((c->nx + cols - 1) / cols) * ((c->ny + rows - 1) / rows);
-        b->hprefix[i] = (int)items;
-        items += strips;
+        for (int k = 0; k < 2; ++k) {
+            const long long strips = (long long)((c->nx + cols[k] - 1) / cols[k]) * ((c->ny + rows - 1) / rows);
+            b->hprefix[k][i] = (int)items[k];
+            items[k] += strips;
+        }
         b->cur_at_build[i] = c->cur;
     }
-    if (items > (1LL << 30)) return bfail(b, GGFV_EINVAL, "too many work items (%lld)", items);
-    b->hprefix[b->n] = (int)items;
-    b->items = (int)items;
+    for (int k = 0; k < 2; ++k) {
+        if (items[k] > (1LL << 30)) return bfail(b, GGFV_EINVAL, "too many work items (%lld)", items[k]);
+        b->hprefix[k][b->n] = (int)items[k];
+        b->items[k] = (int)items[k];
+    }
     if (b->desc_cap < sz * b->n || b->prefix_cap < b->n + 1) {
         (void)hipStreamSynchronize(b->stream);
         drop_graph(b);
@@ -124,7 +135,7 @@ int build(ggfv_batch *b)
         b->ddesc[0] = b->ddesc[1] = nullptr;
         b->dprefix = nullptr;
         if (hipMalloc(&b->ddesc[0], sz * b->n) != hipSuccess || hipMalloc(&b->ddesc[1], sz * b->n) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&b->dprefix), sizeof(int) * (b->n + 1)) != hipSuccess)
+            hipMalloc(reinterpret_cast<void **>(&b->dprefix), 2 * sizeof(int) * (b->n + 1)) != hipSuccess)
             return bfail(b, GGFV_ENOMEM, "cannot allocate batch descriptions");
         b->desc_cap = sz * b->n;
         b->prefix_cap = b->n + 1;
@@ -133,21 +144,26 @@ int build(ggfv_batch *b)
     GGFV_BHIP(b, hipStreamSynchronize(b->stream));
     for (int p = 0; p < 2; ++p)
         GGFV_BHIP(b, hipMemcpy(b->ddesc[p], b->hdesc[p].data(), sz * b->n, hipMemcpyHostToDevice));
-    GGFV_BHIP(b, hipMemcpy(b->dprefix, b->hprefix.data(), sizeof(int) * (b->n + 1), hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k)
+        GGFV_BHIP(b, hipMemcpy(b->dprefix + k * (b->n + 1), b->hprefix[k].data(), sizeof(int) * (b->n + 1),
+                               hipMemcpyHostToDevice));
     b->dirty = false;
     return GGFV_OK;
 }
 
-BatchLaunch launch_of(const ggfv_batch *b, int parity)
+// One launch: the lane-shift kernel (lanes) or the single-step kernel, reading
+// description array `parity`.
+hipError_t launch_one(const ggfv_batch *b, bool lanes, int parity)
 {
     BatchLaunch L;
     L.dtype = b->dtype;
     L.threads = b->threads;
+    L.fused = b->fused;
     L.n = b->n;
-    L.items = b->items;
+    L.items = b->items[lanes ? 1 : 0];
     L.desc = b->ddesc[parity & 1];
-    L.prefix = b->dprefix;
-    return L;
+    L.prefix = b->dprefix + (lanes ? b->n + 1 : 0);
+    return lanes ? launch_step_batch_dpp(L, b->stream) : launch_step_batch(L, b->stream);
 }
 
 int ready(ggfv_batch *b)
@@ -161,19 +177,27 @@ int ready(ggfv_batch *b)
     return GGFV_OK;
 }
 
-// Record nsteps batched launches (parity alternates from 0) on the stream.
-int enqueue(ggfv_batch *b, long long nsteps)
+// Record launches for nsteps steps on the stream: fused launches while at least
+// `fused` steps remain, then single steps.  Parity alternates per launch from
+// `parity`; the number of launches is added to *launches.
+int enqueue(ggfv_batch *b, long long nsteps, long long *launches)
 {
-    for (long long s = 0; s < nsteps; ++s) GGFV_BHIP(b, launch_step_batch(launch_of(b, (int)(s & 1)), b->stream));
+    const int K = b->fused;
+    long long nl = *launches;
+    if (K > 1)
+        for (; nsteps >= K; nsteps -= K, ++nl) GGFV_BHIP(b, launch_one(b, true, (int)(nl & 1)));
+    for (; nsteps > 0; --nsteps, ++nl) GGFV_BHIP(b, launch_one(b, false, (int)(nl & 1)));
+    *launches = nl;
     return GGFV_OK;
 }
 
-void advance(ggfv_batch *b, long long nsteps)
+// nsteps steps done in `launches` launches (each swapped the planes once).
+void advance(ggfv_batch *b, long long nsteps, long long launches)
 {
     for (int i = 0; i < b->n; ++i) {
         ggfv_ctx *c = b->inst[i];
         const double dt = b->dtype == GGFV_F64 ? b->dt[i] : (double)(float)b->dt[i];
-        if (nsteps & 1) c->cur ^= 1;
+        if (launches & 1) c->cur ^= 1;
         c->t += dt * (double)nsteps;
         c->steps += nsteps;
         c->last_dt = dt;
@@ -275,7 +299,31 @@ int ggfv_batch_set_tuning(ggfv_batch *b, int threads, int rows_per_strip, int gr
     }
     b->threads = threads;
     b->rows = rows_per_strip;
-    b->graph_steps = graph_steps + (graph_steps & 1);   // even: planes return in place
+    b->graph_steps = graph_steps;
+    drop_graph(b);
+    return GGFV_OK;
+}
+
+int ggfv_batch_set_fused_steps(ggfv_batch *b, int fused_steps)
+{
+    if (!b) return GGFV_EINVAL;
+    if (fused_steps < 1 || fused_steps > 4) return bfail(b, GGFV_EINVAL, "fused_steps must be 1..4");
+    if (fused_steps != b->fused) {
+        b->dirty = true;
+        drop_graph(b);
+    }
+    b->fused = fused_steps;
+    return GGFV_OK;
+}
+
+int ggfv_batch_get_tuning(const ggfv_batch *b, int *threads, int *rows_per_strip, int *graph_steps,
+                          int *fused_steps)
+{
+    if (!b) return GGFV_EINVAL;
+    if (threads) *threads = b->threads;
+    if (rows_per_strip) *rows_per_strip = b->rows;
+    if (graph_steps) *graph_steps = b->graph_steps;
+    if (fused_steps) *fused_steps = b->fused;
     return GGFV_OK;
 }
 
@@ -292,14 +340,18 @@ int ggfv_batch_run(ggfv_batch *b, long long nsteps)
     const bool was_dirty = b->dirty;
     if ((rc = build(b))) return rc;
     if (was_dirty) drop_graph(b);
-    long long done = 0;
-    const int G = b->graph_steps;
-    if (G > 0 && nsteps >= G) {
-        if (!b->exec || b->exec_steps != G) {
+    long long done = 0, launches = 0;
+    const int K = b->fused;
+    // the graph: an even number of launches of K steps covering about graph_steps steps
+    long long GL = b->graph_steps / K;
+    GL += GL & 1;
+    if (b->graph_steps > 0 && GL > 0 && nsteps >= GL * K) {
+        if (!b->exec || b->exec_launches != GL || b->exec_fused != K) {
             drop_graph(b);
             hipGraph_t graph = nullptr;
             GGFV_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            int erc = enqueue(b, G);
+            long long nl = 0;
+            int erc = enqueue(b, GL * K, &nl);
             hipError_t ee = hipStreamEndCapture(b->stream, &graph);
             if (erc) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -312,13 +364,15 @@ int ggfv_batch_run(ggfv_batch *b, long long nsteps)
                 b->exec = nullptr;
                 return bfail(b, GGFV_EHIP, "graph instantiation failed: %s", hipGetErrorString(ie));
             }
-            b->exec_steps = G;
+            b->exec_launches = (int)GL;
+            b->exec_fused = K;
         }
-        for (; done + G <= nsteps; done += G) GGFV_BHIP(b, hipGraphLaunch(b->exec, b->stream));
+        for (; done + GL * K <= nsteps; done += GL * K, launches += GL)
+            GGFV_BHIP(b, hipGraphLaunch(b->exec, b->stream));
     }
-    if ((rc = enqueue(b, nsteps - done))) return rc;
-    advance(b, nsteps);
-    if (nsteps & 1) b->dirty = true;     // planes swapped: descriptions rebuilt next run
+    if ((rc = enqueue(b, nsteps - done, &launches))) return rc;
+    advance(b, nsteps, launches);
+    if (launches & 1) b->dirty = true;     // planes swapped: descriptions rebuilt next run
     if (prev >= 0) (void)hipSetDevice(prev);
     return GGFV_OK;
 }
@@ -349,36 +403,45 @@ int ggfv_batch_autotune(ggfv_batch *b, int trial_steps, int *best_threads, int *
         s0[i] = c->steps;
         last0[i] = c->last_dt;
     }
-    const int thr0 = b->threads, rows0 = b->rows;
+    const int thr0 = b->threads, rows0 = b->rows, fus0 = b->fused;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     float best_ms = -1.0f;
-    int bt = thr0, br = rows0;
-    const int widths[2] = {64, 256};
+    int bt = thr0, br = rows0, bk = fus0;
+    // candidates: the single-step kernel at widths 64 and 256 (K = 1) and the
+    // lane-shift kernel at K = 2..4, each over the strip heights
+    const int kinds[5][2] = {{1, 64}, {1, 256}, {2, 64}, {3, 64}, {4, 64}};
     const int heights[5] = {4, 8, 16, 32, 64};
-    for (int w : widths)
+    for (const auto &kd : kinds) {
         for (int h : heights) {
-            b->threads = w;
+            b->fused = kd[0];
+            b->threads = kd[1];
             b->rows = h;
             b->dirty = true;
             drop_graph(b);
             if ((rc = build(b))) break;
-            // even counts keep the planes in place
-            if ((rc = enqueue(b, 2))) break;
+            long long nl = 0;
+            // warm-up, then an even number of launches keeps the planes in place
+            if ((rc = enqueue(b, 2LL * b->fused, &nl))) break;
             (void)hipEventRecord(e0, b->stream);
-            const int steps = trial_steps + (trial_steps & 1);
-            if ((rc = enqueue(b, steps))) break;
+            const long long lt = 2 * ((trial_steps + 2 * b->fused - 1) / (2 * b->fused));
+            nl = 0;
+            if ((rc = enqueue(b, lt * b->fused, &nl))) break;
             (void)hipEventRecord(e1, b->stream);
             (void)hipEventSynchronize(e1);
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (best_ms < 0.0f || ms < best_ms) {
-                best_ms = ms;
-                bt = w;
+            const float per_step = ms / (float)(lt * b->fused);
+            if (best_ms < 0.0f || per_step < best_ms) {
+                best_ms = per_step;
+                bt = kd[1];
                 br = h;
+                bk = kd[0];
             }
         }
+        if (rc) break;
+    }
     for (int i = 0; i < b->n; ++i) {
         ggfv_ctx *c = b->inst[i];
         c->cur = cur0[i];
@@ -394,6 +457,7 @@ int ggfv_batch_autotune(ggfv_batch *b, int trial_steps, int *best_threads, int *
     (void)hipEventDestroy(e1);
     b->threads = rc ? thr0 : bt;
     b->rows = rc ? rows0 : br;
+    b->fused = rc ? fus0 : bk;
     b->dirty = true;
     drop_graph(b);
     if (rc) return rc;

@@ -321,27 +321,31 @@ __device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K
     }
 }
 
-template <typename T, bool COMP, int CPL, int K>
-__global__ __launch_bounds__(kWave) void fused_dpp_kernel(StepArgs<T> A)
-{
-    constexpr int TXW = kWave * CPL;
-    constexpr int H = (K + CPL - 1) / CPL * CPL;
-    constexpr int OUTW = TXW - 2 * H;
-    constexpr int RT = 2 * K;
-    static_assert(K >= 1 && K <= 4, "fused depth 1..4");
-    __shared__ TensorRing<T, CPL, RT> L;
+template <int CPL, int K>
+struct DppShape {
+    static constexpr int TXW = kWave * CPL;               // columns a wave holds
+    static constexpr int H = (K + CPL - 1) / CPL * CPL;   // halo columns on each side
+    static constexpr int OUTW = TXW - 2 * H;              // output columns per workgroup
+    static constexpr int RT = 2 * K;                      // tensor ring rows
+};
 
-    const int nbx = gridDim.x;
-    const int lid = xcd_local_id(blockIdx.x + nbx * blockIdx.y, gridDim.x * gridDim.y);
-    const int sx = lid % nbx, sy = lid / nbx;
-    const int o0 = sx * OUTW, e0 = o0 - H;
+// One workgroup's strip: output columns [sx*OUTW, sx*OUTW + OUTW) of rows
+// [sy*A.rows, sy*A.rows + A.rows), K steps from A's input to A's output planes.
+template <typename T, bool COMP, int CPL, int K>
+__device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, const int sy,
+                                          TensorRing<T, CPL, DppShape<CPL, K>::RT> &L)
+{
+    using Sh = DppShape<CPL, K>;
+    constexpr int RT = Sh::RT;
+    static_assert(K >= 1 && K <= 4, "fused depth 1..4");
+    const int o0 = sx * Sh::OUTW, e0 = o0 - Sh::H;
     LaneGeom<K> g;
     g.nx = A.nx;
     g.ny = A.ny;
     g.own = threadIdx.x * CPL;
     g.cbase = e0 + (int)threadIdx.x * CPL;
     g.lcol = min(max(g.cbase, 0), A.pitch - CPL);
-    g.store_ok = g.cbase >= o0 && g.cbase < o0 + OUTW && g.cbase < A.pitch;
+    g.store_ok = g.cbase >= o0 && g.cbase < o0 + Sh::OUTW && g.cbase < A.pitch;
     const int j0 = sy * A.rows, j1 = min(g.ny, j0 + A.rows);
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
@@ -403,11 +407,39 @@ __global__ __launch_bounds__(kWave) void fused_dpp_kernel(StepArgs<T> A)
 }
 
 template <typename T, bool COMP, int CPL, int K>
+__global__ __launch_bounds__(kWave) void fused_dpp_kernel(StepArgs<T> A)
+{
+    __shared__ TensorRing<T, CPL, DppShape<CPL, K>::RT> L;
+    const int nbx = gridDim.x;
+    const int lid = xcd_local_id(blockIdx.x + nbx * blockIdx.y, gridDim.x * gridDim.y);
+    dpp_strip<T, COMP, CPL, K>(A, lid % nbx, lid / nbx, L);
+}
+
+// Ensemble form: the workgroups of all instances in one launch.  Instance i owns
+// the work items [prefix[i], prefix[i+1]) and its own step description D[i]
+// (sizes, planes, parameters, dt and strip height).
+template <typename T, bool COMP, int CPL, int K>
+__global__ __launch_bounds__(kWave) void fused_dpp_batch_kernel(const StepArgs<T> *__restrict__ D,
+                                                                const int *__restrict__ prefix, int n)
+{
+    __shared__ TensorRing<T, CPL, DppShape<CPL, K>::RT> L;
+    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    int lo = 0, hi = n;                    // prefix[lo] <= lid < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= lid) lo = mid;
+        else hi = mid;
+    }
+    const StepArgs<T> A = D[lo];
+    const int nbx = (A.nx + DppShape<CPL, K>::OUTW - 1) / DppShape<CPL, K>::OUTW;
+    const int local = lid - prefix[lo];
+    dpp_strip<T, COMP, CPL, K>(A, local % nbx, local / nbx, L);
+}
+
+template <typename T, bool COMP, int CPL, int K>
 hipError_t launch_dpp_typed(ggfv_ctx *ctx, const void *in, void *out, double dt)
 {
-    constexpr int TXW = kWave * CPL;
-    constexpr int H = (K + CPL - 1) / CPL * CPL;
-    constexpr int OUTW = TXW - 2 * H;
+    constexpr int OUTW = DppShape<CPL, K>::OUTW;
     const int nbx = (ctx->nx + OUTW - 1) / OUTW;
     int rows = ctx->rows_per_strip;
     if (rows <= 0) {
@@ -437,6 +469,26 @@ hipError_t launch_dpp_depth(ggfv_ctx *ctx, const void *in, void *out, double dt,
     }
 }
 
+template <typename T, bool COMP, int CPL, int K>
+hipError_t launch_dpp_batch_typed(const BatchLaunch &b, hipStream_t stream)
+{
+    hipLaunchKernelGGL((fused_dpp_batch_kernel<T, COMP, CPL, K>), dim3(b.items), dim3(kWave), 0, stream,
+                       static_cast<const StepArgs<T> *>(b.desc), b.prefix, b.n);
+    return hipGetLastError();
+}
+
+template <typename T, bool COMP, int CPL>
+hipError_t launch_dpp_batch_depth(const BatchLaunch &b, hipStream_t stream)
+{
+    switch (b.fused) {
+    case 1: return launch_dpp_batch_typed<T, COMP, CPL, 1>(b, stream);
+    case 2: return launch_dpp_batch_typed<T, COMP, CPL, 2>(b, stream);
+    case 3: return launch_dpp_batch_typed<T, COMP, CPL, 3>(b, stream);
+    case 4: return launch_dpp_batch_typed<T, COMP, CPL, 4>(b, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_step_fused_dpp(ggfv_ctx *ctx, const void *in, void *out, double dt, int K)
@@ -445,6 +497,24 @@ hipError_t launch_step_fused_dpp(ggfv_ctx *ctx, const void *in, void *out, doubl
     case GGFV_F64: return launch_dpp_depth<double, false, 1>(ctx, in, out, dt, K);
     case GGFV_F32: return launch_dpp_depth<float, false, 2>(ctx, in, out, dt, K);
     case GGFV_F32C: return launch_dpp_depth<float, true, 2>(ctx, in, out, dt, K);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int lane_shift_columns_per_group(int dtype, int K)
+{
+    const int cpl = dtype == GGFV_F64 ? 1 : 2;
+    const int h = (K + cpl - 1) / cpl * cpl;
+    return kWave * cpl - 2 * h;
+}
+
+hipError_t launch_step_batch_dpp(const BatchLaunch &b, hipStream_t stream)
+{
+    if (b.items <= 0) return hipSuccess;
+    switch (b.dtype) {
+    case GGFV_F64: return launch_dpp_batch_depth<double, false, 1>(b, stream);
+    case GGFV_F32: return launch_dpp_batch_depth<float, false, 2>(b, stream);
+    case GGFV_F32C: return launch_dpp_batch_depth<float, true, 2>(b, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -88,13 +88,18 @@ hipError_t advance_steps(ggfv_ctx *ctx, double dt, long long n);
 // ---- batched step (all instances of an ensemble advance one step per launch) --
 struct BatchLaunch {
     int dtype = 0;
-    int threads = 64;        // workgroup width: 64 or 256
+    int threads = 64;        // workgroup width of the single-step kernel: 64 or 256
+    int fused = 1;           // steps per launch of the lane-shift kernel (launch_step_batch_dpp)
     int n = 0;               // instances
     int items = 0;           // total work items (strips) = prefix[n]
     const void *desc = nullptr;   // device array of n step descriptions
     const int *prefix = nullptr;  // device array of n+1 work-item offsets
 };
 hipError_t launch_step_batch(const BatchLaunch &b, hipStream_t stream);
+// The ensemble form of the lane-shift kernels: b.fused (1..4) steps per launch
+// (ggfv_fused_dpp.hip); output columns per workgroup for a precision and depth.
+hipError_t launch_step_batch_dpp(const BatchLaunch &b, hipStream_t stream);
+int lane_shift_columns_per_group(int dtype, int K);
 // Size of one step description, columns per workgroup, and filling one
 // description for a context (input planes, output planes, dt, strip height).
 size_t step_args_bytes(int dtype);

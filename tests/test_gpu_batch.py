@@ -59,12 +59,65 @@ def test_batch_equals_single_instances_bitwise(dtype, threads):
     b.close()
 
 
-def test_full_ensemble_against_oracle_sampled():
+@pytest.mark.parametrize("dtype", ["f64", "f32c", "f32"])
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_fused_batch_equals_single_instances_bitwise(dtype, K):
+    """The ensemble form of the lane-shift kernel (K steps per launch, graph
+    replays, single-step remainder) gives every instance the bits of that
+    instance stepped alone."""
+    ws = _instances(9, 37, sides=[64, 96, 130, 200, 33])
+    ws.append(wl.Workload("rect", 47, 33, 1.0, 1.0, ws[0].params, *wl.disks_state(47, 33, [(0.5, 0.5)], 0.2),
+                          eig=wl.random_eig(np.random.Generator(np.random.PCG64(7)), 47, 33), safety=0.9))
+    ws.append(wl.Workload("col", 1, 40, 1.0, 1.0, ws[1].params, *wl.disks_state(1, 40, [(0.5, 0.5)], 0.2),
+                          eig=wl.random_eig(np.random.Generator(np.random.PCG64(8)), 1, 40), safety=0.9))
+    ws.append(wl.Workload("row", 150, 1, 1.0, 1.0, ws[2].params, *wl.disks_state(150, 1, [(0.5, 0.5)], 0.2),
+                          eig=wl.random_eig(np.random.Generator(np.random.PCG64(9)), 150, 1), safety=0.9))
+    refs = []
+    b, dts = _setup_batch(ws, dtype)
+    for i, w in enumerate(ws):
+        ctx = _setup_single(w, dtype, dts[i])
+        ctx.step(dts[i], 37)
+        refs.append(ctx.get_state())
+        ctx.close()
+    for rows, graph in ((0, 10), (5, 0), (1, 24)):
+        for i, w in enumerate(ws):
+            b[i].set_state(w.u0, w.v0, w.w0)
+        b.set_tuning(threads=64, rows_per_strip=rows, graph_steps=graph, fused_steps=K)
+        assert b.get_tuning()["fused_steps"] == K
+        b.run(37)
+        for i, w in enumerate(ws):
+            got = b[i].get_state()
+            assert all(np.array_equal(x, y) for x, y in zip(got, refs[i])), (i, w.nx, w.ny, rows, graph)
+    b.close()
+
+
+def test_fused_batch_graph_replays_and_split_runs():
+    """Runs split at arbitrary step counts (odd launch counts, remainders) and
+    repeated graph replays with host reads in between equal one eager run."""
+    ws = _instances(5, 40, sides=[64, 160, 256])
+    b1, _ = _setup_batch(ws, "f32c")
+    b1.set_tuning(threads=64, graph_steps=0, fused_steps=1)
+    b2, _ = _setup_batch(ws, "f32c")
+    b2.set_tuning(threads=64, rows_per_strip=8, graph_steps=16, fused_steps=4)
+    for n in (17, 16, 33, 5, 40):
+        b1.run(n)
+        b2.run(n)
+        for i in range(len(ws)):
+            x, y = b1[i].get_state(), b2[i].get_state()
+            assert all(np.array_equal(p, q) for p, q in zip(x, y)), (n, i)
+            assert b2[i].diagnostics()["steps"] == b1[i].diagnostics()["steps"]
+    b1.close()
+    b2.close()
+
+
+@pytest.mark.parametrize("fused", [1, 4])
+def test_full_ensemble_against_oracle_sampled(fused):
     """256 instances (sides 64..512), compensated FP32, 5000 steps in one batched
-    run; the 8 smallest instances are recomputed by the FP64 oracle on the
-    FP32-rounded inputs."""
+    run (one or four steps per launch); the 8 smallest instances are recomputed
+    by the FP64 oracle on the FP32-rounded inputs."""
     ws = wl.cfg3(256, 5000)
     b, dts = _setup_batch(ws, "f32c")
+    b.set_tuning(threads=64, rows_per_strip=16, graph_steps=48, fused_steps=fused)
     b.run(5000)
     order = sorted(range(len(ws)), key=lambda i: ws[i].cells)[:8]
     f32 = lambda x: np.float64(np.float32(x))
@@ -109,6 +162,7 @@ def test_batch_autotune_keeps_results():
     before = [b[i].get_state() for i in range(len(ws))]
     best = b.autotune(trial_steps=4)
     assert best["threads"] in (64, 256) and best["rows_per_strip"] in (4, 8, 16, 32, 64)
+    assert best["fused_steps"] in (1, 2, 3, 4) and b.get_tuning()["fused_steps"] == best["fused_steps"]
     for i in range(len(ws)):
         assert all(np.array_equal(p, q) for p, q in zip(before[i], b[i].get_state()))
         assert b[i].diagnostics()["steps"] == 0
@@ -149,6 +203,8 @@ def test_batch_errors():
     assert e.value.status == pk.GGFV_ESTATE
     with pytest.raises(pk.GGFVError):
         b.set_tuning(threads=100)
+    with pytest.raises(pk.GGFVError):
+        b.set_tuning(threads=64, fused_steps=5)
     with pytest.raises(pk.GGFVError):
         b.set_dt(5, 1e-6)
     with pytest.raises(pk.GGFVError):
