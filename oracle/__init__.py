@@ -78,6 +78,9 @@ def bind(lib):
     lib.orc_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p, p, p, p, p, p, p]
     lib.orc_diag.argtypes = [i, i, d, d, p, p, p, p, p, p, d, d, p]
     lib.orc_run.argtypes = [i, i, d, d, p, d, l, p, p, p, p, p, p, l, p]
+    lib.orc_adaptive_dt.argtypes = [i, i, d, d, p, p, p, p, d, d]
+    lib.orc_adaptive_dt.restype = d
+    lib.orc_run_adaptive.argtypes = [i, i, d, d, p, d, l, p, p, p, p, p, p, p, p]
     lib.orc_adjoint_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p,
                                      p, p, p, p, p, p, p, p, p, p]
     lib.orc_eig_backward.argtypes = [l, p, p, p, p, p, p, p, p, p]
@@ -165,6 +168,31 @@ def run(u, v, w, a, b, c, params, dt, nsteps, lx=1.0, ly=1.0, mass_every=0):
     _load().orc_run(nx, ny, lx, ly, _ptr(prm), float(dt), int(nsteps), _ptr(u), _ptr(v),
                     _ptr(w), _ptr(a), _ptr(b), _ptr(c), int(mass_every), _ptr(log))
     return u, v, w, log[:nlog]
+
+
+def adaptive_dt(u, a, b, c, Delta2, safety, lx=1.0, ly=1.0) -> float:
+    """Step size of the adaptive scheme on the state u (Section 2: a new step size
+    after every iteration, for stability): the dt whose per-cell Gershgorin
+    number equals `safety`."""
+    u, a, b, c = (_f64(x) for x in (u, a, b, c))
+    ny, nx = u.shape
+    return _load().orc_adaptive_dt(nx, ny, lx, ly, _ptr(u), _ptr(a), _ptr(b), _ptr(c),
+                                   float(Delta2), float(safety))
+
+
+def run_adaptive(u, v, w, a, b, c, params, safety, nsteps, lx=1.0, ly=1.0, t0=0.0):
+    """nsteps steps of eq. (3), each with the adaptive step size of the state it
+    starts from.  Returns (u, v, w, dt_log, t) with t = t0 + sum of the steps."""
+    u, v, w = (np.array(x, dtype=np.float64, copy=True, order="C") for x in (u, v, w))
+    a, b, c = _f64(a), _f64(b), _f64(c)
+    ny, nx = u.shape
+    prm = _f64(params)
+    log = np.zeros(max(int(nsteps), 1))
+    t = ctypes.c_double(float(t0))
+    _load().orc_run_adaptive(nx, ny, lx, ly, _ptr(prm), float(safety), int(nsteps), _ptr(u), _ptr(v),
+                             _ptr(w), _ptr(a), _ptr(b), _ptr(c), _ptr(log),
+                             ctypes.byref(t))
+    return u, v, w, log[:int(nsteps)], t.value
 
 
 def diagnostics(u, v, w, a, b, c, Delta2, dt, lx=1.0, ly=1.0) -> dict:

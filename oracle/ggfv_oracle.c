@@ -224,6 +224,23 @@ void orc_step(int nx, int ny, double lx, double ly, const double *prm, double dt
     free(dV);
 }
 
+/* max over cells of the per-cell Gershgorin bound of the explicit update's
+ * diffusion part:  max( 2(a idx^2 + c idy^2) + |b| idx idy,  2 Delta2 |1-u| (idx^2 + idy^2) ) */
+static double gershgorin_max(int nx, int ny, double lx, double ly, const double *u, const double *a,
+                             const double *b, const double *c, double Delta2)
+{
+    size_t n = (size_t)nx * ny;
+    double idx = nx / lx, idy = ny / ly;
+    double cmax = 0.0;
+    for (size_t k = 0; k < n; ++k) {
+        double cw = 2.0 * (a[k] * (idx * idx) + c[k] * (idy * idy)) + fabs(b[k]) * (idx * idy);
+        double cv = 2.0 * Delta2 * fabs(1.0 - u[k]) * (idx * idx + idy * idy);
+        if (cw > cmax) cmax = cw;
+        if (cv > cmax) cmax = cv;
+    }
+    return cmax;
+}
+
 /* Diagnostics of a state (row-major serial sums):
  *   out[0..2]  mass of u, v, w = dx*dy*sum
  *   out[3..5]  min of u, v, w over finite values
@@ -257,15 +274,47 @@ void orc_diag(int nx, int ny, double lx, double ly, const double *u, const doubl
         out[3 + q] = mn;
         out[6 + q] = mx;
     }
-    double cmax = 0.0;
-    for (size_t k = 0; k < n; ++k) {
-        double cw = 2.0 * (a[k] * (idx * idx) + c[k] * (idy * idy)) + fabs(b[k]) * (idx * idy);
-        double cv = 2.0 * Delta2 * fabs(1.0 - u[k]) * (idx * idx + idy * idy);
-        if (cw > cmax) cmax = cw;
-        if (cv > cmax) cmax = cv;
-    }
-    out[9] = dt * cmax;
+    out[9] = dt * gershgorin_max(nx, ny, lx, ly, u, a, b, c, Delta2);
     out[10] = nonfinite;
+}
+
+/* Adaptive step size.  Section 2 chooses a new step size Delta t_k after every
+ * iteration so that the explicit scheme stays stable, without printing the
+ * rule.  Reading: the largest dt whose per-cell Gershgorin number (the cfl of
+ * orc_diag, on the current state) equals `safety`:
+ *   dt_k = safety / max_ij max( 2(a idx^2 + c idy^2) + |b| idx idy,
+ *                               2 Delta2 |1-u_ij^k| (idx^2 + idy^2) ).
+ * The first term is the acid diffusion (Table 2), the second the tumour-cell
+ * diffusion with its mobility 1-u (Table 1) on the current normal-cell density. */
+double orc_adaptive_dt(int nx, int ny, double lx, double ly, const double *u, const double *a,
+                       const double *b, const double *c, double Delta2, double safety)
+{
+    return safety / gershgorin_max(nx, ny, lx, ly, u, a, b, c, Delta2);
+}
+
+/* nsteps adaptive steps in place on (u, v, w): before every step the step size
+ * is orc_adaptive_dt of the current state; it is written to dt_log[k] (if not
+ * NULL) and added to *t (t_{k+1} = t_k + dt_k). */
+void orc_run_adaptive(int nx, int ny, double lx, double ly, const double *prm, double safety,
+                      long nsteps, double *u, double *v, double *w, const double *a,
+                      const double *b, const double *c, double *dt_log, double *t)
+{
+    size_t n = (size_t)nx * ny;
+    double *un = malloc(n * sizeof(double));
+    double *vn = malloc(n * sizeof(double));
+    double *wn = malloc(n * sizeof(double));
+    for (long s = 0; s < nsteps; ++s) {
+        double dt = orc_adaptive_dt(nx, ny, lx, ly, u, a, b, c, prm[2], safety);
+        orc_step(nx, ny, lx, ly, prm, dt, u, v, w, a, b, c, un, vn, wn, NULL, NULL, NULL);
+        memcpy(u, un, n * sizeof(double));
+        memcpy(v, vn, n * sizeof(double));
+        memcpy(w, wn, n * sizeof(double));
+        if (dt_log) dt_log[s] = dt;
+        *t += dt;
+    }
+    free(un);
+    free(vn);
+    free(wn);
 }
 
 /* nsteps steps in place on (u, v, w).  When mass_every > 0, the masses of u, v, w

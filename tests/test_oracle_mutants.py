@@ -13,6 +13,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_adaptive as adapt
 import test_oracle_adjoint as adj
 import test_oracle_pins as pins
 
@@ -37,6 +38,10 @@ MUTANTS = [
      "for (int i = 0; i + 1 < nx; ++i) {\n            size_t l = IX(i, j), r = IX(i + 1, j);\n            if (i == 0) FX[(size_t)j * (nx + 1)] = 0.5 * b[l] * ty_at(nx, ny, W, 0, j, hy);\n            double tyl", 1),
     ("lambda_max sign", "return m + sqrt(d * d + b * b);", "return m - sqrt(d * d + b * b);", 1),
     ("tensor map b sign", "b[k] = (lam1[k] - lam2[k]) * (sn * cs);", "b[k] = (lam2[k] - lam1[k]) * (sn * cs);", 1),
+    ("adaptive dt without the mobility", "double cv = 2.0 * Delta2 * fabs(1.0 - u[k]) * (idx * idx + idy * idy);",
+     "double cv = 2.0 * Delta2 * (idx * idx + idy * idy);", 1),
+    ("adaptive dt from the diagonal only", "+ fabs(b[k]) * (idx * idy);", ";", 1),
+    ("adaptive dt factor 2 dropped", "double cw = 2.0 * (a[k]", "double cw = (a[k]", 1),
 ]
 
 PIN_TESTS = [
@@ -53,6 +58,9 @@ PIN_TESTS = [
     lambda o: pins.test_p10_polynomials(o),
     lambda o: pins.test_tensor_from_eig_matches_eigh(o),
     lambda o: pins.test_stable_dt_closed_form(o),
+    lambda o: adapt.test_adaptive_isotropic_is_textbook_bound(o),
+    lambda o: adapt.test_adaptive_stability_threshold_on_highest_mode(0.75, 1.05, o),
+    lambda o: adapt.test_adaptive_stability_threshold_on_highest_mode(0.0, 1.05, o),
 ]
 
 
