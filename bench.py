@@ -242,6 +242,33 @@ def time_adjoint(pk, torch, steps=5000):
             "adjoint_step_us_est": 1e3 * res["backward_ms"] / w.steps - fwd_us}
 
 
+def time_adaptive(pk, torch, w, steps=200):
+    """Adaptive stepping on the headline grid (FP64): every step's size derived on
+    the device from the state it starts from; one call of `steps` steps,
+    timed with HIP events on the context's stream (it synchronizes once at the
+    end)."""
+    stream = torch.cuda.current_stream()
+    ctx = pk.Context(w.nx, w.ny, w.lx, w.ly, dtype="f64", stream=stream.cuda_stream)
+    ctx.set_params(w.params)
+    ctx.set_tensor_eig(*w.eig)
+    ctx.set_state(w.u0, w.v0, w.w0)
+    log = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    ctx.step_adaptive(0.9, 10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.step_adaptive(0.9, steps, log)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    dts = log.cpu().numpy()
+    ctx.close()
+    cells = w.nx * w.ny
+    return {"workload": f"{w.nx}x{w.ny} layered tissue, FP64, safety 0.9, {steps} steps in one call",
+            "value": cells * steps / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s",
+            "ms_per_step": ms / steps, "dt_first": float(dts[0]), "dt_last": float(dts[-1])}
+
+
 def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50, force=None):
     """Ensemble workload: `count` instances (sides 64..512, own parameters, tensor
     and dt), compensated FP32.  Batched graph-replayed run versus a loop of
@@ -487,6 +514,7 @@ def main():
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner for the headline shape instead of the fixed shapes")
@@ -543,6 +571,13 @@ def main():
         log("timing the gradient workload (forward with checkpoints, reverse sweep)")
         adj = time_adjoint(pk, torch)
         log(f"  backward/forward = {adj['backward_over_forward']:.2f}")
+    adaptive = None
+    if not args.no_adaptive and "f64" in variants:
+        log("timing adaptive stepping (device-side step size, FP64)")
+        adaptive = time_adaptive(pk, torch, w)
+        adaptive["vs_fixed_single_step"] = adaptive["value"] / single["f64"]["value"]
+        log(f"  adaptive {adaptive['value']:.2f} Gcell/s ({adaptive['vs_fixed_single_step']:.3f} of the fixed-dt "
+            "single-step rate)")
     ens = None
     if not args.no_ensemble:
         log("timing the ensemble (batched graph vs loop of single launches)")
@@ -595,6 +630,7 @@ def main():
                                          "traffic": measured_traffic(v, single[v]["tuning"], single[v]["rows"])}}
                      for v in variants},
         "adjoint": adj,
+        "adaptive": adaptive,
         "ensemble": ens,
         "copy_ceiling_GBs": ceiling,
         "mass_log": r["mass_log"],

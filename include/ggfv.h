@@ -158,6 +158,24 @@ int ggfv_stable_dt(ggfv_ctx *ctx, double safety, double *dt_out);
  * or parameters were never set.  nsteps == 0 is a no-op. */
 int ggfv_step(ggfv_ctx *ctx, double dt, long long nsteps);
 
+/* Advance nsteps steps of eq. (3) with the step size recomputed before every
+ * step, as the time discretization of Section 2 does (a new step size after each
+ * iteration, chosen for stability).  The paper prints no rule; this one takes
+ * the largest step whose per-cell Gershgorin number (the cfl of ggfv_diag) on
+ * the state the step starts from equals `safety`:
+ *   dt_k = safety / max_ij max( 2(a idx^2 + c idy^2) + |b| idx idy,
+ *                               2 Delta2 |1 - u_ij^k| (idx^2 + idy^2) ),
+ * evaluated in FP64 (u = hi + lo for the compensated state).  Everything runs
+ * on the device: each step kernel reduces max |1-u| of the state it writes, and
+ * the next step derives its size from it, so there is no host round trip
+ * between steps.  Single-step launches (the step size may change every step).
+ * dt_log: NULL or device memory for nsteps doubles, receiving dt_0 .. dt_{n-1}.
+ * Synchronizes once at the end, to update the context's time and last step.
+ * EINVAL on safety <= 0 or not finite, nsteps < 0; ESTATE before state, tensor
+ * and parameters are set; ENOMEM if the 64-byte control block cannot be
+ * allocated (once per context). */
+int ggfv_step_adaptive(ggfv_ctx *ctx, double safety, long long nsteps, double *dt_log);
+
 /* Diagnostics of the current state (FP64 accumulation in a fixed order, so the
  * result is reproducible).  Synchronizes.  Returns GGFV_EUNSTABLE (with *out
  * filled) if nonfinite > 0 or cfl > 1. */

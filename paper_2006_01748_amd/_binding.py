@@ -56,6 +56,7 @@ _SIGNATURES = [
     ("ggfv_batch_set_tuning", _c.c_int, [_VP, _c.c_int, _c.c_int, _c.c_int]),
     ("ggfv_batch_autotune", _c.c_int, [_VP, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
     ("ggfv_batch_set_fused_steps", _c.c_int, [_VP, _c.c_int]),
+    ("ggfv_step_adaptive", _c.c_int, [_VP, _c.c_double, _c.c_longlong, _VP]),
     ("ggfv_batch_get_tuning", _c.c_int, [_VP, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int),
                                          _c.POINTER(_c.c_int)]),
     ("ggfv_batch_last_error", _c.c_char_p, [_VP]),
@@ -286,6 +287,19 @@ class Context:
 
     def step(self, dt, nsteps=1):
         self._check(self._lib.ggfv_step(self._h, float(dt), int(nsteps)))
+
+    def step_adaptive(self, safety, nsteps=1, dt_log=None):
+        """nsteps steps, each with the step size the device derives from the state
+        it starts from (ggfv_step_adaptive).  dt_log: None or a CUDA float64
+        tensor of at least nsteps elements that receives the step sizes."""
+        ptr = None
+        if dt_log is not None:
+            if not dt_log.is_cuda or str(dt_log.dtype) != "torch.float64" or not dt_log.is_contiguous():
+                raise ValueError("dt_log must be a contiguous CUDA float64 tensor")
+            if dt_log.numel() < int(nsteps):
+                raise ValueError("dt_log holds fewer than nsteps elements")
+            ptr = ctypes.c_void_p(dt_log.data_ptr())
+        self._check(self._lib.ggfv_step_adaptive(self._h, float(safety), int(nsteps), ptr))
 
     # -- gradients -----------------------------------------------------------
     def state_bytes(self):

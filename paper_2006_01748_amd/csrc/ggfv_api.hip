@@ -241,7 +241,8 @@ void ggfv_destroy(ggfv_ctx *ctx)
     {
         DeviceGuard g(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
-        for (void *p : {ctx->state[0], ctx->state[1], ctx->tensor, ctx->scratch, ctx->staging, ctx->adj})
+        for (void *p : {ctx->state[0], ctx->state[1], ctx->tensor, ctx->scratch, ctx->staging, ctx->adj,
+                        static_cast<void *>(ctx->adapt)})
             if (p) (void)hipFree(p);
     }
     delete ctx;
@@ -542,6 +543,42 @@ int ggfv_step(ggfv_ctx *ctx, double dt, long long nsteps)
     ctx->t += dt_used * (double)nsteps;
     ctx->steps += nsteps;
     ctx->last_dt = dt_used;
+    return GGFV_OK;
+}
+
+int ggfv_step_adaptive(ggfv_ctx *ctx, double safety, long long nsteps, double *dt_log)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!(safety > 0.0) || !std::isfinite(safety))
+        return fail(ctx, GGFV_EINVAL, "safety must be finite and > 0 (got %g)", safety);
+    if (nsteps < 0) return fail(ctx, GGFV_EINVAL, "nsteps must be >= 0 (got %lld)", nsteps);
+    if (!ctx->has_state || !ctx->has_tensor || !ctx->has_params)
+        return fail(ctx, GGFV_ESTATE, "state, tensor and parameters must be set before stepping");
+    if (nsteps == 0) return GGFV_OK;
+    DeviceGuard g(ctx->device);
+    if (!ctx->adapt && hipMalloc(reinterpret_cast<void **>(&ctx->adapt), sizeof(AdaptCtl)) != hipSuccess) {
+        ctx->adapt = nullptr;
+        return fail(ctx, GGFV_ENOMEM, "cannot allocate the adaptive-step control block");
+    }
+    GGFV_HIP(ctx, launch_adapt_init(ctx, ctx->adapt, ctx->t));
+    AdaptArgs ad;
+    ad.ctl = ctx->adapt;
+    ad.dt_log = dt_log;
+    ad.safety = safety;
+    ad.twoD2 = 2.0 * ctx->prm.Delta2;
+    const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly;
+    ad.q = idx * idx + idy * idy;
+    for (long long k = 0; k < nsteps; ++k) {
+        ad.k = k;
+        GGFV_HIP(ctx, launch_step_adaptive(ctx, ctx->state[ctx->cur], ctx->state[1 - ctx->cur], ad));
+        ctx->cur ^= 1;
+    }
+    AdaptCtl host;
+    GGFV_HIP(ctx, hipMemcpyAsync(&host, ctx->adapt, sizeof host, hipMemcpyDeviceToHost, ctx->stream));
+    GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->t = host.t;
+    ctx->steps += nsteps;
+    ctx->last_dt = host.last_dt;
     return GGFV_OK;
 }
 

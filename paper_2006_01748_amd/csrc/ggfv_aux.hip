@@ -231,6 +231,49 @@ __global__ __launch_bounds__(kReduceThreads) void diag_kernel(const T *__restric
     }
 }
 
+// Adaptive stepping: reset the control block.
+__global__ void adapt_reset_kernel(AdaptCtl *ctl, double t0)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->m[0] = ctl->m[1] = ctl->m[2] = 0ull;
+        ctl->t = t0;
+        ctl->tensor_max = 0.0;
+        ctl->last_dt = 0.0;
+    }
+}
+
+// Adaptive stepping: max over cells of the tensor term 2(a idx^2 + c idy^2) +
+// |b| idx idy (at least 0) and of |1 - u| (u = hi + lo in FP64 for the
+// compensated state), as unsigned atomic maxima of the non-negative doubles'
+// bits into the control block.
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void adapt_init_kernel(const T *__restrict__ st, size_t plane,
+                                                                    bool has_lo, const T *__restrict__ abc,
+                                                                    int nx, int ny, int pitch, double idx2,
+                                                                    double idy2, double idxy, AdaptCtl *ctl)
+{
+    const Op ops[2] = {Op::Max, Op::Max};
+    double x[2] = {0.0, 0.0};
+    const long n = (long)nx * ny;
+    for (long k = blockIdx.x * (long)kReduceThreads + threadIdx.x; k < n;
+         k += (long)gridDim.x * kReduceThreads) {
+        const int j = (int)(k / nx), i = (int)(k - (long)j * nx);
+        const size_t o = (size_t)j * pitch + i;
+        const double a = abc[o], b = abc[plane + o], c = abc[2 * plane + o];
+        const double cw = 2.0 * (a * idx2 + c * idy2) + fabs(b) * idxy;
+        double u = double(st[o]);
+        if (has_lo) u = u + double(st[3 * plane + o]);
+        x[0] = fmax(x[0], cw);
+        x[1] = fmax(x[1], fabs(1.0 - u));
+    }
+    block_reduce<2>(x, ops);
+    if (threadIdx.x == 0) {
+        atomicMax(reinterpret_cast<unsigned long long *>(&ctl->tensor_max),
+                  (unsigned long long)__double_as_longlong(x[0]));
+        atomicMax(&ctl->m[0], (unsigned long long)__double_as_longlong(x[1]));
+    }
+}
+
 // Diagnostics final pass (fixed operators per slot).
 __global__ __launch_bounds__(kReduceThreads) void diag_final_kernel(const double *__restrict__ parts,
                                                                     int nparts, double *__restrict__ out)
@@ -354,6 +397,25 @@ hipError_t launch_spd_count(ggfv_ctx *ctx)
 }
 
 hipError_t launch_lambda_max(ggfv_ctx *ctx) { return launch_spd_count(ctx); }
+
+hipError_t launch_adapt_init(ggfv_ctx *ctx, AdaptCtl *ctl, double t0)
+{
+    hipLaunchKernelGGL(adapt_reset_kernel, dim3(1), dim3(64), 0, ctx->stream, ctl, t0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nb = reduce_blocks(ctx);
+    const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly;
+    const bool lo = (ctx->dtype == GGFV_F32C);
+    if (ctx->dtype == GGFV_F64)
+        hipLaunchKernelGGL((adapt_init_kernel<double>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
+                           (const double *)ctx->state[ctx->cur], ctx->plane, false, (const double *)ctx->tensor,
+                           ctx->nx, ctx->ny, ctx->pitch, idx * idx, idy * idy, idx * idy, ctl);
+    else
+        hipLaunchKernelGGL((adapt_init_kernel<float>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
+                           (const float *)ctx->state[ctx->cur], ctx->plane, lo, (const float *)ctx->tensor,
+                           ctx->nx, ctx->ny, ctx->pitch, idx * idx, idy * idy, idx * idy, ctl);
+    return hipGetLastError();
+}
 
 hipError_t launch_diagnostics(ggfv_ctx *ctx, double dt)
 {

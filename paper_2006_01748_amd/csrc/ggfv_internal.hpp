@@ -28,6 +28,20 @@ constexpr int kDiagSlots = 12;    // per-block partials of the diagnostics reduc
 
 }  // namespace ggfv
 
+namespace ggfv {
+// Adaptive stepping (ggfv_step_adaptive): device-resident control block.  m[]
+// holds max |1-u| of a state as the bits of a non-negative double (so an
+// unsigned 64-bit atomic max orders them); step k reads m[k % 3], accumulates
+// the max of its output into m[(k+1) % 3] and clears m[(k+2) % 3].
+struct AdaptCtl {
+    unsigned long long m[3];
+    double t;              // simulated time
+    double tensor_max;     // max over cells of 2(a idx^2 + c idy^2) + |b| idx idy (>= 0)
+    double last_dt;
+    double pad[2];
+};
+}  // namespace ggfv
+
 struct ggfv_ctx {
     int nx = 0, ny = 0, pitch = 0;
     double lx = 1.0, ly = 1.0;
@@ -55,6 +69,7 @@ struct ggfv_ctx {
     int threads = 0;         // workgroup width of the step kernel: 64, 128, 256, or 0 (by grid size)
     int fused_steps = 1;     // time steps per launch (1..4)
     int lane_shift = 0;      // 1: one-wave register/lane-shift kernels (ggfv_fused_dpp.hip)
+    ggfv::AdaptCtl *adapt = nullptr;   // adaptive-step control block (lazily allocated)
 
     void *adj = nullptr;     // adjoint buffers (see ggfv_adjoint.hip), allocated on first use
     size_t adj_bytes = 0;
@@ -86,6 +101,19 @@ hipError_t launch_step_fused_dpp(ggfv_ctx *ctx, const void *in, void *out, doubl
 hipError_t advance_steps(ggfv_ctx *ctx, double dt, long long n);
 
 // ---- batched step (all instances of an ensemble advance one step per launch) --
+struct AdaptArgs {
+    AdaptCtl *ctl = nullptr;
+    double *dt_log = nullptr;      // device, one entry per step of the run, or null
+    long long k = 0;               // step index within the run
+    double safety = 0.0;
+    double twoD2 = 0.0;            // 2 * Delta2
+    double q = 0.0;                // idx^2 + idy^2
+};
+hipError_t launch_step_adaptive(ggfv_ctx *ctx, const void *in, void *out, const AdaptArgs &ad);
+// Reset the control block (time t0) and reduce the tensor term and max |1-u| of
+// the context's current state into it.
+hipError_t launch_adapt_init(ggfv_ctx *ctx, AdaptCtl *ctl, double t0);
+
 struct BatchLaunch {
     int dtype = 0;
     int threads = 64;        // workgroup width of the single-step kernel: 64 or 256

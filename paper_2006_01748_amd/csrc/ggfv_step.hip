@@ -87,8 +87,11 @@ __device__ __forceinline__ void load_row(const StepArgs<T> &A, int jr, int col, 
 
 // One workgroup's strip (sx, sy): columns [sx*TXW, (sx+1)*TXW), rows
 // [sy*rows, (sy+1)*rows), one step from A's input planes to its output planes.
-template <typename T, bool COMP, int CPL, int NT>
-__device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, const int sy)
+// With TRACK the thread also returns in *umax the largest |1 - u| over the new
+// u values it wrote (u = hi + lo in FP64 for the compensated state).
+template <typename T, bool COMP, int CPL, int NT, bool TRACK = false>
+__device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, const int sy,
+                                          double *umax = nullptr)
 {
     constexpr int TXW = NT * CPL;          // owned columns per workgroup
     constexpr int LW = TXW + 2 * CPL;      // LDS row: CPL pad, TXW owned, CPL pad
@@ -141,6 +144,7 @@ __device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, c
     T FYs[CPL], GYs[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) { FYs[k] = T(0); GYs[k] = T(0); }
+    double mu = 0.0;
 
     for (int jj = js; jj < j1; ++jj) {
         // Publish W(jj+1) and U, V, a, b (jj) for the x-neighbours.
@@ -228,6 +232,15 @@ __device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, c
             FYs[k] = FYn;
             GYs[k] = GYn;
         }
+        if constexpr (TRACK) {
+            if (upd) {
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    const double un = COMP ? double(ou[k]) + double(oul[k]) : double(ou[k]);
+                    if (cbase + k < nx) mu = fmax(mu, fabs(1.0 - un));
+                }
+            }
+        }
         if (upd && cbase < A.pitch) {
             const size_t o = (size_t)jj * A.pitch + cbase;
             store_vec<T, CPL>(A.un + o, ou);
@@ -244,6 +257,7 @@ __device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, c
         cur = nxt;
         nxt = pre;
     }
+    if constexpr (TRACK) *umax = mu;
 }
 
 template <typename T, bool COMP, int CPL, int NT>
@@ -252,6 +266,50 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs<T> A)
     const int nbx = gridDim.x;
     const int lid = xcd_local_id(blockIdx.x + nbx * blockIdx.y, gridDim.x * gridDim.y);
     step_strip<T, COMP, CPL, NT>(A, lid % nbx, lid / nbx);
+}
+
+// Adaptive form (Section 2: a new step size after every iteration): the step
+// size is computed here, from the control block, as
+//   dt_k = safety / max(tensor_max, (2 Delta2 * max|1 - u^k|) * (idx^2 + idy^2))
+// in FP64 (max|1 - u^k| was reduced by the previous step, or by the run's
+// initial reduction), and the workgroups reduce max|1 - u^{k+1}| of their output
+// into the next slot.  Workgroup 0 advances the time, logs dt_k and clears slot
+// (k+2) % 3, the one step k+1 accumulates into (step k-1 read it last; nothing
+// touches it during step k).
+template <typename T, bool COMP, int CPL, int NT>
+__global__ __launch_bounds__(NT) void step_adaptive_kernel(StepArgs<T> A, AdaptArgs D)
+{
+    __shared__ double red[NT / 64];
+    const double M = __longlong_as_double((long long)D.ctl->m[D.k % 3]);
+    const double cv = (D.twoD2 * M) * D.q;
+    double cmax = D.ctl->tensor_max;
+    if (cv > cmax) cmax = cv;
+    const double dt = D.safety / cmax;
+    StepArgs<T> B = A;
+    B.dt = T(dt);
+    const int nbx = gridDim.x;
+    const int bid = blockIdx.x + nbx * blockIdx.y;
+    const int lid = xcd_local_id(bid, gridDim.x * gridDim.y);
+    double mu = 0.0;
+    step_strip<T, COMP, CPL, NT, true>(B, lid % nbx, lid / nbx, &mu);
+    // workgroup max of |1 - u|, then one atomic per workgroup
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mu = fmax(mu, __shfl_xor(mu, off, 64));
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) red[wave] = mu;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) m = fmax(m, red[w]);
+        atomicMax(&D.ctl->m[(D.k + 1) % 3], (unsigned long long)__double_as_longlong(m));
+        if (bid == 0) {
+            D.ctl->t = D.ctl->t + dt;
+            D.ctl->last_dt = dt;
+            D.ctl->m[(D.k + 2) % 3] = 0ull;
+            if (D.dt_log) D.dt_log[D.k] = dt;
+        }
+    }
 }
 
 // Batched form: work item k of all instances' strips; instance i owns items
@@ -366,6 +424,39 @@ hipError_t launch_step_batch(const BatchLaunch &b, hipStream_t stream)
     case GGFV_F32C:
         return narrow ? launch_batch_typed<float, true, 2, 64>(b, stream)
                       : launch_batch_typed<float, true, 2, 256>(b, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <typename T, bool COMP, int CPL, int NT>
+hipError_t launch_adaptive_typed(ggfv_ctx *ctx, const void *in, void *out, const AdaptArgs &ad)
+{
+    constexpr int TXW = NT * CPL;
+    const int nbx = (ctx->nx + TXW - 1) / TXW;
+    const int rows = pick_rows(ctx, nbx, NT);
+    const int nby = (ctx->ny + rows - 1) / rows;
+    const StepArgs<T> A = make_args<T>(ctx, in, out, 0.0, rows);
+    hipLaunchKernelGGL((step_adaptive_kernel<T, COMP, CPL, NT>), dim3(nbx, nby), dim3(NT), 0, ctx->stream, A, ad);
+    return hipGetLastError();
+}
+
+template <typename T, bool COMP, int CPL>
+hipError_t launch_adaptive_width(ggfv_ctx *ctx, const void *in, void *out, const AdaptArgs &ad)
+{
+    const int w = pick_threads(ctx);
+    if (w == 64) return launch_adaptive_typed<T, COMP, CPL, 64>(ctx, in, out, ad);
+    if (w == 128) return launch_adaptive_typed<T, COMP, CPL, 128>(ctx, in, out, ad);
+    return launch_adaptive_typed<T, COMP, CPL, 256>(ctx, in, out, ad);
+}
+}  // namespace
+
+hipError_t launch_step_adaptive(ggfv_ctx *ctx, const void *in, void *out, const AdaptArgs &ad)
+{
+    switch (ctx->dtype) {
+    case GGFV_F64: return launch_adaptive_width<double, false, 1>(ctx, in, out, ad);
+    case GGFV_F32: return launch_adaptive_width<float, false, 2>(ctx, in, out, ad);
+    case GGFV_F32C: return launch_adaptive_width<float, true, 2>(ctx, in, out, ad);
     default: return hipErrorInvalidValue;
     }
 }
