@@ -81,6 +81,9 @@ def bind(lib):
     lib.orc_adaptive_dt.argtypes = [i, i, d, d, p, p, p, p, d, d]
     lib.orc_adaptive_dt.restype = d
     lib.orc_run_adaptive.argtypes = [i, i, d, d, p, d, l, p, p, p, p, p, p, p, p]
+    lib.orc_front_diag.argtypes = [i, i, d, p, p, d, d, p]
+    lib.orc_front_speed.argtypes = [d, d, d, d, d, d, d]
+    lib.orc_front_speed.restype = d
     lib.orc_adjoint_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p,
                                      p, p, p, p, p, p, p, p, p, p]
     lib.orc_eig_backward.argtypes = [l, p, p, p, p, p, p, p, p, p]
@@ -193,6 +196,23 @@ def run_adaptive(u, v, w, a, b, c, params, safety, nsteps, lx=1.0, ly=1.0, t0=0.
                              _ptr(w), _ptr(a), _ptr(b), _ptr(c), _ptr(log),
                              ctypes.byref(t))
     return u, v, w, log[:int(nsteps)], t.value
+
+
+def front_diag(u, v, theta_u=0.5, theta_v=0.5, lx=1.0) -> dict:
+    """Tumour front, tissue front and interstitial gap along +x (per row, then
+    mean / min / max over rows); see orc_front_diag."""
+    u, v = _f64(u), _f64(v)
+    ny, nx = u.shape
+    out = np.zeros(11)
+    _load().orc_front_diag(nx, ny, float(lx), _ptr(u), _ptr(v), float(theta_u), float(theta_v), _ptr(out))
+    return {"tumour": out[0:3].copy(), "tissue": out[3:6].copy(), "gap": out[6:9].copy(),
+            "rows_front": int(out[9]), "rows_gap": int(out[10])}
+
+
+def front_speed(mass0, mass1, t0, t1, ly=1.0, behind=1.0, ahead=0.0) -> float:
+    """LeVeque-Yee space-averaged front speed from two masses of one population."""
+    return _load().orc_front_speed(float(mass0), float(mass1), float(t0), float(t1), float(ly),
+                                   float(behind), float(ahead))
 
 
 def diagnostics(u, v, w, a, b, c, Delta2, dt, lx=1.0, ly=1.0) -> dict:

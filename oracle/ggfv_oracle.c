@@ -317,6 +317,92 @@ void orc_run_adaptive(int nx, int ny, double lx, double ly, const double *prm, d
     free(wn);
 }
 
+/* Front diagnostics for fronts that advance towards +x (Section 2's
+ * propagating tumour fronts and the interstitial gap between the tumour and the
+ * healthy tissue).  The paper prints no definition; reading, per row j:
+ *   tumour front  xv_j: the largest cell index i with v_ij >= theta_v, moved to
+ *                 the threshold crossing by linear interpolation towards cell
+ *                 i+1 (x_i + (v_i - theta_v)/(v_i - v_i+1) dx when cell i+1
+ *                 exists and lies below the threshold; x_i otherwise);
+ *   tissue front  xu_j: the smallest index i beyond the tumour front's cell
+ *                 with u_ij >= theta_u, moved back to the crossing by linear
+ *                 interpolation towards cell i-1 (x_i - (u_i - theta_u)/(u_i -
+ *                 u_i-1) dx when u_i-1 < theta_u);
+ *   gap           g_j = xu_j - xv_j (the width of the region between the two
+ *                 fronts where neither population reaches its threshold).
+ * Cell centres are x_i = (i + 1/2) dx.  A row has a tumour front if some cell
+ * reaches theta_v, and a gap if it also has a tissue front.  Outputs:
+ *   out[0..2]  mean, min, max of xv over rows with a tumour front
+ *   out[3..5]  mean, min, max of xu over rows with a gap
+ *   out[6..8]  mean, min, max of g over rows with a gap
+ *   out[9], out[10]  number of rows with a tumour front, with a gap
+ * (means are serial sums in row order divided by the count; 0 when the count
+ * is 0, min and max then +inf and -inf). */
+void orc_front_diag(int nx, int ny, double lx, const double *u, const double *v, double theta_u,
+                    double theta_v, double *out)
+{
+    double dx = lx / nx;
+    double s[3] = {0.0, 0.0, 0.0}, mn[3], mx[3];
+    long nv = 0, ng = 0;
+    for (int q = 0; q < 3; ++q) {
+        mn[q] = INFINITY;
+        mx[q] = -INFINITY;
+    }
+    for (int j = 0; j < ny; ++j) {
+        int iv = -1;
+        for (int i = 0; i < nx; ++i)
+            if (v[IX(i, j)] >= theta_v) iv = i;
+        if (iv < 0) continue;
+        double xv = (iv + 0.5) * dx;
+        if (iv + 1 < nx) {
+            double a = v[IX(iv, j)], b = v[IX(iv + 1, j)];
+            xv = xv + (a - theta_v) / (a - b) * dx;
+        }
+        ++nv;
+        s[0] += xv;
+        if (xv < mn[0]) mn[0] = xv;
+        if (xv > mx[0]) mx[0] = xv;
+        int iu = -1;
+        for (int i = iv + 1; i < nx; ++i)
+            if (u[IX(i, j)] >= theta_u) {
+                iu = i;
+                break;
+            }
+        if (iu < 0) continue;
+        double xu = (iu + 0.5) * dx;
+        double c = u[IX(iu, j)], d = u[IX(iu - 1, j)];
+        if (d < theta_u) xu = xu - (c - theta_u) / (c - d) * dx;
+        double g = xu - xv;
+        ++ng;
+        s[1] += xu;
+        s[2] += g;
+        if (xu < mn[1]) mn[1] = xu;
+        if (xu > mx[1]) mx[1] = xu;
+        if (g < mn[2]) mn[2] = g;
+        if (g > mx[2]) mx[2] = g;
+    }
+    out[0] = nv > 0 ? s[0] / (double)nv : 0.0;
+    out[3] = ng > 0 ? s[1] / (double)ng : 0.0;
+    out[6] = ng > 0 ? s[2] / (double)ng : 0.0;
+    for (int q = 0; q < 3; ++q) {
+        out[3 * q + 1] = mn[q];
+        out[3 * q + 2] = mx[q];
+    }
+    out[9] = (double)nv;
+    out[10] = (double)ng;
+}
+
+/* Speed of a front from two masses (LeVeque and Yee's space-averaged wave
+ * speed, cited in Section 2): a front that moves the transition between the
+ * state behind it (density `behind`) and the state ahead of it (`ahead`) by
+ * s*(t1 - t0) across a domain of height ly changes the mass by
+ * ly*(behind - ahead)*s*(t1 - t0). */
+double orc_front_speed(double mass0, double mass1, double t0, double t1, double ly, double behind,
+                       double ahead)
+{
+    return (mass1 - mass0) / ((t1 - t0) * ly * (behind - ahead));
+}
+
 /* nsteps steps in place on (u, v, w).  When mass_every > 0, the masses of u, v, w
  * after every mass_every-th step are written to mass_log (3 per entry). */
 void orc_run(int nx, int ny, double lx, double ly, const double *prm, double dt,

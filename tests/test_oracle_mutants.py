@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import test_oracle_adaptive as adapt
+import test_oracle_front as front
 import test_oracle_adjoint as adj
 import test_oracle_pins as pins
 
@@ -42,6 +43,12 @@ MUTANTS = [
      "double cv = 2.0 * Delta2 * (idx * idx + idy * idy);", 1),
     ("adaptive dt from the diagonal only", "+ fabs(b[k]) * (idx * idy);", ";", 1),
     ("adaptive dt factor 2 dropped", "double cw = 2.0 * (a[k]", "double cw = (a[k]", 1),
+    ("tumour front interpolated the wrong way", "xv = xv + (a - theta_v) / (a - b) * dx;",
+     "xv = xv - (a - theta_v) / (a - b) * dx;", 1),
+    ("first instead of last tumour cell", "if (v[IX(i, j)] >= theta_v) iv = i;",
+     "if (v[IX(i, j)] >= theta_v && iv < 0) iv = i;", 1),
+    ("tissue front not interpolated", "if (d < theta_u) xu = xu - (c - theta_u) / (c - d) * dx;", "", 1),
+    ("front speed without the jump", "((t1 - t0) * ly * (behind - ahead))", "((t1 - t0) * ly)", 1),
 ]
 
 PIN_TESTS = [
@@ -61,6 +68,9 @@ PIN_TESTS = [
     lambda o: adapt.test_adaptive_isotropic_is_textbook_bound(o),
     lambda o: adapt.test_adaptive_stability_threshold_on_highest_mode(0.75, 1.05, o),
     lambda o: adapt.test_adaptive_stability_threshold_on_highest_mode(0.0, 1.05, o),
+    lambda o: front.test_front_diag_ramps_exact(o),
+    lambda o: front.test_front_diag_edge_cases(o),
+    lambda o: front.test_leveque_yee_recovers_a_translation(o),
 ]
 
 
