@@ -269,6 +269,54 @@ def time_adaptive(pk, torch, w, steps=200):
             "ms_per_step": ms / steps, "dt_first": float(dts[0]), "dt_last": float(dts[-1])}
 
 
+def time_front_sweep(pk, torch, t_end=0.25):
+    """Invasion sweep (Section 2's propagating fronts and interstitial gap):
+    delta1 in {0.5, 0.8, 1.5, 3, 6, 12.5} x vertical/horizontal acid
+    diffusivity ratio in {1, 0.2}, 512 x 256 fronts on [0,1] x [0,0.5], FP64,
+    one batch on the lane-shift kernel (4 steps per launch) with a common dt, run
+    to t_end; then the fronts, the gap and the LeVeque-Yee tumour speed of every
+    instance."""
+    from paper_2006_01748_amd import workloads as wl
+    ws = wl.front_sweep()
+    stream = torch.cuda.Stream()
+    b = pk.Batch([(w.nx, w.ny) for w in ws], lx=ws[0].lx, ly=ws[0].ly, dtype="f64", stream=stream.cuda_stream)
+    dts = []
+    for i, w in enumerate(ws):
+        c = b[i]
+        c.set_params(w.params)
+        c.set_tensor_eig(*w.eig)
+        c.set_state(w.u0, w.v0, w.w0)
+        dts.append(c.stable_dt(w.safety))
+    dt = min(dts)
+    for i in range(len(ws)):
+        b.set_dt(i, dt)
+    b.set_tuning(threads=64, rows_per_strip=16, graph_steps=48, fused_steps=4)
+    m0 = [b[i].diagnostics()["mass"][1] for i in range(len(ws))]
+    f0 = [b[i].front_diagnostics(0.25, 0.5)["tumour"][0] for i in range(len(ws))]
+    n = int(t_end / dt) // 4 * 4
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.run(n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = sum(w.cells for w in ws)
+    out = []
+    for i, w in enumerate(ws):
+        d = b[i].diagnostics()
+        f = b[i].front_diagnostics(0.25, 0.5)
+        out.append({"delta1": w.params[0], "kappa": round(float(w.eig[1][0, 0] / w.eig[0][0, 0]), 6),
+                    "tumour_front": float(f["tumour"][0]), "tumour_front_advance": float(f["tumour"][0] - f0[i]),
+                    "gap_mean": float(f["gap"][0]) if f["rows_gap"] else None,
+                    "gap_max": float(f["gap"][2]) if f["rows_gap"] else None,
+                    "tumour_speed_leveque_yee": pk.front_speed(m0[i], d["mass"][1], 0.0, d["t"], w.ly, 1.0, 0.0)})
+    b.close()
+    return {"workload": f"{len(ws)} fronts 512x256 (delta1 sweep x 2 acid anisotropies), FP64, lane-shift "
+                        f"batch, {n} steps to t = {n * dt:.3g}",
+            "value": cells * n / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "ms": ms, "instances": out}
+
+
 def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50, force=None):
     """Ensemble workload: `count` instances (sides 64..512, own parameters, tensor
     and dt), compensated FP32.  Batched graph-replayed run versus a loop of
@@ -515,6 +563,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--no-fronts", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner for the headline shape instead of the fixed shapes")
@@ -578,6 +627,13 @@ def main():
         adaptive["vs_fixed_single_step"] = adaptive["value"] / single["f64"]["value"]
         log(f"  adaptive {adaptive['value']:.2f} Gcell/s ({adaptive['vs_fixed_single_step']:.3f} of the fixed-dt "
             "single-step rate)")
+    fronts = None
+    if not args.no_fronts:
+        log("timing the invasion sweep (fronts and interstitial gap)")
+        fronts = time_front_sweep(pk, torch)
+        log(f"  {fronts['value']:.1f} Gcell/s; gaps " +
+            ", ".join(f"d={x['delta1']}/k={x['kappa']:.1f}: {x['gap_mean'] if x['gap_mean'] is None else round(x['gap_mean'], 4)}"
+                      for x in fronts["instances"]))
     ens = None
     if not args.no_ensemble:
         log("timing the ensemble (batched graph vs loop of single launches)")
@@ -631,6 +687,7 @@ def main():
                      for v in variants},
         "adjoint": adj,
         "adaptive": adaptive,
+        "front_sweep": fronts,
         "ensemble": ens,
         "copy_ceiling_GBs": ceiling,
         "mass_log": r["mass_log"],

@@ -176,6 +176,31 @@ int ggfv_step(ggfv_ctx *ctx, double dt, long long nsteps);
  * allocated (once per context). */
 int ggfv_step_adaptive(ggfv_ctx *ctx, double safety, long long nsteps, double *dt_log);
 
+/* Fronts of the current state for fronts that advance towards +x: the
+ * propagating tumour front and the hypocellular interstitial gap ahead of it
+ * (Section 2's homogeneous and heterogeneous invasion).  The paper prints no
+ * definition; per row j:
+ *   tumour front xv_j: the last cell i with v >= theta_v, moved to the crossing
+ *     by linear interpolation towards cell i+1 (x_i + (v_i - theta_v)/(v_i -
+ *     v_i+1) dx when cell i+1 exists);
+ *   tissue front xu_j: the first cell i beyond it with u >= theta_u, moved back
+ *     to the crossing when u_i-1 < theta_u (x_i - (u_i - theta_u)/(u_i -
+ *     u_i-1) dx);
+ *   gap g_j = xu_j - xv_j;
+ * with cell centres x_i = (i + 1/2) lx/nx and u, v as FP64 (hi + lo for the
+ * compensated state).  out (host, 11 doubles): mean, min, max of xv over rows
+ * with a tumour front; mean, min, max of xu and of g over rows with both
+ * fronts; the two row counts.  Means of no rows are 0, their min/max +inf /
+ * -inf.  Synchronizes.  EINVAL on NULL out or non-finite thresholds, ESTATE
+ * without a state, ENOMEM if the (4 ny + 16)-double buffer cannot be allocated
+ * (once per context). */
+int ggfv_front_diagnostics(ggfv_ctx *ctx, double theta_u, double theta_v, double *out);
+/* Space-averaged front speed (LeVeque and Yee, cited in Section 2) from the mass
+ * of one population at two times (ggfv_diagnostics): a transition from density
+ * `behind` to density `ahead` moving at speed s across a domain of height ly
+ * changes the mass at the rate ly (behind - ahead) s.  Pure arithmetic. */
+double ggfv_front_speed(double mass0, double mass1, double t0, double t1, double ly, double behind, double ahead);
+
 /* Diagnostics of the current state (FP64 accumulation in a fixed order, so the
  * result is reproducible).  Synchronizes.  Returns GGFV_EUNSTABLE (with *out
  * filled) if nonfinite > 0 or cfl > 1. */

@@ -57,6 +57,8 @@ _SIGNATURES = [
     ("ggfv_batch_autotune", _c.c_int, [_VP, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
     ("ggfv_batch_set_fused_steps", _c.c_int, [_VP, _c.c_int]),
     ("ggfv_step_adaptive", _c.c_int, [_VP, _c.c_double, _c.c_longlong, _VP]),
+    ("ggfv_front_diagnostics", _c.c_int, [_VP, _c.c_double, _c.c_double, _c.POINTER(_c.c_double)]),
+    ("ggfv_front_speed", _c.c_double, [_c.c_double] * 7),
     ("ggfv_batch_get_tuning", _c.c_int, [_VP, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int),
                                          _c.POINTER(_c.c_int)]),
     ("ggfv_batch_last_error", _c.c_char_p, [_VP]),
@@ -116,6 +118,12 @@ def lib():
         f.argtypes = args
     _lib = L
     return L
+
+
+def front_speed(mass0, mass1, t0, t1, ly=1.0, behind=1.0, ahead=0.0):
+    """LeVeque-Yee space-averaged front speed from two masses (ggfv_front_speed)."""
+    return float(lib().ggfv_front_speed(float(mass0), float(mass1), float(t0), float(t1), float(ly),
+                                        float(behind), float(ahead)))
 
 
 def exported_names():
@@ -287,6 +295,14 @@ class Context:
 
     def step(self, dt, nsteps=1):
         self._check(self._lib.ggfv_step(self._h, float(dt), int(nsteps)))
+
+    def front_diagnostics(self, theta_u=0.5, theta_v=0.5):
+        """Tumour front, tissue front and interstitial gap along +x (ggfv_front_diagnostics)."""
+        out = (ctypes.c_double * 11)()
+        self._check(self._lib.ggfv_front_diagnostics(self._h, float(theta_u), float(theta_v), out))
+        o = list(out)
+        return {"tumour": np.array(o[0:3]), "tissue": np.array(o[3:6]), "gap": np.array(o[6:9]),
+                "rows_front": int(o[9]), "rows_gap": int(o[10])}
 
     def step_adaptive(self, safety, nsteps=1, dt_log=None):
         """nsteps steps, each with the step size the device derives from the state

@@ -242,7 +242,7 @@ void ggfv_destroy(ggfv_ctx *ctx)
         DeviceGuard g(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
         for (void *p : {ctx->state[0], ctx->state[1], ctx->tensor, ctx->scratch, ctx->staging, ctx->adj,
-                        static_cast<void *>(ctx->adapt)})
+                        static_cast<void *>(ctx->adapt), static_cast<void *>(ctx->front)})
             if (p) (void)hipFree(p);
     }
     delete ctx;
@@ -580,6 +580,31 @@ int ggfv_step_adaptive(ggfv_ctx *ctx, double safety, long long nsteps, double *d
     ctx->steps += nsteps;
     ctx->last_dt = host.last_dt;
     return GGFV_OK;
+}
+
+int ggfv_front_diagnostics(ggfv_ctx *ctx, double theta_u, double theta_v, double *out)
+{
+    if (!ctx) return GGFV_EINVAL;
+    if (!out) return fail(ctx, GGFV_EINVAL, "null output");
+    if (!std::isfinite(theta_u) || !std::isfinite(theta_v))
+        return fail(ctx, GGFV_EINVAL, "thresholds must be finite");
+    if (!ctx->has_state) return fail(ctx, GGFV_ESTATE, "no state set");
+    DeviceGuard g(ctx->device);
+    const size_t n = 4 * (size_t)ctx->ny + 16;
+    if (!ctx->front && hipMalloc(reinterpret_cast<void **>(&ctx->front), n * sizeof(double)) != hipSuccess) {
+        ctx->front = nullptr;
+        return fail(ctx, GGFV_ENOMEM, "cannot allocate the front-diagnostics buffer");
+    }
+    double *res = ctx->front + 4 * (size_t)ctx->ny;
+    GGFV_HIP(ctx, launch_front_diagnostics(ctx, theta_u, theta_v, ctx->front, res));
+    GGFV_HIP(ctx, hipMemcpyAsync(out, res, 11 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GGFV_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GGFV_OK;
+}
+
+double ggfv_front_speed(double mass0, double mass1, double t0, double t1, double ly, double behind, double ahead)
+{
+    return (mass1 - mass0) / ((t1 - t0) * ly * (behind - ahead));
 }
 
 int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tn)

@@ -274,6 +274,116 @@ __global__ __launch_bounds__(kReduceThreads) void adapt_init_kernel(const T *__r
     }
 }
 
+// Front diagnostics, per row (one wave per row): the tumour front is the last
+// cell with v >= theta_v, moved to the crossing by linear interpolation towards
+// the next cell; the tissue front is the first cell beyond it with u >=
+// theta_u, moved back to the crossing when the previous cell lies below the
+// threshold.  Writes (xv, xu, xu - xv, flags) per row; flags bit 0: tumour
+// front, bit 1: tissue front (gap).  Values are u, v (hi + lo in FP64 for the
+// compensated state); positions are cell centres (i + 1/2) dx.
+template <typename T>
+__device__ __forceinline__ double field_at(const T *__restrict__ hi, const T *__restrict__ lo, int i)
+{
+    return lo ? double(hi[i]) + double(lo[i]) : double(hi[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void front_row_kernel(const T *__restrict__ st, size_t plane, bool has_lo, int nx,
+                                                       int pitch, double dx, double theta_u, double theta_v,
+                                                       double *__restrict__ rows)
+{
+    const int j = blockIdx.x, lane = threadIdx.x;
+    const T *u = st + (size_t)j * pitch;
+    const T *v = st + plane + (size_t)j * pitch;
+    const T *ul = has_lo ? st + 3 * plane + (size_t)j * pitch : nullptr;
+    const T *vl = has_lo ? st + 4 * plane + (size_t)j * pitch : nullptr;
+    int iv = -1;
+    for (int i = lane; i < nx; i += 64)
+        if (field_at(v, vl, i) >= theta_v) iv = i;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) iv = max(iv, __shfl_xor(iv, off, 64));
+    int iu = nx;
+    if (iv >= 0) {
+        for (int i = iv + 1 + lane; i < nx; i += 64)
+            if (field_at(u, ul, i) >= theta_u) {
+                iu = i;
+                break;
+            }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) iu = min(iu, __shfl_xor(iu, off, 64));
+    if (lane == 0) {
+        double xv = 0.0, xu = 0.0, flags = 0.0;
+        if (iv >= 0) {
+            xv = (iv + 0.5) * dx;
+            if (iv + 1 < nx) {
+                const double a = field_at(v, vl, iv), b = field_at(v, vl, iv + 1);
+                xv = xv + (a - theta_v) / (a - b) * dx;
+            }
+            flags = 1.0;
+            if (iu < nx) {
+                xu = (iu + 0.5) * dx;
+                const double c = field_at(u, ul, iu), d = field_at(u, ul, iu - 1);
+                if (d < theta_u) xu = xu - (c - theta_u) / (c - d) * dx;
+                flags = 3.0;
+            }
+        }
+        rows[4 * (size_t)j + 0] = xv;
+        rows[4 * (size_t)j + 1] = xu;
+        rows[4 * (size_t)j + 2] = xu - xv;
+        rows[4 * (size_t)j + 3] = flags;
+    }
+}
+
+// Front diagnostics over rows: sums, minima and maxima of the per-row values
+// (each thread a fixed contiguous range of rows, then the fixed-order block
+// reduction), and the counts; out as the oracle's front diagnostics.
+__global__ __launch_bounds__(kReduceThreads) void front_final_kernel(const double *__restrict__ rows, int ny,
+                                                                     double *__restrict__ out)
+{
+    const Op ops[11] = {Op::Sum, Op::Min, Op::Max, Op::Sum, Op::Min, Op::Max,
+                        Op::Sum, Op::Min, Op::Max, Op::Sum, Op::Sum};
+    double x[11];
+#pragma unroll
+    for (int s = 0; s < 11; ++s) x[s] = identity(ops[s]);
+    const int per = (ny + kReduceThreads - 1) / kReduceThreads;
+    const int j0 = threadIdx.x * per, j1 = min(ny, j0 + per);
+    for (int j = j0; j < j1; ++j) {
+        const double f = rows[4 * (size_t)j + 3];
+        if (f >= 1.0) {
+            const double xv = rows[4 * (size_t)j];
+            x[0] += xv;
+            x[1] = fmin(x[1], xv);
+            x[2] = fmax(x[2], xv);
+            x[9] += 1.0;
+        }
+        if (f >= 3.0) {
+            const double xu = rows[4 * (size_t)j + 1], g = rows[4 * (size_t)j + 2];
+            x[3] += xu;
+            x[4] = fmin(x[4], xu);
+            x[5] = fmax(x[5], xu);
+            x[6] += g;
+            x[7] = fmin(x[7], g);
+            x[8] = fmax(x[8], g);
+            x[10] += 1.0;
+        }
+    }
+    block_reduce<11>(x, ops);
+    if (threadIdx.x == 0) {
+        out[0] = x[9] > 0.0 ? x[0] / x[9] : 0.0;
+        out[3] = x[10] > 0.0 ? x[3] / x[10] : 0.0;
+        out[6] = x[10] > 0.0 ? x[6] / x[10] : 0.0;
+        out[1] = x[1];
+        out[2] = x[2];
+        out[4] = x[4];
+        out[5] = x[5];
+        out[7] = x[7];
+        out[8] = x[8];
+        out[9] = x[9];
+        out[10] = x[10];
+    }
+}
+
 // Diagnostics final pass (fixed operators per slot).
 __global__ __launch_bounds__(kReduceThreads) void diag_final_kernel(const double *__restrict__ parts,
                                                                     int nparts, double *__restrict__ out)
@@ -414,6 +524,24 @@ hipError_t launch_adapt_init(ggfv_ctx *ctx, AdaptCtl *ctl, double t0)
         hipLaunchKernelGGL((adapt_init_kernel<float>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
                            (const float *)ctx->state[ctx->cur], ctx->plane, lo, (const float *)ctx->tensor,
                            ctx->nx, ctx->ny, ctx->pitch, idx * idx, idy * idy, idx * idy, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_front_diagnostics(ggfv_ctx *ctx, double theta_u, double theta_v, double *rows, double *out)
+{
+    const double dx = ctx->lx / ctx->nx;
+    const bool lo = (ctx->dtype == GGFV_F32C);
+    if (ctx->dtype == GGFV_F64)
+        hipLaunchKernelGGL((front_row_kernel<double>), dim3(ctx->ny), dim3(64), 0, ctx->stream,
+                           (const double *)ctx->state[ctx->cur], ctx->plane, false, ctx->nx, ctx->pitch, dx,
+                           theta_u, theta_v, rows);
+    else
+        hipLaunchKernelGGL((front_row_kernel<float>), dim3(ctx->ny), dim3(64), 0, ctx->stream,
+                           (const float *)ctx->state[ctx->cur], ctx->plane, lo, ctx->nx, ctx->pitch, dx, theta_u,
+                           theta_v, rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(front_final_kernel, dim3(1), dim3(kReduceThreads), 0, ctx->stream, rows, ctx->ny, out);
     return hipGetLastError();
 }
 

@@ -17,9 +17,13 @@
 //     on its right receives it by a shift; b*dw/dy is shifted as one product;
 //   * the x-difference of w of row q+1 and its right-lane neighbour are kept
 //     for the next row, where they belong to the row being computed;
-//   * the tensor rows (needed by all levels, 2K rows deep) sit in a per-lane LDS
-//     ring, each lane reading only what it wrote, stored as the half face sums
-//     (a_i + a_i+1)/2 and (c_j + c_j+1)/2 that the fluxes use, plus b;
+//   * the tensor rows (needed by all levels) sit in per-lane LDS rings, each lane
+//     reading only what it wrote, stored as the half face sums (a_i + a_i+1)/2
+//     and (c_j + c_j+1)/2 that the fluxes use, plus b.  A row of (a+a')/2 or b
+//     is last read by level K, 2K-1 iterations after it is stored, and a row of
+//     (c+c')/2 one iteration sooner; since levels K..2 read before the store of
+//     an iteration, rings of 2K-1 and 2K-2 rows suffice (2 and 1 for K = 1):
+//     10 KB for FP64 at K = 4, so 16 one-wave workgroups fit a CU's 160 KB;
 //   * the mirrored rows of the no-flux boundary (row -1 = row 0, row ny = row
 //     ny-1) are written into the rings, so rows need no per-row selects.
 // Each level starts one row early (a warm-up row) to produce its carried south
@@ -99,11 +103,11 @@ struct LaneGeom {
     bool store_ok;                         // the lane's columns are outputs of this workgroup
 };
 
-template <typename T, int CPL, int RT>
+template <typename T, int CPL, int RTA, int RTC>
 struct TensorRing {
-    T hA[RT][kWave * CPL];        // (a_i + a_i+1) / 2
-    T B[RT][kWave * CPL];         // b
-    T hC[RT][kWave * CPL];        // (c_j + c_j+1) / 2
+    T hA[RTA][kWave * CPL];       // (a_i + a_i+1) / 2
+    T B[RTA][kWave * CPL];        // b
+    T hC[RTC][kWave * CPL];       // (c_j + c_j+1) / 2
 };
 
 template <int CPL>
@@ -135,9 +139,10 @@ __device__ __forceinline__ void x_difference(const T (&X)[CPL], const ColumnMask
     WRo = WRs;
 }
 
-template <typename T, bool COMP, int CPL, int K, int PH, int S, int RT>
+template <typename T, bool COMP, int CPL, int K, int PH, int S, int RTA, int RTC>
 __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL> &m,
-                                          LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RT> &L, const int r)
+                                          LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RTA, RTC> &L,
+                                          const int r)
 {
     const int q = r - 2 * S + 1;
     if (q < g.lo[S] - 1 || q > g.hi[S]) return;                  // uniform
@@ -166,7 +171,7 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
     const T half = T(0.5), one = T(1);
     const bool real = q >= g.re[S];
     const bool has_n = q + 1 < g.ny;
-    const int ts = tslot<RT>(q), tp = tslot<RT>(q + 1);
+    const int ts = tslot<RTA>(q), tp = tslot<RTA>(q + 1), tc = tslot<RTC>(q);
 
     T W0[CPL], Wp[CPL], U0[CPL], V0[CPL], TY[CPL], BT[CPL], B0[CPL];
 #pragma unroll
@@ -205,7 +210,7 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const T Up = R.U[I][p2][k], Vp = R.V[I][p2][k];
-        const T Bp = L.B[tp][g.own + k], hC = L.hC[ts][g.own + k];
+        const T Bp = L.B[tp][g.own + k], hC = L.hC[tc][g.own + k];
         const T FXw = k > 0 ? FXe[k > 0 ? k - 1 : 0] : FXl;
         const T GXw = k > 0 ? GXe[k > 0 ? k - 1 : 0] : GXl;
         const T Wc = W0[k], Uc = U0[k], Vc = V0[k];
@@ -275,22 +280,22 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
     }
 }
 
-template <typename T, bool COMP, int CPL, int K, int PH, int RT>
+template <typename T, bool COMP, int CPL, int K, int PH, int RTA, int RTC>
 __device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL> &m,
-                                          LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RT> &L, const int r,
-                                          const int r_start, const int r_end)
+                                          LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RTA, RTC> &L,
+                                          const int r, const int r_start, const int r_end)
 {
     if (r < r_start || r > r_end) return;                        // uniform
-    if constexpr (K >= 4) level_row<T, COMP, CPL, K, PH, 4, RT>(A, g, m, R, L, r);
-    if constexpr (K >= 3) level_row<T, COMP, CPL, K, PH, 3, RT>(A, g, m, R, L, r);
-    if constexpr (K >= 2) level_row<T, COMP, CPL, K, PH, 2, RT>(A, g, m, R, L, r);
+    if constexpr (K >= 4) level_row<T, COMP, CPL, K, PH, 4, RTA, RTC>(A, g, m, R, L, r);
+    if constexpr (K >= 3) level_row<T, COMP, CPL, K, PH, 3, RTA, RTC>(A, g, m, R, L, r);
+    if constexpr (K >= 2) level_row<T, COMP, CPL, K, PH, 2, RTA, RTC>(A, g, m, R, L, r);
 
     // tensor row r (requested one iteration ago) into the ring; the c face sum
     // of row r-1 needs row r
     if (r >= r_start + 1 && r <= g.last0) {
         const T half = T(0.5);
         const T aRs = from_right(R.ta[0]);
-        const int ts = tslot<RT>(r), tm = tslot<RT>(r - 1);
+        const int ts = tslot<RTA>(r), tm = tslot<RTC>(r - 1);
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             const T ar = k + 1 < CPL ? R.ta[k + 1 < CPL ? k + 1 : k] : aRs;
@@ -300,7 +305,7 @@ __device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K
             R.cprev[k] = R.tc[k];
         }
     }
-    level_row<T, COMP, CPL, K, PH, 1, RT>(A, g, m, R, L, r);
+    level_row<T, COMP, CPL, K, PH, 1, RTA, RTC>(A, g, m, R, L, r);
 
     // request old-state row r+1 (clamped: rows -1 and ny load their mirrors)
     if (r + 1 <= g.last0) {
@@ -326,17 +331,18 @@ struct DppShape {
     static constexpr int TXW = kWave * CPL;               // columns a wave holds
     static constexpr int H = (K + CPL - 1) / CPL * CPL;   // halo columns on each side
     static constexpr int OUTW = TXW - 2 * H;              // output columns per workgroup
-    static constexpr int RT = 2 * K;                      // tensor ring rows
+    static constexpr int RTA = K >= 2 ? 2 * K - 1 : 2;     // rows of the (a+a')/2 and b rings
+    static constexpr int RTC = K >= 2 ? 2 * K - 2 : 1;     // rows of the (c+c')/2 ring
 };
 
 // One workgroup's strip: output columns [sx*OUTW, sx*OUTW + OUTW) of rows
 // [sy*A.rows, sy*A.rows + A.rows), K steps from A's input to A's output planes.
 template <typename T, bool COMP, int CPL, int K>
 __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, const int sy,
-                                          TensorRing<T, CPL, DppShape<CPL, K>::RT> &L)
+                                          TensorRing<T, CPL, DppShape<CPL, K>::RTA, DppShape<CPL, K>::RTC> &L)
 {
     using Sh = DppShape<CPL, K>;
-    constexpr int RT = Sh::RT;
+    constexpr int RTA = Sh::RTA, RTC = Sh::RTC;
     static_assert(K >= 1 && K <= 4, "fused depth 1..4");
     const int o0 = sx * Sh::OUTW, e0 = o0 - Sh::H;
     LaneGeom<K> g;
@@ -397,19 +403,19 @@ __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, co
     const int r_end = g.hi[K] + 2 * K - 2;
     const int r0 = r_start - pmod(r_start, kPeriod);
     for (int rb = r0; rb <= r_end; rb += kPeriod) {
-        lane_iter<T, COMP, CPL, K, 0, RT>(A, g, m, R, L, rb + 0, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 1, RT>(A, g, m, R, L, rb + 1, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 2, RT>(A, g, m, R, L, rb + 2, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 3, RT>(A, g, m, R, L, rb + 3, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 4, RT>(A, g, m, R, L, rb + 4, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 5, RT>(A, g, m, R, L, rb + 5, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 0, RTA, RTC>(A, g, m, R, L, rb + 0, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 1, RTA, RTC>(A, g, m, R, L, rb + 1, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 2, RTA, RTC>(A, g, m, R, L, rb + 2, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 3, RTA, RTC>(A, g, m, R, L, rb + 3, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 4, RTA, RTC>(A, g, m, R, L, rb + 4, r_start, r_end);
+        lane_iter<T, COMP, CPL, K, 5, RTA, RTC>(A, g, m, R, L, rb + 5, r_start, r_end);
     }
 }
 
 template <typename T, bool COMP, int CPL, int K>
 __global__ __launch_bounds__(kWave) void fused_dpp_kernel(StepArgs<T> A)
 {
-    __shared__ TensorRing<T, CPL, DppShape<CPL, K>::RT> L;
+    __shared__ TensorRing<T, CPL, DppShape<CPL, K>::RTA, DppShape<CPL, K>::RTC> L;
     const int nbx = gridDim.x;
     const int lid = xcd_local_id(blockIdx.x + nbx * blockIdx.y, gridDim.x * gridDim.y);
     dpp_strip<T, COMP, CPL, K>(A, lid % nbx, lid / nbx, L);
@@ -422,7 +428,7 @@ template <typename T, bool COMP, int CPL, int K>
 __global__ __launch_bounds__(kWave) void fused_dpp_batch_kernel(const StepArgs<T> *__restrict__ D,
                                                                 const int *__restrict__ prefix, int n)
 {
-    __shared__ TensorRing<T, CPL, DppShape<CPL, K>::RT> L;
+    __shared__ TensorRing<T, CPL, DppShape<CPL, K>::RTA, DppShape<CPL, K>::RTC> L;
     const int lid = xcd_local_id(blockIdx.x, gridDim.x);
     int lo = 0, hi = n;                    // prefix[lo] <= lid < prefix[hi]
     while (hi - lo > 1) {

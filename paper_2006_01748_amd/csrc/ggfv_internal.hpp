@@ -70,6 +70,7 @@ struct ggfv_ctx {
     int fused_steps = 1;     // time steps per launch (1..4)
     int lane_shift = 0;      // 1: one-wave register/lane-shift kernels (ggfv_fused_dpp.hip)
     ggfv::AdaptCtl *adapt = nullptr;   // adaptive-step control block (lazily allocated)
+    double *front = nullptr;           // front diagnostics: 4 * ny per-row values + 16 results (lazily)
 
     void *adj = nullptr;     // adjoint buffers (see ggfv_adjoint.hip), allocated on first use
     size_t adj_bytes = 0;
@@ -113,6 +114,9 @@ hipError_t launch_step_adaptive(ggfv_ctx *ctx, const void *in, void *out, const 
 // Reset the control block (time t0) and reduce the tensor term and max |1-u| of
 // the context's current state into it.
 hipError_t launch_adapt_init(ggfv_ctx *ctx, AdaptCtl *ctl, double t0);
+// Front diagnostics of the current state: per-row values into rows (4 * ny
+// doubles), the 11 results into out (device).
+hipError_t launch_front_diagnostics(ggfv_ctx *ctx, double theta_u, double theta_v, double *rows, double *out);
 
 struct BatchLaunch {
     int dtype = 0;
