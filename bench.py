@@ -36,7 +36,7 @@ BYTES_PER_CELL = {"f64": 72, "f32c": 60, "f32": 36}
 # Launch shapes of the headline runs: (rows per strip, threads, steps per
 # launch, lane-shift kernels), as the autotuner picks them on MI355X for this
 # workload.
-HEADLINE_SHAPE = {"f64": (32, 64, 4, 1), "f32c": (16, 64, 4, 1), "f32": (64, 64, 4, 1)}
+HEADLINE_SHAPE = {"f64": (32, 64, 4, 1), "f32c": (16, 64, 4, 1), "f32": (32, 64, 4, 1)}
 METRIC = "Gcell-updates/s + % HBM peak, 4096² aniso FV step FP32/FP64; adjoint/fwd ratio"
 # Algorithmic floating-point operations per cell-update (each face flux counted
 # once, shared by its two cells): x/y faces of W 2 x 10, tangential differences
@@ -269,7 +269,7 @@ def time_adaptive(pk, torch, w, steps=200):
             "ms_per_step": ms / steps, "dt_first": float(dts[0]), "dt_last": float(dts[-1])}
 
 
-def time_front_sweep(pk, torch, t_end=0.25):
+def time_front_sweep(pk, torch, t_end=0.5):
     """Invasion sweep (Section 2's propagating fronts and interstitial gap):
     delta1 in {0.5, 0.8, 1.5, 3, 6, 12.5} x vertical/horizontal acid
     diffusivity ratio in {1, 0.2}, 512 x 256 fronts on [0,1] x [0,0.5], FP64,

@@ -288,7 +288,8 @@ int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
 int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
 
 /* Time `trial_steps` steps for each candidate shape (fused depths 1..4, widths
- * 64, 128, 256 and the lane-shift kernels, strip heights from 2 to 128 and the
+ * 64, 128, 256 and the lane-shift kernels, strip heights 2..128 (2, 4, 8, 16, 24, 32,
+ * 48, 64, 128) and the
  * default) on the context's own data, keep the fastest per step as the
  * context's tuning and return it.  The state, simulated time and step count are restored
  * afterwards.  Needs state, tensor and parameters.  Synchronizes. */

@@ -5,7 +5,11 @@
 Every HIP source under ``csrc/`` is compiled with hipcc for gfx950 into one shared
 library next to this file.  Floating-point contraction is off (the step's
 arithmetic order is part of its contract) and packed FP32 instructions are
-disabled.
+disabled.  The optimizer's sinking of common code out of the branches of a
+condition is off: in the register-ring kernels it merges stores to different
+ring slots into one store through a selected address, which moves the rings to
+scratch memory.  The build fails if any kernel uses scratch memory or spills
+(from the compiler's per-kernel resource report).
 """
 from __future__ import annotations
 
@@ -34,7 +38,22 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-result",
+    "-mllvm", "-simplifycfg-sink-common=false",
+    "-Rpass-analysis=kernel-resource-usage",
 ]
+
+
+def scratch_users(text: str):
+    """Kernels whose resource report shows scratch memory or spills."""
+    bad, name = [], None
+    for line in text.splitlines():
+        if "remark: Function Name:" in line:
+            name = line.split("Function Name:")[1].split("[")[0].strip()
+        elif name and ("ScratchSize [bytes/lane]:" in line or "VGPRs Spill:" in line or "SGPRs Spill:" in line):
+            value = line.split(":")[-1].split("[")[0].strip()
+            if value not in ("0", ""):
+                bad.append((name, line.split("remark:")[1].split("[")[0].strip()))
+    return bad
 
 
 def hipcc() -> str:
@@ -65,9 +84,14 @@ def build(verbose: bool = False, extra_flags=()) -> str:
         out, _ = p.communicate()
         text = out.decode(errors="replace")
         # hipcc's host pass does not know the packed-fp32 target feature; harmless
-        lines = [l for l in text.splitlines() if "packed-fp32-ops" not in l and l.strip()]
+        lines = [l for l in text.splitlines()
+                 if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l and l.strip()]
         if p.returncode != 0:
             failed.append((src, "\n".join(lines)))
+            continue
+        bad = scratch_users(text)
+        if bad:
+            failed.append((src, "kernels using scratch memory:\n" + "\n".join(f"  {n}: {w}" for n, w in bad)))
         elif lines and verbose:
             print("\n".join(lines))
     if failed:

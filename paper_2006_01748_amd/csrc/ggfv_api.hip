@@ -665,7 +665,7 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
         cleanup();
         return fail(ctx, GGFV_EHIP, "autotune setup failed");
     }
-    const int heights[8] = {0, 2, 4, 8, 16, 32, 64, 128};
+    const int heights[10] = {0, 2, 4, 8, 16, 24, 32, 48, 64, 128};
     const int widths[4] = {64, 128, 256, 0};     // 0: lane-shift kernels
     bool first = true;
     for (int K = 1; K <= 4 && rc == GGFV_OK; ++K)

@@ -50,15 +50,15 @@ constexpr int kPeriod = 6;    // row-loop unroll: lcm of the ring lengths 3 and 
 //
 // A shift must run with every lane of the wave active: a lane reading from a
 // lane that is masked off does not receive that lane's value.  All shifts here
-// sit in wave-uniform control flow, and the empty volatile asm on the result
-// keeps the compiler from sinking a shift into a per-lane branch of a later
-// select.
+// sit in wave-uniform control flow and outside every ?: operand (which C
+// evaluates conditionally); the DPP builtin is convergent, so the compiler does
+// not move it under a per-lane condition either.  Every value a select chooses
+// between is computed in a statement of its own, so the select stays a select
+// rather than a branch around the computation.
 template <int CTRL>
 __device__ __forceinline__ int dpp_bits(int v)
 {
-    int r = __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
-    asm volatile("" : "+v"(r));
-    return r;
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
 }
 
 template <int CTRL>
@@ -150,10 +150,6 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
     constexpr int q2 = pmod(PH + 1, 2), p2 = pmod(PH, 2);       // rows q and q +- 1
     constexpr int I = S - 1;
 
-    if (q == g.lo[S] - 1) {                  // x-difference of the first row
-        x_difference<T, CPL>(R.W[I][p3], m, A.hx, R.TX[I], R.WR[I]);
-        return;
-    }
     if (q == g.hi[S]) {                      // mirror row ny for level S+1
         if constexpr (S < K) {
             if (q == g.ny) {
@@ -168,9 +164,14 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         return;
     }
 
+    // Row q = lo[S]-1 (the pre-row) runs the same code: what it carries to the
+    // next row is the x-difference and right neighbour of row q+1 = lo[S], which
+    // the first row needs; its other results are discarded or overwritten (its
+    // south-face flux by the warm-up row; below the domain it is 0, the
+    // boundary face of row 0).
     const T half = T(0.5), one = T(1);
     const bool real = q >= g.re[S];
-    const bool has_n = q + 1 < g.ny;
+    const bool has_n = q >= 0 && q + 1 < g.ny;
     const int ts = tslot<RTA>(q), tp = tslot<RTA>(q + 1), tc = tslot<RTC>(q);
 
     T W0[CPL], Wp[CPL], U0[CPL], V0[CPL], TY[CPL], BT[CPL], B0[CPL];
@@ -199,8 +200,10 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         const T ur = k + 1 < CPL ? U0[k1] : uR;
         const T vr = k + 1 < CPL ? V0[k1] : vR;
         const T hA = L.hA[ts][g.own + k];
-        FXe[k] = m.ve[k] ? hA * ((wr - W0[k]) * A.idx) + half * (BT[k] + btr) : T(0);
-        GXe[k] = m.ve[k] ? (one - half * (U0[k] + ur)) * ((vr - V0[k]) * A.idx) : T(0);
+        const T fx = (hA * ((wr - W0[k]) * A.idx) + half * (BT[k] + btr));
+        const T gx = ((one - half * (U0[k] + ur)) * ((vr - V0[k]) * A.idx));
+        FXe[k] = m.ve[k] ? fx : T(0);
+        GXe[k] = m.ve[k] ? gx : T(0);
     }
     // west face of the first column: the left lane's last east face (0 left of
     // column 0, where that face lies outside the domain)
@@ -214,8 +217,10 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         const T FXw = k > 0 ? FXe[k > 0 ? k - 1 : 0] : FXl;
         const T GXw = k > 0 ? GXe[k > 0 ? k - 1 : 0] : GXl;
         const T Wc = W0[k], Uc = U0[k], Vc = V0[k];
-        const T FYn = has_n ? hC * ((Wp[k] - Wc) * A.idy) + half * (B0[k] * R.TX[I][k] + Bp * TXn[k]) : T(0);
-        const T GYn = has_n ? (one - half * (Uc + Up)) * ((Vp - Vc) * A.idy) : T(0);
+        const T fy = (hC * ((Wp[k] - Wc) * A.idy) + half * (B0[k] * R.TX[I][k] + Bp * TXn[k]));
+        const T gy = ((one - half * (Uc + Up)) * ((Vp - Vc) * A.idy));
+        const T FYn = has_n ? fy : T(0);
+        const T GYn = has_n ? gy : T(0);
         const T divW = (FXe[k] - FXw) * A.idx + (FYn - R.FYs[I][k]) * A.idy;
         const T divV = (GXe[k] - GXw) * A.idx + (GYn - R.GYs[I][k]) * A.idy;
         const T fu = Uc * (one - Uc) - (A.d1 * Uc) * Wc;
