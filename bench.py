@@ -413,11 +413,16 @@ def cpu_baseline(w, steps):
 # /tmp with TMPDIR=/tmp; $R is the repository root, $P an output folder.
 PROFILE_COMMANDS = {
     "trace": "timeout -k 10 500 rocprofv3 --kernel-trace --stats --output-format csv -d $P/trace -o trace "
-             "-- python3 $R/bench.py --steps 200 --warmup 12 --no-cpu-baseline > $P/trace_bench.json",
+             "-- python3 $R/bench.py --steps 200 --warmup 12 --no-cpu-baseline --no-fronts > $P/trace_bench.json",
+    "fronts": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/fronts -o fronts "
+              "-- python3 $R/bench.py --variants f64 --no-tune --steps 4 --warmup 4 --no-cpu-baseline --no-adjoint "
+              "--no-ensemble --no-adaptive --no-copy-ceiling --fronts-t 0.02 > $P/fronts_bench.json",
     "fetch": "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $P/fetch -o fetch "
-             "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble",
+             "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble "
+             "--no-adaptive --no-fronts",
     "write": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/write -o write "
-             "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble",
+             "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble "
+             "--no-adaptive --no-fronts",
 }
 
 
@@ -514,7 +519,8 @@ def summarize_profiles(pdir):
                 f"```\n{cmds}\n```\n\nSummary written by `python bench.py --summarize-profiles $P`.\n\n"
                 "## Kernel trace (--stats), 4096^2 step kernels and diagnostics\n\n" + head +
                 stat_rows(lambda k: k.startswith(("step_kernel<", "fused_dpp_kernel<", "fused_kernel<",
-                                                  "diag_kernel", "diag_final")) and not k.endswith(", 64>")) +
+                                                  "step_adaptive_kernel<", "adapt_", "diag_kernel", "diag_final"))
+                          and not k.endswith(", 64>")) +
                 "\n\nAverage launch time measured live by bench.py with HIP events in the same traced run "
                 "(headline shapes): " + ", ".join(f"{v} {us:.1f} us" for v, us in live.items()) + ".\n\n"
                 "## HBM traffic per dispatch (--pmc, one counter per run)\n\n"
@@ -547,6 +553,26 @@ def summarize_profiles(pdir):
                 + "\n\n`step_kernel<double, false, 1, 64>` is the 512^2 forward step (checkpointed forward and "
                 "the recomputation of each segment in the reverse sweep).  bench.py in the same run: "
                 f"backward / forward = {adj.get('backward_over_forward', float('nan')):.2f}.\n")
+    fdir = os.path.join(pdir, "fronts")
+    if os.path.isdir(fdir):
+        fstats = {}
+        with open(os.path.join(fdir, "fronts_kernel_stats.csv")) as f:
+            for row in csv.DictReader(f):
+                fstats[_short(row["Name"])] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3,
+                                              float(row["MinNs"]) / 1e3, float(row["MaxNs"]) / 1e3)
+        with open(os.path.join(pdir, "fronts_bench.json")) as f:
+            fb = json.loads(f.read().strip().splitlines()[-1])["front_sweep"]
+        rows = [f"| {k} | {n} | {avg:.1f} | {lo:.1f} | {hi:.1f} |"
+                for k, (n, avg, lo, hi) in sorted(fstats.items(), key=lambda x: -x[1][0] * x[1][1])
+                if k.startswith(("fused_dpp_batch_kernel", "step_batch_kernel", "front_"))]
+        with open(os.path.join(here, "profiles", "front_sweep_kernels_512x256.md"), "w") as f:
+            f.write("# Invasion sweep: 12 fronts of 512x256 (delta1 sweep x 2 acid anisotropies), FP64 (rocprofv3)\n\n"
+                    f"Command (from /tmp with TMPDIR=/tmp):\n\n```\n{PROFILE_COMMANDS['fronts']}\n```\n\n"
+                    "## Kernel trace (--stats)\n\n" + head + "\n".join(rows) +
+                    "\n\n`fused_dpp_batch_kernel<double, false, 1, 4>` steps all twelve fronts 4 steps per launch; "
+                    "`front_row_kernel` / `front_final_kernel` are the front and gap diagnostics (one wave per row, "
+                    f"then a fixed-order reduction).  bench.py in the same run: {fb['value']:.1f} Gcell/s over "
+                    f"{fb['workload']}.\n")
     print(json.dumps({"calibration": {"fetch": f_scale, "write": w_scale}, "traffic": traffic}, indent=1))
 
 
@@ -564,6 +590,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-fronts", action="store_true")
+    ap.add_argument("--fronts-t", type=float, default=0.5, help="simulated time of the invasion sweep")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner for the headline shape instead of the fixed shapes")
@@ -630,7 +657,7 @@ def main():
     fronts = None
     if not args.no_fronts:
         log("timing the invasion sweep (fronts and interstitial gap)")
-        fronts = time_front_sweep(pk, torch)
+        fronts = time_front_sweep(pk, torch, t_end=args.fronts_t)
         log(f"  {fronts['value']:.1f} Gcell/s; gaps " +
             ", ".join(f"d={x['delta1']}/k={x['kappa']:.1f}: {x['gap_mean'] if x['gap_mean'] is None else round(x['gap_mean'], 4)}"
                       for x in fronts["instances"]))
