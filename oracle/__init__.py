@@ -20,6 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ggfv_oracle.c")
 _SRC_ADJ = os.path.join(_HERE, "ggfv_oracle_adjoint.c")
+_SRC_3D = os.path.join(_HERE, "ggfv_oracle3d.c")
 LIB_PATH = os.path.join(_HERE, "libggfv_oracle.so")
 CFLAGS = ["-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-std=c11"]
 
@@ -28,7 +29,7 @@ _D = ctypes.POINTER(ctypes.c_double)
 
 
 def sources():
-    return [p for p in (_SRC, _SRC_ADJ) if os.path.exists(p)]
+    return [p for p in (_SRC, _SRC_ADJ, _SRC_3D) if os.path.exists(p)]
 
 
 def build(force: bool = True) -> str:
@@ -82,6 +83,14 @@ def bind(lib):
     lib.orc_adaptive_dt.restype = d
     lib.orc_run_adaptive.argtypes = [i, i, d, d, p, d, l, p, p, p, p, p, p, p, p]
     lib.orc_front_diag.argtypes = [i, i, d, p, p, d, d, p]
+    pp = ctypes.POINTER(_D)
+    lib.orc3_div_w.argtypes = [i, i, i, d, d, d, p, pp, p]
+    lib.orc3_div_v.argtypes = [i, i, i, d, d, d, p, p, p]
+    lib.orc3_step.argtypes = [i, i, i, d, d, d, p, d, p, p, p, pp, p, p, p]
+    lib.orc3_run.argtypes = [i, i, i, d, d, d, p, d, l, p, p, p, pp]
+    lib.orc3_stable_dt.argtypes = [i, i, i, d, d, d, pp, d, d]
+    lib.orc3_stable_dt.restype = d
+    lib.orc3_mass.argtypes = [i, i, i, d, d, d, p, p, p, p]
     lib.orc_front_speed.argtypes = [d, d, d, d, d, d, d]
     lib.orc_front_speed.restype = d
     lib.orc_adjoint_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p,
@@ -213,6 +222,75 @@ def front_speed(mass0, mass1, t0, t1, ly=1.0, behind=1.0, ahead=0.0) -> float:
     """LeVeque-Yee space-averaged front speed from two masses of one population."""
     return _load().orc_front_speed(float(mass0), float(mass1), float(t0), float(t1), float(ly),
                                    float(behind), float(ahead))
+
+
+# ---------------------------------------------------------------------------
+# three dimensions: fields of shape (nz, ny, nx), the tensor as the six fields
+# (axx, ayy, azz, axy, axz, ayz)
+
+def _tensor3(A):
+    arrs = [_f64(x) for x in A]
+    if len(arrs) != 6:
+        raise ValueError("the 3D tensor has six fields (axx, ayy, azz, axy, axz, ayz)")
+    ptrs = (ctypes.POINTER(ctypes.c_double) * 6)(*[_ptr(x) for x in arrs])
+    return arrs, ptrs
+
+
+def div_w3(W, A, lx=1.0, ly=1.0, lz=1.0):
+    """div(A grad W) of the 3D scheme (19-point stencil in flux form)."""
+    W = _f64(W)
+    nz, ny, nx = W.shape
+    keep, ptrs = _tensor3(A)
+    out = np.empty_like(W)
+    _load().orc3_div_w(nx, ny, nz, lx, ly, lz, _ptr(W), ptrs, _ptr(out))
+    return out
+
+
+def div_v3(U, V, lx=1.0, ly=1.0, lz=1.0):
+    """div((1-U) grad V) of the 3D scheme (7-point stencil in flux form)."""
+    U, V = _f64(U), _f64(V)
+    nz, ny, nx = V.shape
+    out = np.empty_like(V)
+    _load().orc3_div_v(nx, ny, nz, lx, ly, lz, _ptr(U), _ptr(V), _ptr(out))
+    return out
+
+
+def step3(u, v, w, A, params, dt, lx=1.0, ly=1.0, lz=1.0):
+    """One step of the 3D scheme; returns new (u, v, w)."""
+    u, v, w = (_f64(x) for x in (u, v, w))
+    nz, ny, nx = u.shape
+    keep, ptrs = _tensor3(A)
+    prm = _f64(params)
+    un, vn, wn = np.empty_like(u), np.empty_like(v), np.empty_like(w)
+    _load().orc3_step(nx, ny, nz, lx, ly, lz, _ptr(prm), float(dt), _ptr(u), _ptr(v), _ptr(w), ptrs,
+                      _ptr(un), _ptr(vn), _ptr(wn))
+    return un, vn, wn
+
+
+def run3(u, v, w, A, params, dt, nsteps, lx=1.0, ly=1.0, lz=1.0):
+    """nsteps steps of the 3D scheme; returns (u, v, w)."""
+    u, v, w = (np.array(x, dtype=np.float64, copy=True, order="C") for x in (u, v, w))
+    nz, ny, nx = u.shape
+    keep, ptrs = _tensor3(A)
+    prm = _f64(params)
+    _load().orc3_run(nx, ny, nz, lx, ly, lz, _ptr(prm), float(dt), int(nsteps), _ptr(u), _ptr(v), _ptr(w),
+                     ptrs)
+    return u, v, w
+
+
+def stable_dt3(A, Delta2, safety, lx=1.0, ly=1.0, lz=1.0) -> float:
+    """Explicit step bound of the 3D scheme (Gershgorin bound of max lambda)."""
+    keep, ptrs = _tensor3(A)
+    nz, ny, nx = keep[0].shape
+    return _load().orc3_stable_dt(nx, ny, nz, lx, ly, lz, ptrs, float(Delta2), float(safety))
+
+
+def mass3(u, v, w, lx=1.0, ly=1.0, lz=1.0):
+    u, v, w = (_f64(x) for x in (u, v, w))
+    nz, ny, nx = u.shape
+    out = np.zeros(3)
+    _load().orc3_mass(nx, ny, nz, lx, ly, lz, _ptr(u), _ptr(v), _ptr(w), _ptr(out))
+    return out
 
 
 def diagnostics(u, v, w, a, b, c, Delta2, dt, lx=1.0, ly=1.0) -> dict:

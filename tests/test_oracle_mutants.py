@@ -13,6 +13,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_3d as o3
 import test_oracle_adaptive as adapt
 import test_oracle_front as front
 import test_oracle_adjoint as adj
@@ -85,6 +86,31 @@ ADJ_MUTANTS = [
     ("growth adjoint of v", "(1.0 + dt * r2 * (1.0 - 2.0 * v[k]))", "(1.0 + dt * r2 * (1.0 - v[k]))", 1),
 ]
 
+MUTANTS_3D = [
+    ("3D tz one-sided", "return (W[IX3(i, j, clamp3(k + 1, nz))] - W[IX3(i, j, clamp3(k - 1, nz))]) * hz;",
+     "return (W[IX3(i, j, clamp3(k + 1, nz))] - W[IX3(i, j, k)]) * hz;", 1),
+    ("3D axz on the y faces", "0.5 * (axy[l] * txl + axy[r] * txr) + 0.5 * (ayz[l] * tzl + ayz[r] * tzr);",
+     "0.5 * (axy[l] * txl + axy[r] * txr) + 0.5 * (axz[l] * tzl + axz[r] * tzr);", 1),
+    ("3D z face without its cross terms", "0.5 * (axz[l] * txl + axz[r] * txr) + 0.5 * (ayz[l] * tyl + ayz[r] * tyr);",
+     "0.0;", 1),
+    ("3D z mobility of one cell", "GZ[l] = (1.0 - 0.5 * (U[l] + U[r])) * ((V[r] - V[l]) * idz);",
+     "GZ[l] = (1.0 - U[l]) * ((V[r] - V[l]) * idz);", 1),
+    ("3D idz on the z divergence dropped", "+ (FZ[c] - fb) * idz;", "+ (FZ[c] - fb);", 1),
+    ("3D bound without the off-diagonals", "double r0 = fabs(axx[c]) + fabs(axy[c]) + fabs(axz[c]);",
+     "double r0 = fabs(axx[c]);", 1),
+]
+
+PINS_3D = [
+    lambda o: o3.test_3d_one_layer_is_the_2d_scheme(o),
+    lambda o: o3.test_3d_isotropic_is_7point_laplacian(o),
+    lambda o: o3.test_3d_eigenmode_decay_diagonal_tensor(1, 2, 1, o),
+    lambda o: o3.test_3d_step_bound_is_the_stability_limit(1.05, o),
+    lambda o: o3.test_3d_mass_conservation(o),
+    lambda o: o3.test_3d_operator_symmetry_and_null_space(o),
+    lambda o: o3.test_3d_relabelled_axes(o),
+    lambda o: o3.test_3d_step_bound_covers_the_largest_eigenvalue(o),
+]
+
 ADJ_PINS = [
     lambda: adj.test_state_adjoint_dot_identity(13, 9),
     lambda: adj.test_state_adjoint_dot_identity(1, 6),
@@ -151,3 +177,25 @@ def test_adjoint_pins_catch_mutant(name, old, new, count):
         finally:
             oracle.restore_library(prev)
     assert caught, f"no adjoint pin caught the planted mistake '{name}'"
+
+
+@pytest.mark.parametrize("name,old,new,count", MUTANTS_3D, ids=[m[0] for m in MUTANTS_3D])
+def test_3d_pins_catch_mutant(name, old, new, count):
+    base = open(oracle._SRC_3D).read()
+    assert base.count(old) == count, f"mutation anchor for '{name}' not found"
+    mutated = base.replace(old, new)
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _build_mutant(tmp, mutated, "ggfv_oracle3d.c")
+        oracle.build(force=False)
+        prev = oracle.use_library(lib)
+        caught = False
+        try:
+            for pin in PINS_3D:
+                try:
+                    pin(oracle)
+                except AssertionError:
+                    caught = True
+                    break
+        finally:
+            oracle.restore_library(prev)
+    assert caught, f"no 3D pin caught the planted mistake '{name}'"
