@@ -317,6 +317,43 @@ def time_front_sweep(pk, torch, t_end=0.5):
             "value": cells * n / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "ms": ms, "instances": out}
 
 
+def time_3d(pk, torch, n=256, steps=100, warmup=10, dtypes=("f64", "f32")):
+    """Three-dimensional step on the 256^3 slab tissue (19-point acid stencil,
+    7-point tumour-cell stencil): `steps` steps of the step kernel per dtype,
+    timed with HIP events on the context's stream.  Algorithmic bytes per
+    cell-update: 3 state values read, 6 tensor values read, 3 written."""
+    from paper_2006_01748_amd import workloads as wl
+    w = wl.tissue3(n=n)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"slab tissue {w.nx}x{w.ny}x{w.nz}, 8 z-slabs of random SPD tensors, tumour ball, "
+                       f"dt=0.9 of the step bound, {steps} steps", "variants": {}}
+    for dt_name in dtypes:
+        ctx = pk.Context3(w.nx, w.ny, w.nz, w.lx, w.ly, w.lz, dtype=dt_name, stream=stream.cuda_stream)
+        ctx.set_params(w.params)
+        ctx.set_tensor(*w.tensor)
+        ctx.set_state(w.u0, w.v0, w.w0)
+        dt = ctx.stable_dt(w.safety)
+        ctx.step(dt, warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.step(dt, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        mass = ctx.mass()
+        ctx.close()
+        per = 12 * (8 if dt_name == "f64" else 4)
+        us = ms * 1e3 / steps
+        gbs = w.cells * per / (us * 1e-6) / 1e9
+        out["variants"][dt_name] = {
+            "value": w.cells * steps / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "kernel_avg_us": us,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS, "traffic": None},
+            "bytes_per_cell_update": per, "dt": dt, "mass": list(mass)}
+    return out
+
+
 def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50, force=None):
     """Ensemble workload: `count` instances (sides 64..512, own parameters, tensor
     and dt), compensated FP32.  Batched graph-replayed run versus a loop of
@@ -590,6 +627,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-fronts", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--fronts-t", type=float, default=0.5, help="simulated time of the invasion sweep")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
     ap.add_argument("--autotune", action="store_true",
@@ -661,6 +699,12 @@ def main():
         log(f"  {fronts['value']:.1f} Gcell/s; gaps " +
             ", ".join(f"d={x['delta1']}/k={x['kappa']:.1f}: {x['gap_mean'] if x['gap_mean'] is None else round(x['gap_mean'], 4)}"
                       for x in fronts["instances"]))
+    three = None
+    if not args.no_3d:
+        log("timing the three-dimensional step (256^3 slab tissue)")
+        three = time_3d(pk, torch)
+        log("  " + ", ".join(f"{k}: {v['value']:.1f} Gcell/s, {v['kernel_avg_us']:.0f} us, "
+                             f"{100 * v['roofline']['frac']:.1f}% of HBM" for k, v in three["variants"].items()))
     ens = None
     if not args.no_ensemble:
         log("timing the ensemble (batched graph vs loop of single launches)")
@@ -715,6 +759,7 @@ def main():
         "adjoint": adj,
         "adaptive": adaptive,
         "front_sweep": fronts,
+        "three_d": three,
         "ensemble": ens,
         "copy_ceiling_GBs": ceiling,
         "mass_log": r["mass_log"],

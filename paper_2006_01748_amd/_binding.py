@@ -1,4 +1,4 @@
-"""ctypes binding of ``libggfv.so`` (the C ABI of include/ggfv.h).
+"""ctypes binding of ``libggfv.so`` (the C ABI of include/ggfv.h and include/ggfv3.h).
 
 Argument marshalling only: every step of the computation runs in the HIP
 library.  Arrays may be numpy arrays (host memory) or torch tensors; a torch
@@ -64,6 +64,20 @@ _SIGNATURES = [
     ("ggfv_batch_last_error", _c.c_char_p, [_VP]),
     ("ggfv_last_error", _c.c_char_p, [_VP]),
     ("ggfv_status_string", _c.c_char_p, [_c.c_int]),
+    # include/ggfv3.h
+    ("ggfv3_create", _c.c_int, [_c.POINTER(_VP), _c.c_int, _c.c_int, _c.c_int, _c.c_double, _c.c_double,
+                                _c.c_double, _c.c_int, _c.c_int, _VP]),
+    ("ggfv3_destroy", None, [_VP]),
+    ("ggfv3_set_params", _c.c_int, [_VP, _VP]),
+    ("ggfv3_set_tensor", _c.c_int, [_VP] + [_VP] * 6 + [_c.c_int, _c.c_int]),
+    ("ggfv3_set_state", _c.c_int, [_VP, _VP, _VP, _VP, _c.c_int, _c.c_int]),
+    ("ggfv3_get_state", _c.c_int, [_VP, _VP, _VP, _VP, _c.c_int, _c.c_int]),
+    ("ggfv3_stable_dt", _c.c_int, [_VP, _c.c_double, _c.POINTER(_c.c_double)]),
+    ("ggfv3_step", _c.c_int, [_VP, _c.c_double, _c.c_longlong]),
+    ("ggfv3_mass", _c.c_int, [_VP, _c.POINTER(_c.c_double)]),
+    ("ggfv3_time", _c.c_int, [_VP, _c.POINTER(_c.c_double), _c.POINTER(_c.c_longlong)]),
+    ("ggfv3_set_tuning", _c.c_int, [_VP, _c.c_int]),
+    ("ggfv3_last_error", _c.c_char_p, [_VP]),
 ]
 
 
@@ -165,6 +179,50 @@ def _current_stream():
     return ctypes.c_void_p(t.cuda.current_stream().cuda_stream)
 
 
+def _prep_arrays(arrays, count):
+    """(pointers, where, io, keepalive) for input arrays of `count` values each."""
+    if all(_is_device_tensor(x) for x in arrays):
+        xs = [x.contiguous() for x in arrays]
+        io = _io_of(xs[0])
+        if any(_io_of(x) != io for x in xs):
+            raise TypeError("all arrays must share a dtype")
+        for x in xs:
+            if x.numel() != count:
+                raise ValueError(f"expected {count} values, got {x.numel()}")
+        return [ctypes.c_void_p(x.data_ptr()) for x in xs], GGFV_DEVICE, io, xs
+    xs = []
+    for x in arrays:
+        if _torch() is not None and isinstance(x, _torch().Tensor):
+            x = x.cpu().numpy()
+        x = np.asarray(x)
+        if x.dtype not in (np.float32, np.float64):
+            x = x.astype(np.float64)
+        x = np.ascontiguousarray(x)
+        if x.size != count:
+            raise ValueError(f"expected {count} values, got {x.size}")
+        xs.append(x)
+    io = _io_of(xs[0])
+    xs = [x.astype(xs[0].dtype, copy=False) for x in xs]
+    return [x.ctypes.data_as(ctypes.c_void_p) for x in xs], GGFV_HOST, io, xs
+
+
+def _call_out3(obj, fn, outs, count):
+    """Call fn(handle, p0, p1, p2, where, io) into three outputs of `count` values."""
+    if all(_is_device_tensor(x) for x in outs):
+        for x in outs:
+            if not x.is_contiguous() or x.numel() != count:
+                raise ValueError(f"device outputs must be contiguous with {count} values")
+        ptrs = [ctypes.c_void_p(x.data_ptr()) for x in outs]
+        obj._check(fn(obj._h, *ptrs, GGFV_DEVICE, _io_of(outs[0])))
+    else:
+        for x in outs:
+            if not (isinstance(x, np.ndarray) and x.flags.c_contiguous and x.size == count):
+                raise ValueError(f"host outputs must be contiguous numpy arrays with {count} values")
+        ptrs = [x.ctypes.data_as(ctypes.c_void_p) for x in outs]
+        obj._check(fn(obj._h, *ptrs, GGFV_HOST, _io_of(outs[0])))
+    return tuple(outs)
+
+
 class Context:
     """One grid, its tensor, parameters and state on one GPU (see include/ggfv.h)."""
 
@@ -218,30 +276,7 @@ class Context:
         return self._h
 
     def _prep_in(self, arrays):
-        """Returns (pointers, where, io, keepalive) for three input arrays."""
-        if all(_is_device_tensor(x) for x in arrays):
-            xs = [x.contiguous() for x in arrays]
-            io = _io_of(xs[0])
-            if any(_io_of(x) != io for x in xs):
-                raise TypeError("all three arrays must share a dtype")
-            for x in xs:
-                if x.numel() != self.nx * self.ny:
-                    raise ValueError(f"expected {self.nx * self.ny} values, got {x.numel()}")
-            return [ctypes.c_void_p(x.data_ptr()) for x in xs], GGFV_DEVICE, io, xs
-        xs = []
-        for x in arrays:
-            if _torch() is not None and isinstance(x, _torch().Tensor):
-                x = x.cpu().numpy()
-            x = np.asarray(x)
-            if x.dtype not in (np.float32, np.float64):
-                x = x.astype(np.float64)
-            x = np.ascontiguousarray(x)
-            if x.size != self.nx * self.ny:
-                raise ValueError(f"expected {self.nx * self.ny} values, got {x.size}")
-            xs.append(x)
-        io = _io_of(xs[0])
-        xs = [x.astype(xs[0].dtype, copy=False) for x in xs]
-        return [x.ctypes.data_as(ctypes.c_void_p) for x in xs], GGFV_HOST, io, xs
+        return _prep_arrays(arrays, self.nx * self.ny)
 
     def _out(self, out, dtype):
         if out is not None:
@@ -250,17 +285,7 @@ class Context:
         return [np.empty((self.ny, self.nx), dtype=dt) for _ in range(3)]
 
     def _call_out(self, fn, out, dtype):
-        outs = self._out(out, dtype)
-        if all(_is_device_tensor(x) for x in outs):
-            for x in outs:
-                if not x.is_contiguous() or x.numel() != self.nx * self.ny:
-                    raise ValueError("device outputs must be contiguous with nx*ny values")
-            ptrs = [ctypes.c_void_p(x.data_ptr()) for x in outs]
-            self._check(fn(self._h, *ptrs, GGFV_DEVICE, _io_of(outs[0])))
-        else:
-            ptrs = [x.ctypes.data_as(ctypes.c_void_p) for x in outs]
-            self._check(fn(self._h, *ptrs, GGFV_HOST, _io_of(outs[0])))
-        return tuple(outs)
+        return _call_out3(self, fn, self._out(out, dtype), self.nx * self.ny)
 
     # -- API ---------------------------------------------------------------
     def set_stream(self, stream):
@@ -483,3 +508,90 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Context3:
+    """One three-dimensional grid, its tensor, parameters and state on one GPU
+    (see include/ggfv3.h).  Arrays are (nz, ny, nx), x fastest."""
+
+    def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, dtype="f64", device=0, stream=None):
+        self._lib = lib()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.lx, self.ly, self.lz = float(lx), float(ly), float(lz)
+        self.dtype = dtype
+        if dtype not in ("f64", "f32"):
+            raise ValueError("Context3 dtype must be 'f64' or 'f32'")
+        h = ctypes.c_void_p()
+        if stream is None:
+            stream = _current_stream()
+        rc = self._lib.ggfv3_create(ctypes.byref(h), self.nx, self.ny, self.nz, self.lx, self.ly, self.lz,
+                                    DTYPES[dtype], int(device), stream)
+        if rc != GGFV_OK:
+            why = self._lib.ggfv3_last_error(None).decode()
+            raise GGFVError(rc, f"ggfv3_create({nx}, {ny}, {nz}, {dtype}, device={device}) failed: {why}")
+        self._h = h
+
+    @property
+    def count(self):
+        return self.nx * self.ny * self.nz
+
+    def _check(self, rc):
+        if rc != GGFV_OK:
+            raise GGFVError(rc, self._lib.ggfv3_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ggfv3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_params(self, params):
+        p = Params(*[float(x) for x in params])
+        self._check(self._lib.ggfv3_set_params(self._h, ctypes.byref(p)))
+
+    def set_tensor(self, axx, ayy, azz, axy, axz, ayz):
+        ptrs, where, io, keep = _prep_arrays((axx, ayy, azz, axy, axz, ayz), self.count)
+        self._check(self._lib.ggfv3_set_tensor(self._h, *ptrs, where, io))
+
+    def set_state(self, u, v, w):
+        ptrs, where, io, keep = _prep_arrays((u, v, w), self.count)
+        self._check(self._lib.ggfv3_set_state(self._h, *ptrs, where, io))
+
+    def get_state(self, out=None, dtype="f64"):
+        if out is None:
+            dt = np.float64 if dtype == "f64" else np.float32
+            out = [np.empty((self.nz, self.ny, self.nx), dtype=dt) for _ in range(3)]
+        return _call_out3(self, self._lib.ggfv3_get_state, out, self.count)
+
+    def stable_dt(self, safety):
+        d = ctypes.c_double()
+        self._check(self._lib.ggfv3_stable_dt(self._h, float(safety), ctypes.byref(d)))
+        return d.value
+
+    def step(self, dt, nsteps=1):
+        self._check(self._lib.ggfv3_step(self._h, float(dt), int(nsteps)))
+
+    def mass(self):
+        m = (ctypes.c_double * 3)()
+        self._check(self._lib.ggfv3_mass(self._h, m))
+        return tuple(m)
+
+    def time(self):
+        t, n = ctypes.c_double(), ctypes.c_longlong()
+        self._check(self._lib.ggfv3_time(self._h, ctypes.byref(t), ctypes.byref(n)))
+        return t.value, n.value
+
+    def set_tuning(self, z_per_strip=0):
+        self._check(self._lib.ggfv3_set_tuning(self._h, int(z_per_strip)))

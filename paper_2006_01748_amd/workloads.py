@@ -19,6 +19,9 @@ below are synthetic and stand in for "tissue-like" anisotropic media:
 * ``cfg3`` ensembles of uneven square instances (64..512) with per-instance
   parameters.
 * ``cfg4`` 512x512 smooth anisotropic field for gradient runs.
+* ``tissue3`` 256^3 three-dimensional slab tissue (the model is stated for
+  dimension 2 or 3): eight z-slabs of piecewise-constant random SPD tensors with
+  a per-cell perturbation, one central tumour ball.
 
 Every random draw uses ``numpy.random.Generator(PCG64(seed))``.
 """
@@ -287,3 +290,70 @@ def random_abc(rng: np.random.Generator, nx: int, ny: int):
     c = rng.uniform(0.5, 2.0, size=(ny, nx))
     b = rng.uniform(-0.9, 0.9, size=(ny, nx)) * np.sqrt(a * c)
     return a, b, c
+
+
+def random_tensor3(rng: np.random.Generator, nx: int, ny: int, nz: int, corr: float = 0.45):
+    """Per-cell random SPD 3x3 tensor (axx, ayy, azz, axy, axz, ayz): diagonal
+    uniform in [0.5, 2], off-diagonal a_ij = r sqrt(a_ii a_jj) with |r| < corr.
+    The correlation matrix has unit diagonal and off-diagonals below corr in
+    magnitude, so for corr < 1/2 it (hence the tensor) is positive definite."""
+    shape = (nz, ny, nx)
+    axx, ayy, azz = (rng.uniform(0.5, 2.0, size=shape) for _ in range(3))
+    axy = rng.uniform(-corr, corr, size=shape) * np.sqrt(axx * ayy)
+    axz = rng.uniform(-corr, corr, size=shape) * np.sqrt(axx * azz)
+    ayz = rng.uniform(-corr, corr, size=shape) * np.sqrt(ayy * azz)
+    return axx, ayy, azz, axy, axz, ayz
+
+
+def random_state3(rng: np.random.Generator, nx: int, ny: int, nz: int):
+    """Uniform [0, 1] state (u, v, w) of shape (nz, ny, nx) for operator tests."""
+    return tuple(rng.uniform(0.0, 1.0, size=(nz, ny, nx)) for _ in range(3))
+
+
+@dataclasses.dataclass
+class Workload3:
+    """One synthetic three-dimensional run."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    lx: float
+    ly: float
+    lz: float
+    params: tuple
+    u0: np.ndarray                # (nz, ny, nx) float64, x fastest
+    v0: np.ndarray
+    w0: np.ndarray
+    tensor: tuple                 # (axx, ayy, azz, axy, axz, ayz)
+    safety: float = 0.9
+    steps: int = 1
+    seed: int = 0
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def tissue3(seed: int = BASE_SEED + 30, n: int = 256, nz: Optional[int] = None, steps: int = 100,
+            slabs: int = 8) -> Workload3:
+    """Three-dimensional slab tissue on the unit cube: ``slabs`` layers along z,
+    each with one random SPD tensor (random_tensor3 of a single cell), every cell
+    scaled by a factor uniform in [0.9, 1.1]; a tumour ball of radius 0.15 at the
+    centre (v = 1, u = 0 inside; u = 1, v = 0 outside), no acid.  Parameters
+    PARAMS_REF."""
+    nz = n if nz is None else nz
+    rng = np.random.Generator(np.random.PCG64(seed))
+    slab = [random_tensor3(rng, 1, 1, 1) for _ in range(slabs)]
+    layer = np.minimum((np.arange(nz) * slabs) // nz, slabs - 1)
+    scale = rng.uniform(0.9, 1.1, size=(nz, n, n))
+    tensor = tuple(np.ascontiguousarray(np.array([slab[layer[k]][q][0, 0, 0] for k in range(nz)])[:, None, None]
+                                        * scale) for q in range(6))
+    x = (np.arange(n) + 0.5) / n
+    z = (np.arange(nz) + 0.5) / nz
+    r2 = (x[None, None, :] - 0.5) ** 2 + (x[None, :, None] - 0.5) ** 2 + (z[:, None, None] - 0.5) ** 2
+    v = (r2 < 0.15 ** 2).astype(np.float64)
+    u = 1.0 - v
+    w = np.zeros_like(v)
+    return Workload3(f"tissue3 {n}x{n}x{nz}", n, n, nz, 1.0, 1.0, 1.0, PARAMS_REF, u, v, w, tensor,
+                     steps=steps, seed=seed)

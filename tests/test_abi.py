@@ -1,8 +1,9 @@
 """Host-side checks of the C ABI: the built library loads, exports every function
-that include/ggfv.h declares, the binding covers exactly those, argument checks
+that include/*.h declare, the binding covers exactly those, argument checks
 that run before any device work reject bad input, and the product path has no
 CPU fallback.  No GPU is used."""
 import ctypes
+import glob
 import os
 import re
 import subprocess
@@ -13,13 +14,15 @@ import paper_2006_01748_amd as pk
 from paper_2006_01748_amd import _binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ggfv.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def header_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ggfv_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(ggfv3?_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -87,3 +90,25 @@ def test_create_failure_message_is_reported(built):
     h = ctypes.c_void_p()
     assert lib.ggfv_create(ctypes.byref(h), 0, 5, 1.0, 1.0, pk.GGFV_F64, 0, None) == pk.GGFV_EINVAL
     assert b"grid" in lib.ggfv_last_error(None)
+
+
+@pytest.mark.parametrize("nx,ny,nz,lz,dtype", [
+    (0, 4, 4, 1.0, pk.GGFV_F64), (4, 4, -2, 1.0, pk.GGFV_F64), (4, 4, 4, 0.0, pk.GGFV_F64),
+    (4, 4, 4, float("inf"), pk.GGFV_F64), (4, 4, 4, 1.0, pk.GGFV_F32C), (2048, 2048, 2048, 1.0, pk.GGFV_F64)])
+def test_create3_rejects_bad_arguments_before_device_work(built, nx, ny, nz, lz, dtype):
+    lib = pk.lib()
+    h = ctypes.c_void_p(123)
+    rc = lib.ggfv3_create(ctypes.byref(h), nx, ny, nz, 1.0, 1.0, lz, dtype, 0, None)
+    assert rc == pk.GGFV_EINVAL
+    assert h.value is None
+    assert lib.ggfv3_last_error(None) != b""
+
+
+def test_null_context3_is_rejected(built):
+    lib = pk.lib()
+    assert lib.ggfv3_step(None, 1e-3, 1) == pk.GGFV_EINVAL
+    assert lib.ggfv3_set_params(None, None) == pk.GGFV_EINVAL
+    assert lib.ggfv3_mass(None, None) == pk.GGFV_EINVAL
+    assert lib.ggfv3_set_tuning(None, 4) == pk.GGFV_EINVAL
+    assert lib.ggfv3_create(None, 4, 4, 4, 1.0, 1.0, 1.0, pk.GGFV_F64, 0, None) == pk.GGFV_EINVAL
+    lib.ggfv3_destroy(None)

@@ -1,0 +1,196 @@
+"""GPU parity of the three-dimensional step (include/ggfv3.h) against the 3D
+oracle: the scheme of Section 2 in flux form in three directions (19-point acid
+stencil with the full symmetric tensor, 7-point tumour-cell stencil, reactions
+and forward Euler of eq. (3), zero boundary flux).
+
+Bar: FP64 states bit for bit (both sides evaluate the same FP64 expressions in
+the same order, with no contraction into FMA); the FP64 step bound bit for bit
+(a maximum of identically computed row sums); masses within 1e-13 relative
+(the reduction order differs).  FP32 against the FP64 oracle run on the
+FP32-rounded inputs: 5e-4 of the field's range after 20 steps (the 2D FP32
+bar; each step adds a few FP32 roundings of O(1) values, damped by the stable
+step).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_01748_amd as pk
+from paper_2006_01748_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SEED = wl.BASE_SEED + 900
+PRM = (12.5, 1.0, 0.05, 70.0, 60.0)
+
+
+def rng(k):
+    return np.random.Generator(np.random.PCG64(SEED + k))
+
+
+def inputs(nx, ny, nz, k):
+    g = rng(k)
+    A = wl.random_tensor3(g, nx, ny, nz)
+    u, v, w = wl.random_state3(g, nx, ny, nz)
+    return (u, v, w), A
+
+
+def ctx_of(nx, ny, nz, state, A, dtype="f64", prm=PRM, L=(1.0, 1.0, 1.0), zs=0):
+    ctx = pk.Context3(nx, ny, nz, *L, dtype=dtype)
+    ctx.set_params(prm)
+    ctx.set_tensor(*A)
+    ctx.set_state(*state)
+    ctx.set_tuning(zs)
+    return ctx
+
+
+def bitwise(got, ref):
+    for x, y in zip(got, ref):
+        if not np.array_equal(x, y):
+            d = np.abs(x - y)
+            idx = np.unravel_index(np.argmax(d), d.shape)
+            raise AssertionError(f"max |diff| {d.max():.3e} at {idx}: {x[idx]!r} vs {y[idx]!r}")
+
+
+SHAPES = [(1, 1, 1), (5, 3, 2), (64, 4, 3), (70, 9, 13), (130, 7, 5), (33, 65, 1), (1, 9, 17), (200, 3, 40)]
+
+
+@pytest.mark.parametrize("nx,ny,nz", SHAPES)
+@pytest.mark.parametrize("zs", [0, 1, 3])
+def test_step3_f64_bitwise(nx, ny, nz, zs):
+    print(f"step3 f64 {nx}x{ny}x{nz} zs={zs}", flush=True)
+    state, A = inputs(nx, ny, nz, nx + 7 * ny + 13 * nz)
+    L = (1.3, 0.7, 0.9)
+    dt = 0.5 * oracle.stable_dt3(A, PRM[2], 0.9, *L)
+    with ctx_of(nx, ny, nz, state, A, L=L, zs=zs) as ctx:
+        ctx.step(dt, 1)
+        got = ctx.get_state()
+        bitwise(got, oracle.step3(*state, A, PRM, dt, *L))
+        ctx.step(dt, 4)
+        bitwise(ctx.get_state(), oracle.run3(*state, A, PRM, dt, 5, *L))
+        t, n = ctx.time()
+        assert n == 5 and t == pytest.approx(5 * dt, rel=1e-15)
+
+
+def test_step3_launch_shape_does_not_change_results():
+    nx, ny, nz = 67, 10, 23
+    state, A = inputs(nx, ny, nz, 1)
+    outs = []
+    for zs in (0, 1, 2, 5, 23, 100):
+        with ctx_of(nx, ny, nz, state, A, zs=zs) as ctx:
+            ctx.step(1e-6, 3)
+            outs.append(ctx.get_state())
+    for o in outs[1:]:
+        bitwise(o, outs[0])
+
+
+def test_step3_full_size_f64_bitwise():
+    """The benchmark workload (256^3 slab tissue) in the benchmark's launch
+    configuration, two steps, every value."""
+    w = wl.tissue3(n=256)
+    print(f"step3 full size {w.nx}x{w.ny}x{w.nz}", flush=True)
+    dt = oracle.stable_dt3(w.tensor, w.params[2], w.safety)
+    # a state with structure everywhere (the ball alone leaves most cells at rest)
+    g = rng(99)
+    state = (np.clip(w.u0 + 0.1 * g.random(w.u0.shape), 0, 1), w.v0, 0.2 * g.random(w.u0.shape))
+    with ctx_of(w.nx, w.ny, w.nz, state, w.tensor, prm=w.params) as ctx:
+        assert ctx.stable_dt(w.safety) == dt
+        ctx.step(dt, 2)
+        got = ctx.get_state()
+    bitwise(got, oracle.run3(*state, w.tensor, w.params, dt, 2))
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(70, 9, 13), (1, 1, 1), (130, 7, 5)])
+def test_stable_dt3_and_mass_match_oracle(nx, ny, nz):
+    state, A = inputs(nx, ny, nz, 2)
+    L = (2.0, 0.5, 1.5)
+    with ctx_of(nx, ny, nz, state, A, L=L) as ctx:
+        assert ctx.stable_dt(0.8) == oracle.stable_dt3(A, PRM[2], 0.8, *L)
+        ref = oracle.mass3(*state, *L)
+        m = ctx.mass()
+        np.testing.assert_allclose(m, ref, rtol=1e-13)
+        assert ctx.mass() == m                       # fixed reduction order
+    # Delta2 decides when it exceeds every row sum
+    prm = (12.5, 1.0, 50.0, 70.0, 60.0)
+    with ctx_of(nx, ny, nz, state, A, prm=prm, L=L) as ctx:
+        assert ctx.stable_dt(0.8) == oracle.stable_dt3(A, prm[2], 0.8, *L)
+
+
+def test_step3_conserves_tumour_cells_and_acid_without_reactions():
+    """With rho2 = rho3 = delta3 = 0 only the no-flux diffusion acts on v and w,
+    so their masses stay fixed; u (logistic growth, delta1 = 0) changes
+    pointwise by the closed-form logistic factor of one Euler step."""
+    nx, ny, nz = 40, 24, 18
+    state, A = inputs(nx, ny, nz, 3)
+    prm = (0.0, 0.0, 0.5, 0.0, 0.0)
+    with ctx_of(nx, ny, nz, state, A, prm=prm) as ctx:
+        m0 = ctx.mass()
+        dt = 0.9 * ctx.stable_dt(1.0)
+        ctx.step(dt, 50)
+        m1 = ctx.mass()
+        u = ctx.get_state()[0]
+    np.testing.assert_allclose(m1[1:], m0[1:], rtol=1e-12)
+    ref = state[0].copy()
+    for _ in range(50):
+        ref = ref + dt * (ref * (1.0 - ref))
+    np.testing.assert_allclose(u, ref, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(70, 9, 13), (33, 65, 4)])
+def test_step3_f32_within_tolerance(nx, ny, nz):
+    state, A = inputs(nx, ny, nz, 4)
+    s32 = [x.astype(np.float32).astype(np.float64) for x in state]
+    A32 = [x.astype(np.float32).astype(np.float64) for x in A]
+    dt = float(np.float32(oracle.stable_dt3(A32, PRM[2], 0.9)))
+    with ctx_of(nx, ny, nz, [x.astype(np.float32) for x in state], [x.astype(np.float32) for x in A],
+                dtype="f32") as ctx:
+        ctx.step(dt, 20)
+        got = ctx.get_state()
+    ref = oracle.run3(*s32, A32, PRM, dt, 20)
+    for x, y in zip(got, ref):
+        scale = max(1.0, float(np.abs(y).max()))
+        assert np.abs(x - y).max() <= 5e-4 * scale
+
+
+def test_step3_device_io_matches_host_io():
+    torch = pytest.importorskip("torch")
+    nx, ny, nz = 50, 11, 9
+    state, A = inputs(nx, ny, nz, 5)
+    with ctx_of(nx, ny, nz, state, A) as ctx:
+        ctx.step(1e-5, 2)
+        host = ctx.get_state()
+    dev_state = [torch.from_numpy(x).cuda() for x in state]
+    dev_A = [torch.from_numpy(x).cuda() for x in A]
+    with ctx_of(nx, ny, nz, dev_state, dev_A) as ctx:
+        ctx.step(1e-5, 2)
+        out = [torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda") for _ in range(3)]
+        ctx.get_state(out)
+        torch.cuda.synchronize()
+    bitwise([x.cpu().numpy() for x in out], host)
+
+
+def test_step3_errors():
+    with pk.Context3(8, 8, 8) as ctx:
+        with pytest.raises(pk.GGFVError) as e:
+            ctx.step(1e-3)
+        assert e.value.status == pk.GGFV_ESTATE
+        with pytest.raises(pk.GGFVError) as e:
+            ctx.get_state()
+        assert e.value.status == pk.GGFV_ESTATE
+        with pytest.raises(pk.GGFVError) as e:
+            ctx.stable_dt(0.9)
+        assert e.value.status == pk.GGFV_ESTATE
+        state, A = inputs(8, 8, 8, 6)
+        ctx.set_params(PRM)
+        ctx.set_tensor(*A)
+        ctx.set_state(*state)
+        for bad in (0.0, -1.0, float("nan")):
+            with pytest.raises(pk.GGFVError) as e:
+                ctx.step(bad)
+            assert e.value.status == pk.GGFV_EINVAL
+        with pytest.raises(pk.GGFVError):
+            ctx.step(1e-3, -1)
+        with pytest.raises(pk.GGFVError):
+            ctx.set_tuning(-1)
+        with pytest.raises(ValueError):
+            ctx.set_state(state[0][:4], state[1], state[2])
