@@ -317,30 +317,46 @@ def time_front_sweep(pk, torch, t_end=0.5):
             "value": cells * n / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "ms": ms, "instances": out}
 
 
-def time_3d(pk, torch, n=256, steps=100, warmup=10, dtypes=("f64", "f32")):
+def time_3d(pk, torch, n=256, steps=100, warmup=10, dtypes=("f64", "f32"), trial_steps=20):
     """Three-dimensional step on the 256^3 slab tissue (19-point acid stencil,
-    7-point tumour-cell stencil): `steps` steps of the step kernel per dtype,
-    timed with HIP events on the context's stream.  Algorithmic bytes per
-    cell-update: 3 state values read, 6 tensor values read, 3 written."""
+    7-point tumour-cell stencil): for each dtype a short sweep of pencil shapes
+    (rows per wave x planes per strip), then `steps` steps in the fastest, timed
+    with HIP events on the context's stream.  Algorithmic bytes per cell-update:
+    3 state values read, 6 tensor values read, 3 written."""
     from paper_2006_01748_amd import workloads as wl
     w = wl.tissue3(n=n)
     stream = torch.cuda.current_stream()
     out = {"workload": f"slab tissue {w.nx}x{w.ny}x{w.nz}, 8 z-slabs of random SPD tensors, tumour ball, "
                        f"dt=0.9 of the step bound, {steps} steps", "variants": {}}
+
+    def timed(ctx, dt, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.step(dt, k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
     for dt_name in dtypes:
         ctx = pk.Context3(w.nx, w.ny, w.nz, w.lx, w.ly, w.lz, dtype=dt_name, stream=stream.cuda_stream)
         ctx.set_params(w.params)
         ctx.set_tensor(*w.tensor)
         ctx.set_state(w.u0, w.v0, w.w0)
         dt = ctx.stable_dt(w.safety)
+        sweep = {}
+        for rows in (1, 2, 4):
+            for zs in (0, 16, 32, 64):
+                ctx.set_tuning(zs, rows)
+                ctx.step(dt, 2)
+                torch.cuda.synchronize()
+                sweep[f"rows={rows},zs={zs}"] = timed(ctx, dt, trial_steps) * 1e3 / trial_steps
+        best = min(sweep, key=sweep.get)
+        rows, zs = (int(v.split("=")[1]) for v in best.split(","))
+        ctx.set_tuning(zs, rows)
+        ctx.set_state(w.u0, w.v0, w.w0)
         ctx.step(dt, warmup)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        ctx.step(dt, steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
+        ms = timed(ctx, dt, steps)
         mass = ctx.mass()
         ctx.close()
         per = 12 * (8 if dt_name == "f64" else 4)
@@ -348,9 +364,11 @@ def time_3d(pk, torch, n=256, steps=100, warmup=10, dtypes=("f64", "f32")):
         gbs = w.cells * per / (us * 1e-6) / 1e9
         out["variants"][dt_name] = {
             "value": w.cells * steps / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "kernel_avg_us": us,
+            "launch_shape": {"rows_per_wave": rows, "z_per_strip": zs},
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": gbs / PEAK_HBM_GBS, "traffic": None},
-            "bytes_per_cell_update": per, "dt": dt, "mass": list(mass)}
+            "bytes_per_cell_update": per, "dt": dt, "mass": list(mass),
+            "shape_sweep_us": {k: round(v, 1) for k, v in sweep.items()}}
     return out
 
 

@@ -63,9 +63,10 @@ int ggfv3_step(ggfv3_ctx *ctx, double dt, long long nsteps);
 int ggfv3_mass(ggfv3_ctx *ctx, double *mass3);
 /* Simulated time and step count of the context. */
 int ggfv3_time(const ggfv3_ctx *ctx, double *t, long long *steps);
-/* Launch shape: the z extent of the column each thread marches through (0: the
- * library's choice).  Results are identical for every value.  EINVAL if < 0. */
-int ggfv3_set_tuning(ggfv3_ctx *ctx, int z_per_strip);
+/* Launch shape: the number of planes each wave marches through and the number
+ * of rows each wave holds (1, 2 or 4); 0 leaves the library's choice.  Results
+ * are identical for every shape.  EINVAL on other values. */
+int ggfv3_set_tuning(ggfv3_ctx *ctx, int z_per_strip, int rows_per_wave);
 /* Last failure message of ctx ("" if none); ctx == NULL: the last failed
  * ggfv3_create on the calling thread. */
 const char *ggfv3_last_error(const ggfv3_ctx *ctx);

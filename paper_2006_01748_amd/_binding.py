@@ -76,7 +76,7 @@ _SIGNATURES = [
     ("ggfv3_step", _c.c_int, [_VP, _c.c_double, _c.c_longlong]),
     ("ggfv3_mass", _c.c_int, [_VP, _c.POINTER(_c.c_double)]),
     ("ggfv3_time", _c.c_int, [_VP, _c.POINTER(_c.c_double), _c.POINTER(_c.c_longlong)]),
-    ("ggfv3_set_tuning", _c.c_int, [_VP, _c.c_int]),
+    ("ggfv3_set_tuning", _c.c_int, [_VP, _c.c_int, _c.c_int]),
     ("ggfv3_last_error", _c.c_char_p, [_VP]),
 ]
 
@@ -593,5 +593,5 @@ class Context3:
         self._check(self._lib.ggfv3_time(self._h, ctypes.byref(t), ctypes.byref(n)))
         return t.value, n.value
 
-    def set_tuning(self, z_per_strip=0):
-        self._check(self._lib.ggfv3_set_tuning(self._h, int(z_per_strip)))
+    def set_tuning(self, z_per_strip=0, rows_per_wave=0):
+        self._check(self._lib.ggfv3_set_tuning(self._h, int(z_per_strip), int(rows_per_wave)))

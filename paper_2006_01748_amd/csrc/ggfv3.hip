@@ -7,17 +7,35 @@
 // boundary faces and the boundary cell as its own missing neighbour in the
 // tangential differences.
 //
-// Layout: every field is nz*ny rows of `pitch` values (nx rounded up to 64),
-// x fastest, then y, then z.  Two state buffers (u, v, w) alternate; the tensor
-// holds axx, ayy, azz, axy, axz, ayz.
+// Layout: a plane of a field is ny rows of `pitch` values (nx rounded up to
+// 64), x fastest.  The fields of one plane lie next to each other: the state
+// buffer holds plane k of u, v, w at planes 3k, 3k+1, 3k+2, the tensor buffer
+// plane k of axx, ayy, azz, axy, axz, ayz at planes 6k .. 6k+5.  Two state
+// buffers alternate.  A kernel then reaches every field of a plane through one
+// buffer resource (a scalar base) and a scalar field offset.
 //
-// Step kernel: a workgroup of 64 x 4 threads owns 64 x 4 (x, y) columns and a
-// strip of zs planes; each thread marches up its column.  The cell's own values
-// of the planes below and above stay in registers as the column advances, and
-// the flux through the bottom face of a plane is the top face of the plane
-// below (computed once, so both cells see the same bits).  The x and y faces are
-// evaluated by both neighbouring cells from identical operands in identical
-// order, and neighbour values come through the caches.  The arithmetic order is
+// Step kernel (one wave per workgroup, a pencil of cells):
+//   * the 64 lanes of a wave hold 64 adjacent columns x0-1 .. x0+62; lanes 1..62
+//     produce output, lanes 0 and 63 only supply neighbour values, so strips of
+//     62 columns tile x;
+//   * each lane holds R adjacent rows j0..j0+R-1 plus the rows j0-1 and j0+R
+//     that the y-faces and tangential differences need, and the wave marches
+//     up a strip of planes k0..k1-1, starting one plane early (at k0-1, no
+//     output) to produce the flux through the strip's bottom face;
+//   * x-neighbours come from the neighbouring lane through DPP wave shifts;
+//     every x-face flux is evaluated once, by the cell on its left, and passed
+//     to the cell on its right; every z-face flux once, by the cell below, and
+//     carried in registers to the next plane; the two y-faces at the ends of a
+//     row group are also evaluated by the neighbouring groups, from the same
+//     operands in the same order;
+//   * the state of plane k+1, the tz-difference of plane k and the tensor
+//     entries of plane k+1 that the z-face needs are carried in registers;
+//     every input value enters the wave once per plane (halo rows and halo
+//     lanes aside), and the neighbouring row groups of a plane run on the same
+//     XCD so that halo rows come from its L2.
+// Rows and columns outside the grid are read clamped to the last row or column
+// (the mirrored ghost value of the tangential differences); their results are
+// not stored.  The arithmetic order is
 //   FX(i+1/2) = 0.5*(axx_l + axx_r)*((W_r - W_l)*idx)
 //             + 0.5*(axy_l*ty_l + axy_r*ty_r) + 0.5*(axz_l*tz_l + axz_r*tz_r)
 //   (FY, FZ alike), GX = (1 - 0.5*(U_l + U_r))*((V_r - V_l)*idx),
@@ -32,6 +50,7 @@
 #include <string>
 
 #include "ggfv3.h"
+#include "ggfv_dpp.hpp"
 #include "ggfv_internal.hpp"
 
 struct ggfv3_ctx {
@@ -39,11 +58,11 @@ struct ggfv3_ctx {
     double lx = 1.0, ly = 1.0, lz = 1.0;
     int dtype = 0, device = 0;
     hipStream_t stream = nullptr;
-    size_t field = 0;              // values per field (nz * ny * pitch)
+    size_t plane = 0;              // values per plane of one field (ny * pitch)
     size_t elem = 0;               // bytes per value
     void *state[2] = {nullptr, nullptr};
     int cur = 0;
-    void *tensor = nullptr;        // 6 fields
+    void *tensor = nullptr;        // 6 fields, plane-interleaved
     void *staging = nullptr;       // dense io arrays (FP64-sized)
     size_t staging_bytes = 0;
     double *scratch = nullptr;     // reduction partials and results
@@ -52,6 +71,7 @@ struct ggfv3_ctx {
     double t = 0.0;
     long long steps = 0;
     int zs = 0;                    // planes per strip (0: default)
+    int rows = 0;                  // rows per wave (0: default)
     std::string err;
 };
 
@@ -99,128 +119,275 @@ struct Guard3 {
 
 template <typename T>
 struct Step3Args {
-    const T *u, *v, *w;
-    T *un, *vn, *wn;
-    const T *axx, *ayy, *azz, *axy, *axz, *ayz;
+    const T *s;                    // state in (u, v, w interleaved by plane)
+    T *o;                          // state out
+    const T *t;                    // tensor (axx, ayy, azz, axy, axz, ayz interleaved by plane)
     int nx, ny, nz, pitch, zs;
+    unsigned pb;                   // bytes per plane of one field
     T idx, idy, idz, hx, hy, hz, dt;
     T d1, r2, D2, r3, d3;
 };
 
-template <typename T>
-struct Grid3 {
-    const Step3Args<T> &A;
-    __device__ __forceinline__ size_t at(int i, int j, int k) const
-    {
-        return ((size_t)k * A.ny + j) * A.pitch + i;
-    }
-    __device__ __forceinline__ int cx(int i) const { return i < 0 ? 0 : (i >= A.nx ? A.nx - 1 : i); }
-    __device__ __forceinline__ int cy(int j) const { return j < 0 ? 0 : (j >= A.ny ? A.ny - 1 : j); }
-    __device__ __forceinline__ int cz(int k) const { return k < 0 ? 0 : (k >= A.nz ? A.nz - 1 : k); }
-    __device__ __forceinline__ T tx(int i, int j, int k) const
-    {
-        return (A.w[at(cx(i + 1), j, k)] - A.w[at(cx(i - 1), j, k)]) * A.hx;
-    }
-    __device__ __forceinline__ T ty(int i, int j, int k) const
-    {
-        return (A.w[at(i, cy(j + 1), k)] - A.w[at(i, cy(j - 1), k)]) * A.hy;
-    }
-    __device__ __forceinline__ T tz(int i, int j, int k) const
-    {
-        return (A.w[at(i, j, cz(k + 1))] - A.w[at(i, j, cz(k - 1))]) * A.hz;
-    }
-    // acid flux through the face between cell (i,j,k) and its +x / +y / +z neighbour
-    __device__ __forceinline__ T fx(int i, int j, int k) const
-    {
-        const size_t l = at(i, j, k), r = at(i + 1, j, k);
-        const T half = T(0.5);
-        const T tyl = ty(i, j, k), tyr = ty(i + 1, j, k);
-        const T tzl = tz(i, j, k), tzr = tz(i + 1, j, k);
-        return half * (A.axx[l] + A.axx[r]) * ((A.w[r] - A.w[l]) * A.idx) + half * (A.axy[l] * tyl + A.axy[r] * tyr) +
-               half * (A.axz[l] * tzl + A.axz[r] * tzr);
-    }
-    __device__ __forceinline__ T fy(int i, int j, int k) const
-    {
-        const size_t l = at(i, j, k), r = at(i, j + 1, k);
-        const T half = T(0.5);
-        const T txl = tx(i, j, k), txr = tx(i, j + 1, k);
-        const T tzl = tz(i, j, k), tzr = tz(i, j + 1, k);
-        return half * (A.ayy[l] + A.ayy[r]) * ((A.w[r] - A.w[l]) * A.idy) + half * (A.axy[l] * txl + A.axy[r] * txr) +
-               half * (A.ayz[l] * tzl + A.ayz[r] * tzr);
-    }
-    __device__ __forceinline__ T fz(int i, int j, int k) const
-    {
-        const size_t l = at(i, j, k), r = at(i, j, k + 1);
-        const T half = T(0.5);
-        const T txl = tx(i, j, k), txr = tx(i, j, k + 1);
-        const T tyl = ty(i, j, k), tyr = ty(i, j, k + 1);
-        return half * (A.azz[l] + A.azz[r]) * ((A.w[r] - A.w[l]) * A.idz) + half * (A.axz[l] * txl + A.axz[r] * txr) +
-               half * (A.ayz[l] * tyl + A.ayz[r] * tyr);
-    }
-    // tumour-cell flux through the face between l and r (spacing factor id)
-    __device__ __forceinline__ T g(size_t l, size_t r, T id) const
-    {
-        return (T(1) - T(0.5) * (A.u[l] + A.u[r])) * ((A.v[r] - A.v[l]) * id);
-    }
-};
+constexpr int kStrip = 62;     // output columns per wave
+
+__device__ __forceinline__ int xcd_local_id3(int bid, int nb)
+{
+    // workgroups are dealt round-robin to the eight XCDs: give each XCD one
+    // contiguous range of pencils
+    const int xcd = bid & 7, q = nb >> 3, rem = nb & 7;
+    return xcd * q + min(xcd, rem) + (bid >> 3);
+}
+
+// Loads and stores through a buffer resource per plane group (wave-uniform base
+// and size in scalar registers), a scalar field offset and a 32-bit per-lane
+// byte offset, so no lane keeps a 64-bit address.  A plane group holds fewer
+// than 2^32 bytes.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;          // raw buffer, 32-bit data format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
+}
 
 template <typename T>
-__global__ __launch_bounds__(256) void step3_kernel(Step3Args<T> A)
+__device__ __forceinline__ T gld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+
+template <>
+__device__ __forceinline__ double gld<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
 {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    if (i >= A.nx || j >= A.ny) return;            // no barriers below
-    const int k0 = blockIdx.z * A.zs, k1 = min(A.nz, k0 + A.zs);
-    const Grid3<T> G{A};
-    const bool has_e = i + 1 < A.nx, has_w = i > 0, has_n = j + 1 < A.ny, has_s = j > 0;
-    const T one = T(1);
-    // bottom faces of the first plane of the strip
-    T FZb = k0 > 0 ? G.fz(i, j, k0 - 1) : T(0);
-    T GZb = k0 > 0 ? G.g(G.at(i, j, k0 - 1), G.at(i, j, k0), A.idz) : T(0);
-    for (int k = k0; k < k1; ++k) {
-        const size_t c = G.at(i, j, k);
-        const bool has_t = k + 1 < A.nz;
-        const T FXe = has_e ? G.fx(i, j, k) : T(0);
-        const T FXw = has_w ? G.fx(i - 1, j, k) : T(0);
-        const T FYn = has_n ? G.fy(i, j, k) : T(0);
-        const T FYs = has_s ? G.fy(i, j - 1, k) : T(0);
-        const T FZt = has_t ? G.fz(i, j, k) : T(0);
-        const T GXe = has_e ? G.g(c, G.at(i + 1, j, k), A.idx) : T(0);
-        const T GXw = has_w ? G.g(G.at(i - 1, j, k), c, A.idx) : T(0);
-        const T GYn = has_n ? G.g(c, G.at(i, j + 1, k), A.idy) : T(0);
-        const T GYs = has_s ? G.g(G.at(i, j - 1, k), c, A.idy) : T(0);
-        const T GZt = has_t ? G.g(c, G.at(i, j, k + 1), A.idz) : T(0);
-        const T divW = ((FXe - FXw) * A.idx + (FYn - FYs) * A.idy) + (FZt - FZb) * A.idz;
-        const T divV = ((GXe - GXw) * A.idx + (GYn - GYs) * A.idy) + (GZt - GZb) * A.idz;
-        const T U = A.u[c], V = A.v[c], W = A.w[c];
-        A.un[c] = U + A.dt * (U * (one - U) - (A.d1 * U) * W);
-        A.vn[c] = V + A.dt * ((A.r2 * V) * (one - V) + A.D2 * divV);
-        A.wn[c] = W + A.dt * ((A.r3 * V - A.d3 * W) + divW);
-        FZb = FZt;
-        GZb = GZt;
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <>
+__device__ __forceinline__ float gld<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void gst(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, 0);
+}
+
+__device__ __forceinline__ void gst(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(64) void step3_pencil_kernel(Step3Args<T> A, int nsx, int ngy, int nzb)
+{
+    using ggfv::from_left;
+    using ggfv::from_right;
+    constexpr int NR = R + 2;                      // rows held: j0-1 .. j0+R
+    const int lid = xcd_local_id3(blockIdx.x, nsx * ngy * nzb);
+    const int sx = lid % nsx, rest = lid / nsx;
+    const int gy = rest % ngy, zb = rest / ngy;
+    const int lane = threadIdx.x;
+    const int x = sx * kStrip - 1 + lane;
+    const int xl = min(max(x, 0), A.nx - 1);
+    const bool east_edge = x >= A.nx - 1, west_edge = x <= 0;
+    const bool out_lane = lane >= 1 && lane <= kStrip && x < A.nx;
+    const int j0 = gy * R;
+    const int k0 = zb * A.zs, k1 = min(A.nz, k0 + A.zs);
+    const size_t P = (size_t)A.ny * A.pitch;
+    const unsigned PB = A.pb;
+    // field offsets within a plane group
+    const unsigned fU = 0, fV = PB, fW = 2 * PB;
+    const unsigned fXX = 0, fYY = PB, fZZ = 2 * PB, fXY = 3 * PB, fXZ = 4 * PB, fYZ = 5 * PB;
+    const T half = T(0.5), one = T(1);
+    auto state_at = [&](int k) { return group_rsrc(A.s + (size_t)k * 3 * P, 3 * PB); };
+    auto tensor_at = [&](int k) { return group_rsrc(A.t + (size_t)k * 6 * P, 6 * PB); };
+
+    unsigned off[NR];                              // clamped byte offsets within a plane
+    bool face_ok[R + 1];                           // y-face between rows f and f+1 inside the grid
+    bool row_ok[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int j = j0 - 1 + r;
+        off[r] = (unsigned)(min(max(j, 0), A.ny - 1) * A.pitch + xl) * (unsigned)sizeof(T);
+        row_ok[r] = j < A.ny;
+    }
+#pragma unroll
+    for (int f = 0; f <= R; ++f) face_ok[f] = (j0 - 1 + f) >= 0 && (j0 + f) <= A.ny - 1;
+
+    const int kstart = k0 > 0 ? k0 - 1 : 0;
+    // registers carried from plane to plane
+    T Wc[NR], Wn[NR], TZc[NR];                     // w of planes k and k+1, tz of plane k
+    T TX[NR];                                      // tx of plane k (own rows carried)
+    T Uc[NR], Vc[NR];                              // u, v of plane k (own rows carried)
+    T zz[NR], xz[NR], yz[NR];                      // azz, axz, ayz of plane k (own rows carried)
+    T FZb[NR], GZb[NR];                            // fluxes through the bottom faces
+    {
+        const auto Sm = state_at(max(kstart - 1, 0)), Sc = state_at(kstart);
+        const auto Sn = state_at(min(kstart + 1, A.nz - 1));
+        const auto Tc = tensor_at(kstart);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            Wc[r] = gld<T>(Sc, off[r], fW);
+            Wn[r] = gld<T>(Sn, off[r], fW);
+            const T m = gld<T>(Sm, off[r], fW);
+            TZc[r] = (Wn[r] - m) * A.hz;
+        }
+#pragma unroll
+        for (int r = 1; r <= R; ++r) {
+            const T e = from_right(Wc[r]), w = from_left(Wc[r]);
+            const T er = east_edge ? Wc[r] : e;
+            const T wl = west_edge ? Wc[r] : w;
+            TX[r] = (er - wl) * A.hx;
+            Uc[r] = gld<T>(Sc, off[r], fU);
+            Vc[r] = gld<T>(Sc, off[r], fV);
+            zz[r] = gld<T>(Tc, off[r], fZZ);
+            xz[r] = gld<T>(Tc, off[r], fXZ);
+            yz[r] = gld<T>(Tc, off[r], fYZ);
+            FZb[r] = T(0);
+            GZb[r] = T(0);
+        }
+    }
+
+    for (int k = kstart; k < k1; ++k) {
+        const bool top = k + 1 < A.nz;
+        const auto Sn = state_at(min(k + 1, A.nz - 1)), S2 = state_at(min(k + 2, A.nz - 1));
+        const auto Tn = tensor_at(min(k + 1, A.nz - 1));
+        // w of plane k+2 -> tz of plane k+1
+        T W2[NR], TZn[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            W2[r] = gld<T>(S2, off[r], fW);
+            TZn[r] = (W2[r] - Wc[r]) * A.hz;
+        }
+        // values of plane k+1 for the top faces
+        T Un[NR], Vn[NR], zzn[NR], xzn[NR], yzn[NR];
+#pragma unroll
+        for (int r = 1; r <= R; ++r) {
+            Un[r] = gld<T>(Sn, off[r], fU);
+            Vn[r] = gld<T>(Sn, off[r], fV);
+            zzn[r] = gld<T>(Tn, off[r], fZZ);
+            xzn[r] = gld<T>(Tn, off[r], fXZ);
+            yzn[r] = gld<T>(Tn, off[r], fYZ);
+        }
+        // top faces (also in the warm-up plane)
+        T FZt[NR], GZt[NR], TXn[NR];
+#pragma unroll
+        for (int r = 1; r <= R; ++r) {
+            const T ty = (Wc[r + 1] - Wc[r - 1]) * A.hy;
+            const T tyn = (Wn[r + 1] - Wn[r - 1]) * A.hy;
+            const T e = from_right(Wn[r]), w = from_left(Wn[r]);
+            const T er = east_edge ? Wn[r] : e;
+            const T wl = west_edge ? Wn[r] : w;
+            TXn[r] = (er - wl) * A.hx;
+            const T fz = half * (zz[r] + zzn[r]) * ((Wn[r] - Wc[r]) * A.idz) + half * (xz[r] * TX[r] + xzn[r] * TXn[r]) +
+                         half * (yz[r] * ty + yzn[r] * tyn);
+            const T gz = (one - half * (Uc[r] + Un[r])) * ((Vn[r] - Vc[r]) * A.idz);
+            FZt[r] = top ? fz : T(0);
+            GZt[r] = top ? gz : T(0);
+        }
+        if (k >= k0) {                             // wave-uniform
+            const auto Sk = state_at(k), Tk = tensor_at(k);
+            // halo rows of plane k: u, v, tx and the y-face tensor entries
+            T yy[NR], xy[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                yy[r] = gld<T>(Tk, off[r], fYY);
+                xy[r] = gld<T>(Tk, off[r], fXY);
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r += R + 1) {
+                Uc[r] = gld<T>(Sk, off[r], fU);
+                Vc[r] = gld<T>(Sk, off[r], fV);
+                yz[r] = gld<T>(Tk, off[r], fYZ);
+                const T e = from_right(Wc[r]), w = from_left(Wc[r]);
+                const T er = east_edge ? Wc[r] : e;
+                const T wl = west_edge ? Wc[r] : w;
+                TX[r] = (er - wl) * A.hx;
+            }
+            // y-faces f between rows f and f+1
+            T FY[R + 1], GY[R + 1];
+#pragma unroll
+            for (int f = 0; f <= R; ++f) {
+                const T fy = half * (yy[f] + yy[f + 1]) * ((Wc[f + 1] - Wc[f]) * A.idy) +
+                             half * (xy[f] * TX[f] + xy[f + 1] * TX[f + 1]) + half * (yz[f] * TZc[f] + yz[f + 1] * TZc[f + 1]);
+                const T gy = (one - half * (Uc[f] + Uc[f + 1])) * ((Vc[f + 1] - Vc[f]) * A.idy);
+                FY[f] = face_ok[f] ? fy : T(0);
+                GY[f] = face_ok[f] ? gy : T(0);
+            }
+            const auto Ok = group_rsrc(A.o + (size_t)k * 3 * P, 3 * PB);
+#pragma unroll
+            for (int r = 1; r <= R; ++r) {
+                const T xx = gld<T>(Tk, off[r], fXX);
+                const T ty = (Wc[r + 1] - Wc[r - 1]) * A.hy;
+                const T xxE = from_right(xx), xyE = from_right(xy[r]), xzE = from_right(xz[r]);
+                const T wE = from_right(Wc[r]), tyE = from_right(ty), tzE = from_right(TZc[r]);
+                const T uE = from_right(Uc[r]), vE = from_right(Vc[r]);
+                const T fx = half * (xx + xxE) * ((wE - Wc[r]) * A.idx) + half * (xy[r] * ty + xyE * tyE) +
+                             half * (xz[r] * TZc[r] + xzE * tzE);
+                const T gx = (one - half * (Uc[r] + uE)) * ((vE - Vc[r]) * A.idx);
+                const T FXe = east_edge ? T(0) : fx;
+                const T GXe = east_edge ? T(0) : gx;
+                const T fw = from_left(FXe), gw = from_left(GXe);
+                const T FXw = west_edge ? T(0) : fw;
+                const T GXw = west_edge ? T(0) : gw;
+                const T divW = ((FXe - FXw) * A.idx + (FY[r] - FY[r - 1]) * A.idy) + (FZt[r] - FZb[r]) * A.idz;
+                const T divV = ((GXe - GXw) * A.idx + (GY[r] - GY[r - 1]) * A.idy) + (GZt[r] - GZb[r]) * A.idz;
+                const T U = Uc[r], V = Vc[r], W = Wc[r];
+                const T un = U + A.dt * (U * (one - U) - (A.d1 * U) * W);
+                const T vn = V + A.dt * ((A.r2 * V) * (one - V) + A.D2 * divV);
+                const T wn = W + A.dt * ((A.r3 * V - A.d3 * W) + divW);
+                if (out_lane && row_ok[r]) {
+                    gst(Ok, off[r], fU, un);
+                    gst(Ok, off[r], fV, vn);
+                    gst(Ok, off[r], fW, wn);
+                }
+            }
+        }
+        // advance one plane
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            Wc[r] = Wn[r];
+            Wn[r] = W2[r];
+            TZc[r] = TZn[r];
+        }
+#pragma unroll
+        for (int r = 1; r <= R; ++r) {
+            TX[r] = TXn[r];
+            Uc[r] = Un[r];
+            Vc[r] = Vn[r];
+            zz[r] = zzn[r];
+            xz[r] = xzn[r];
+            yz[r] = yzn[r];
+            FZb[r] = FZt[r];
+            GZb[r] = GZt[r];
+        }
     }
 }
 
-// dense (nz*ny rows of nx) io array -> padded field
+// dense (nz, ny, nx) io array -> field f of NF plane-interleaved fields
 template <typename S, typename T>
-__global__ void pack3_kernel(const S *__restrict__ src, T *__restrict__ dst, int nx, long rows, int pitch)
+__global__ void pack3_kernel(const S *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz, int pitch,
+                             int nf, int f)
 {
-    const long n = (long)nx * rows;
+    const long n = (long)nx * ny * nz;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
-        const long r = q / nx;
-        const int i = (int)(q - r * nx);
-        dst[(size_t)r * pitch + i] = T(src[q]);
+        const long row = q / nx;
+        const int i = (int)(q - row * nx);
+        const long k = row / ny;
+        const int j = (int)(row - k * ny);
+        dst[((size_t)(k * nf + f) * ny + j) * pitch + i] = T(src[q]);
     }
 }
 
 template <typename T, typename D>
-__global__ void unpack3_kernel(const T *__restrict__ src, D *__restrict__ dst, int nx, long rows, int pitch)
+__global__ void unpack3_kernel(const T *__restrict__ src, D *__restrict__ dst, int nx, int ny, int nz, int pitch,
+                               int nf, int f)
 {
-    const long n = (long)nx * rows;
+    const long n = (long)nx * ny * nz;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
-        const long r = q / nx;
-        const int i = (int)(q - r * nx);
-        dst[q] = D(src[(size_t)r * pitch + i]);
+        const long row = q / nx;
+        const int i = (int)(q - row * nx);
+        const long k = row / ny;
+        const int j = (int)(row - k * ny);
+        dst[q] = D(src[((size_t)(k * nf + f) * ny + j) * pitch + i]);
     }
 }
 
@@ -241,23 +408,27 @@ __device__ __forceinline__ double wave_max(double x)
 // Per-block partial sums of the three state fields (fixed partition and order),
 // and of the Gershgorin bound of the tensor (max), written to parts[block*4 + q].
 template <typename T>
-__global__ __launch_bounds__(kRed3) void reduce3_kernel(const T *__restrict__ st, const T *__restrict__ ten,
-                                                       size_t field, int nx, long rows, int pitch,
-                                                       double *__restrict__ parts)
+__global__ __launch_bounds__(kRed3) void reduce3_kernel(const T *__restrict__ st, const T *__restrict__ ten, int nx,
+                                                       int ny, int nz, int pitch, double *__restrict__ parts)
 {
     __shared__ double sm[kRed3 / 64][4];
     double x[4] = {0.0, 0.0, 0.0, 0.0};
-    const long n = (long)nx * rows;
+    const long n = (long)nx * ny * nz;
+    const size_t P = (size_t)ny * pitch;
     for (long q = blockIdx.x * (long)kRed3 + threadIdx.x; q < n; q += (long)gridDim.x * kRed3) {
-        const long r = q / nx;
-        const size_t o = (size_t)r * pitch + (q - r * nx);
+        const long row = q / nx;
+        const int i = (int)(q - row * nx);
+        const long k = row / ny;
+        const size_t o = (size_t)(row - k * ny) * pitch + i;
         if (st) {
+            const T *sk = st + (size_t)k * 3 * P + o;
 #pragma unroll
-            for (int f = 0; f < 3; ++f) x[f] += double(st[f * field + o]);
+            for (int f = 0; f < 3; ++f) x[f] += double(sk[f * P]);
         }
         if (ten) {
-            const double axx = ten[o], ayy = ten[field + o], azz = ten[2 * field + o];
-            const double axy = ten[3 * field + o], axz = ten[4 * field + o], ayz = ten[5 * field + o];
+            const T *tk = ten + (size_t)k * 6 * P + o;
+            const double axx = tk[0], ayy = tk[P], azz = tk[2 * P];
+            const double axy = tk[3 * P], axz = tk[4 * P], ayz = tk[5 * P];
             const double r0 = fabs(axx) + fabs(axy) + fabs(axz);
             const double r1 = fabs(axy) + fabs(ayy) + fabs(ayz);
             const double r2 = fabs(axz) + fabs(ayz) + fabs(azz);
@@ -340,20 +511,20 @@ int pack_fields(ggfv3_ctx *ctx, const void *const *src, int n, int where, int io
         for (int p = 0; p < n; ++p) d[p] = src[p];
     }
     const int blocks = 1024;
+    const int gd[4] = {ctx->nx, ctx->ny, ctx->nz, ctx->pitch};
     for (int p = 0; p < n; ++p) {
-        char *out = static_cast<char *>(dst) + p * ctx->field * ctx->elem;
         if (ctx->dtype == GGFV_F64 && io == GGFV_F64)
             hipLaunchKernelGGL((pack3_kernel<double, double>), dim3(blocks), dim3(256), 0, ctx->stream,
-                               (const double *)d[p], (double *)out, ctx->nx, rows_of(ctx), ctx->pitch);
+                               (const double *)d[p], (double *)dst, gd[0], gd[1], gd[2], gd[3], n, p);
         else if (ctx->dtype == GGFV_F64)
             hipLaunchKernelGGL((pack3_kernel<float, double>), dim3(blocks), dim3(256), 0, ctx->stream,
-                               (const float *)d[p], (double *)out, ctx->nx, rows_of(ctx), ctx->pitch);
+                               (const float *)d[p], (double *)dst, gd[0], gd[1], gd[2], gd[3], n, p);
         else if (io == GGFV_F64)
             hipLaunchKernelGGL((pack3_kernel<double, float>), dim3(blocks), dim3(256), 0, ctx->stream,
-                               (const double *)d[p], (float *)out, ctx->nx, rows_of(ctx), ctx->pitch);
+                               (const double *)d[p], (float *)dst, gd[0], gd[1], gd[2], gd[3], n, p);
         else
             hipLaunchKernelGGL((pack3_kernel<float, float>), dim3(blocks), dim3(256), 0, ctx->stream,
-                               (const float *)d[p], (float *)out, ctx->nx, rows_of(ctx), ctx->pitch);
+                               (const float *)d[p], (float *)dst, gd[0], gd[1], gd[2], gd[3], n, p);
         GGFV3_HIP(ctx, hipGetLastError());
     }
     // the host staging area is reused by the next call
@@ -368,12 +539,10 @@ int reduce3(ggfv3_ctx *ctx, bool state, bool tensor, double *host4)
     const void *tn = tensor ? ctx->tensor : nullptr;
     if (ctx->dtype == GGFV_F64)
         hipLaunchKernelGGL((reduce3_kernel<double>), dim3(kRed3Blocks), dim3(kRed3), 0, ctx->stream,
-                           (const double *)st, (const double *)tn, ctx->field, ctx->nx, rows_of(ctx), ctx->pitch,
-                           parts);
+                           (const double *)st, (const double *)tn, ctx->nx, ctx->ny, ctx->nz, ctx->pitch, parts);
     else
         hipLaunchKernelGGL((reduce3_kernel<float>), dim3(kRed3Blocks), dim3(kRed3), 0, ctx->stream,
-                           (const float *)st, (const float *)tn, ctx->field, ctx->nx, rows_of(ctx), ctx->pitch,
-                           parts);
+                           (const float *)st, (const float *)tn, ctx->nx, ctx->ny, ctx->nz, ctx->pitch, parts);
     GGFV3_HIP(ctx, hipGetLastError());
     hipLaunchKernelGGL(reduce3_final_kernel, dim3(1), dim3(64), 0, ctx->stream, parts, kRed3Blocks, res);
     GGFV3_HIP(ctx, hipGetLastError());
@@ -386,26 +555,14 @@ template <typename T>
 Step3Args<T> args3(const ggfv3_ctx *ctx, double dt)
 {
     Step3Args<T> A{};
-    const T *in = static_cast<const T *>(ctx->state[ctx->cur]);
-    T *out = static_cast<T *>(ctx->state[1 - ctx->cur]);
-    const T *tn = static_cast<const T *>(ctx->tensor);
-    const size_t F = ctx->field;
-    A.u = in;
-    A.v = in + F;
-    A.w = in + 2 * F;
-    A.un = out;
-    A.vn = out + F;
-    A.wn = out + 2 * F;
-    A.axx = tn;
-    A.ayy = tn + F;
-    A.azz = tn + 2 * F;
-    A.axy = tn + 3 * F;
-    A.axz = tn + 4 * F;
-    A.ayz = tn + 5 * F;
+    A.s = static_cast<const T *>(ctx->state[ctx->cur]);
+    A.o = static_cast<T *>(ctx->state[1 - ctx->cur]);
+    A.t = static_cast<const T *>(ctx->tensor);
     A.nx = ctx->nx;
     A.ny = ctx->ny;
     A.nz = ctx->nz;
     A.pitch = ctx->pitch;
+    A.pb = (unsigned)(ctx->plane * sizeof(T));
     const double idx = ctx->nx / ctx->lx, idy = ctx->ny / ctx->ly, idz = ctx->nz / ctx->lz;
     A.idx = T(idx);
     A.idy = T(idy);
@@ -419,26 +576,56 @@ Step3Args<T> args3(const ggfv3_ctx *ctx, double dt)
     A.D2 = T(ctx->prm.Delta2);
     A.r3 = T(ctx->prm.rho3);
     A.d3 = T(ctx->prm.delta3);
-    // strips of z: about four workgroups per CU on 256 CUs
+    A.zs = 1;
+    return A;
+}
+
+struct Shape3 {
+    int rows, nsx, ngy, nzb, zs;
+};
+
+// Pencil shape: rows per wave (1, 2 or 4) and planes per strip.  By default
+// enough strips of z that the grid holds about 16 waves per CU on 256 CUs.
+Shape3 shape3(const ggfv3_ctx *ctx)
+{
+    Shape3 S{};
+    S.rows = ctx->rows > 0 ? ctx->rows : 2;
+    S.nsx = (ctx->nx + kStrip - 1) / kStrip;
+    S.ngy = (ctx->ny + S.rows - 1) / S.rows;
     int zs = ctx->zs;
     if (zs <= 0) {
-        const long cols = (long)((ctx->nx + 63) / 64) * ((ctx->ny + 3) / 4);
-        const long target = 1024;
-        long nzb = (target + cols - 1) / cols;
+        const long pencils = (long)S.nsx * S.ngy;
+        const long target = 4096;
+        long nzb = (target + pencils - 1) / pencils;
         if (nzb < 1) nzb = 1;
         zs = (int)((ctx->nz + nzb - 1) / nzb);
-        if (zs < 4) zs = 4;
+        if (zs < 8) zs = 8;
     }
-    A.zs = zs > ctx->nz ? ctx->nz : zs;
-    return A;
+    S.zs = zs > ctx->nz ? ctx->nz : zs;
+    S.nzb = (ctx->nz + S.zs - 1) / S.zs;
+    return S;
 }
 
 template <typename T>
 hipError_t launch3(ggfv3_ctx *ctx, double dt)
 {
-    const Step3Args<T> A = args3<T>(ctx, dt);
-    const dim3 grid((ctx->nx + 63) / 64, (ctx->ny + 3) / 4, (ctx->nz + A.zs - 1) / A.zs);
-    hipLaunchKernelGGL((step3_kernel<T>), grid, dim3(64, 4), 0, ctx->stream, A);
+    Step3Args<T> A = args3<T>(ctx, dt);
+    const Shape3 S = shape3(ctx);
+    A.zs = S.zs;
+    const long nb = (long)S.nsx * S.ngy * S.nzb;
+    if (nb > 0x7fffffffL) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nb), block(64);
+    switch (S.rows) {
+    case 1:
+        hipLaunchKernelGGL((step3_pencil_kernel<T, 1>), grid, block, 0, ctx->stream, A, S.nsx, S.ngy, S.nzb);
+        break;
+    case 2:
+        hipLaunchKernelGGL((step3_pencil_kernel<T, 2>), grid, block, 0, ctx->stream, A, S.nsx, S.ngy, S.nzb);
+        break;
+    default:
+        hipLaunchKernelGGL((step3_pencil_kernel<T, 4>), grid, block, 0, ctx->stream, A, S.nsx, S.ngy, S.nzb);
+        break;
+    }
     return hipGetLastError();
 }
 
@@ -454,6 +641,9 @@ int ggfv3_create(ggfv3_ctx **out, int nx, int ny, int nz, double lx, double ly, 
     if (nx < 1 || ny < 1 || nz < 1) return fail3(nullptr, GGFV_EINVAL, "sizes must be >= 1");
     if ((long long)nx * ny * nz > (1LL << 31))
         return fail3(nullptr, GGFV_EINVAL, "grid of %lld cells is too large", (long long)nx * ny * nz);
+    // the six tensor planes of one z-level are addressed with 32-bit offsets
+    if (6LL * ggfv::round_up(nx, ggfv::kRowAlign) * ny * (dtype == GGFV_F64 ? 8 : 4) >= (1LL << 32))
+        return fail3(nullptr, GGFV_EINVAL, "a %dx%d plane is too large for 32-bit plane offsets", nx, ny);
     if (!(lx > 0.0) || !(ly > 0.0) || !(lz > 0.0) || !std::isfinite(lx) || !std::isfinite(ly) || !std::isfinite(lz))
         return fail3(nullptr, GGFV_EINVAL, "domain lengths must be finite and > 0");
     if (dtype != GGFV_F64 && dtype != GGFV_F32) return fail3(nullptr, GGFV_EINVAL, "dtype must be F64 or F32");
@@ -473,17 +663,18 @@ int ggfv3_create(ggfv3_ctx **out, int nx, int ny, int nz, double lx, double ly, 
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->pitch = ggfv::round_up(nx, ggfv::kRowAlign);
-    c->field = (size_t)nz * ny * c->pitch;
+    c->plane = (size_t)ny * c->pitch;
+    const size_t field = c->plane * nz;
     c->elem = dtype == GGFV_F64 ? 8 : 4;
     Guard3 g(device);
-    bool ok = hipMalloc(&c->state[0], 3 * c->field * c->elem) == hipSuccess &&
-              hipMalloc(&c->state[1], 3 * c->field * c->elem) == hipSuccess &&
-              hipMalloc(&c->tensor, 6 * c->field * c->elem) == hipSuccess &&
+    bool ok = hipMalloc(&c->state[0], 3 * field * c->elem) == hipSuccess &&
+              hipMalloc(&c->state[1], 3 * field * c->elem) == hipSuccess &&
+              hipMalloc(&c->tensor, 6 * field * c->elem) == hipSuccess &&
               hipMalloc(reinterpret_cast<void **>(&c->scratch), ((size_t)kRed3Blocks * 4 + 8) * sizeof(double)) ==
                   hipSuccess;
-    if (ok) ok = hipMemset(c->state[0], 0, 3 * c->field * c->elem) == hipSuccess &&
-                 hipMemset(c->state[1], 0, 3 * c->field * c->elem) == hipSuccess &&
-                 hipMemset(c->tensor, 0, 6 * c->field * c->elem) == hipSuccess;
+    if (ok) ok = hipMemset(c->state[0], 0, 3 * field * c->elem) == hipSuccess &&
+                 hipMemset(c->state[1], 0, 3 * field * c->elem) == hipSuccess &&
+                 hipMemset(c->tensor, 0, 6 * field * c->elem) == hipSuccess;
     if (!ok) {
         ggfv3_destroy(c);
         return fail3(nullptr, GGFV_ENOMEM, "cannot allocate device memory for a %dx%dx%d grid", nx, ny, nz);
@@ -557,21 +748,22 @@ int ggfv3_get_state(ggfv3_ctx *ctx, void *u, void *v, void *w, int where, int io
     const size_t count = (size_t)ctx->nx * rows_of(ctx);
     void *dst[3] = {u, v, w};
     if (where == GGFV_HOST && (rc = ensure_staging3(ctx, 3))) return rc;
+    const int gd[4] = {ctx->nx, ctx->ny, ctx->nz, ctx->pitch};
     for (int p = 0; p < 3; ++p) {
-        const char *src = static_cast<const char *>(ctx->state[ctx->cur]) + p * ctx->field * ctx->elem;
+        const void *src = ctx->state[ctx->cur];
         void *d = where == GGFV_HOST ? static_cast<char *>(ctx->staging) + p * count * io_bytes(io) : dst[p];
         if (ctx->dtype == GGFV_F64 && io == GGFV_F64)
             hipLaunchKernelGGL((unpack3_kernel<double, double>), dim3(1024), dim3(256), 0, ctx->stream,
-                               (const double *)src, (double *)d, ctx->nx, rows_of(ctx), ctx->pitch);
+                               (const double *)src, (double *)d, gd[0], gd[1], gd[2], gd[3], 3, p);
         else if (ctx->dtype == GGFV_F64)
             hipLaunchKernelGGL((unpack3_kernel<double, float>), dim3(1024), dim3(256), 0, ctx->stream,
-                               (const double *)src, (float *)d, ctx->nx, rows_of(ctx), ctx->pitch);
+                               (const double *)src, (float *)d, gd[0], gd[1], gd[2], gd[3], 3, p);
         else if (io == GGFV_F64)
             hipLaunchKernelGGL((unpack3_kernel<float, double>), dim3(1024), dim3(256), 0, ctx->stream,
-                               (const float *)src, (double *)d, ctx->nx, rows_of(ctx), ctx->pitch);
+                               (const float *)src, (double *)d, gd[0], gd[1], gd[2], gd[3], 3, p);
         else
             hipLaunchKernelGGL((unpack3_kernel<float, float>), dim3(1024), dim3(256), 0, ctx->stream,
-                               (const float *)src, (float *)d, ctx->nx, rows_of(ctx), ctx->pitch);
+                               (const float *)src, (float *)d, gd[0], gd[1], gd[2], gd[3], 3, p);
         GGFV3_HIP(ctx, hipGetLastError());
         if (where == GGFV_HOST)
             GGFV3_HIP(ctx, hipMemcpyAsync(dst[p], d, count * io_bytes(io), hipMemcpyDeviceToHost, ctx->stream));
@@ -638,11 +830,14 @@ int ggfv3_time(const ggfv3_ctx *ctx, double *t, long long *steps)
     return GGFV_OK;
 }
 
-int ggfv3_set_tuning(ggfv3_ctx *ctx, int z_per_strip)
+int ggfv3_set_tuning(ggfv3_ctx *ctx, int z_per_strip, int rows_per_wave)
 {
     if (!ctx) return GGFV_EINVAL;
     if (z_per_strip < 0) return fail3(ctx, GGFV_EINVAL, "z_per_strip must be >= 0");
+    if (rows_per_wave != 0 && rows_per_wave != 1 && rows_per_wave != 2 && rows_per_wave != 4)
+        return fail3(ctx, GGFV_EINVAL, "rows_per_wave must be 0, 1, 2 or 4");
     ctx->zs = z_per_strip;
+    ctx->rows = rows_per_wave;
     return GGFV_OK;
 }
 

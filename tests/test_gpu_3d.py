@@ -35,12 +35,12 @@ def inputs(nx, ny, nz, k):
     return (u, v, w), A
 
 
-def ctx_of(nx, ny, nz, state, A, dtype="f64", prm=PRM, L=(1.0, 1.0, 1.0), zs=0):
+def ctx_of(nx, ny, nz, state, A, dtype="f64", prm=PRM, L=(1.0, 1.0, 1.0), zs=0, rows=0):
     ctx = pk.Context3(nx, ny, nz, *L, dtype=dtype)
     ctx.set_params(prm)
     ctx.set_tensor(*A)
     ctx.set_state(*state)
-    ctx.set_tuning(zs)
+    ctx.set_tuning(zs, rows)
     return ctx
 
 
@@ -52,17 +52,20 @@ def bitwise(got, ref):
             raise AssertionError(f"max |diff| {d.max():.3e} at {idx}: {x[idx]!r} vs {y[idx]!r}")
 
 
-SHAPES = [(1, 1, 1), (5, 3, 2), (64, 4, 3), (70, 9, 13), (130, 7, 5), (33, 65, 1), (1, 9, 17), (200, 3, 40)]
+# ragged in every direction: one cell, fewer rows than a wave holds, columns
+# across several 62-column strips with a ragged tail, single planes and layers
+SHAPES = [(1, 1, 1), (5, 3, 2), (62, 4, 3), (63, 2, 2), (70, 9, 13), (130, 7, 5), (33, 65, 1), (1, 9, 17),
+          (200, 3, 40), (125, 5, 6)]
 
 
 @pytest.mark.parametrize("nx,ny,nz", SHAPES)
-@pytest.mark.parametrize("zs", [0, 1, 3])
-def test_step3_f64_bitwise(nx, ny, nz, zs):
-    print(f"step3 f64 {nx}x{ny}x{nz} zs={zs}", flush=True)
+@pytest.mark.parametrize("zs,rows", [(0, 0), (1, 1), (3, 2), (2, 4), (5, 1)])
+def test_step3_f64_bitwise(nx, ny, nz, zs, rows):
+    print(f"step3 f64 {nx}x{ny}x{nz} zs={zs} rows={rows}", flush=True)
     state, A = inputs(nx, ny, nz, nx + 7 * ny + 13 * nz)
     L = (1.3, 0.7, 0.9)
     dt = 0.5 * oracle.stable_dt3(A, PRM[2], 0.9, *L)
-    with ctx_of(nx, ny, nz, state, A, L=L, zs=zs) as ctx:
+    with ctx_of(nx, ny, nz, state, A, L=L, zs=zs, rows=rows) as ctx:
         ctx.step(dt, 1)
         got = ctx.get_state()
         bitwise(got, oracle.step3(*state, A, PRM, dt, *L))
@@ -76,8 +79,8 @@ def test_step3_launch_shape_does_not_change_results():
     nx, ny, nz = 67, 10, 23
     state, A = inputs(nx, ny, nz, 1)
     outs = []
-    for zs in (0, 1, 2, 5, 23, 100):
-        with ctx_of(nx, ny, nz, state, A, zs=zs) as ctx:
+    for zs, rows in ((0, 0), (1, 1), (2, 2), (5, 4), (23, 2), (100, 1), (7, 4)):
+        with ctx_of(nx, ny, nz, state, A, zs=zs, rows=rows) as ctx:
             ctx.step(1e-6, 3)
             outs.append(ctx.get_state())
     for o in outs[1:]:
@@ -137,13 +140,14 @@ def test_step3_conserves_tumour_cells_and_acid_without_reactions():
 
 
 @pytest.mark.parametrize("nx,ny,nz", [(70, 9, 13), (33, 65, 4)])
-def test_step3_f32_within_tolerance(nx, ny, nz):
+@pytest.mark.parametrize("rows", [1, 2, 4])
+def test_step3_f32_within_tolerance(nx, ny, nz, rows):
     state, A = inputs(nx, ny, nz, 4)
     s32 = [x.astype(np.float32).astype(np.float64) for x in state]
     A32 = [x.astype(np.float32).astype(np.float64) for x in A]
     dt = float(np.float32(oracle.stable_dt3(A32, PRM[2], 0.9)))
     with ctx_of(nx, ny, nz, [x.astype(np.float32) for x in state], [x.astype(np.float32) for x in A],
-                dtype="f32") as ctx:
+                dtype="f32", rows=rows) as ctx:
         ctx.step(dt, 20)
         got = ctx.get_state()
     ref = oracle.run3(*s32, A32, PRM, dt, 20)
@@ -192,5 +196,7 @@ def test_step3_errors():
             ctx.step(1e-3, -1)
         with pytest.raises(pk.GGFVError):
             ctx.set_tuning(-1)
+        with pytest.raises(pk.GGFVError):
+            ctx.set_tuning(0, 3)
         with pytest.raises(ValueError):
             ctx.set_state(state[0][:4], state[1], state[2])
