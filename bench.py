@@ -67,10 +67,22 @@ def kernel_name(variant, tuning):
     return f"step_kernel<{T}, {comp}, {cpl}, {nt}>", "single"
 
 
-def traffic_sources(here):
-    return sorted(os.path.relpath(os.path.join(d, f), here)
-                  for d, _, fs in os.walk(os.path.join(here, "paper_2006_01748_amd", "csrc"))
-                  for f in fs if f.endswith((".hip", ".hpp")))
+# Sources of the three-dimensional kernels; every other csrc file belongs to the
+# two-dimensional ones.
+SOURCES_3D = ("ggfv3.hip", "ggfv_dpp.hpp", "ggfv_internal.hpp")
+
+
+def traffic_sources(here, family="2d"):
+    """Kernel sources whose change invalidates a counter summary of `family`."""
+    out = []
+    for d, _, fs in os.walk(os.path.join(here, "paper_2006_01748_amd", "csrc")):
+        for f in fs:
+            if not f.endswith((".hip", ".hpp")):
+                continue
+            keep = f in SOURCES_3D if family == "3d" else f != "ggfv3.hip"
+            if keep:
+                out.append(os.path.relpath(os.path.join(d, f), here))
+    return sorted(set(out))
 
 
 def sources_digest(here, srcs):
@@ -99,6 +111,26 @@ def measured_traffic(variant, tuning, rows):
     _, key = kernel_name(variant, tuning)
     t = data["bytes_per_launch"].get(f"{variant}/{key}")
     if t is None or t.get("rows") != rows:
+        return None
+    return t["read"] + t["write"]
+
+
+def measured_traffic3(dtype, shape):
+    """HBM bytes per launch of the 3D step kernel from the committed counter
+    summary, or None (no summary for this kernel and launch shape, or a 3D
+    kernel source changed since)."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "step3_kernel_traffic.json")) as f:
+            data = json.load(f)
+        if data["kernel_sources"] != traffic_sources(here, "3d"):
+            return None
+        if sources_digest(here, data["kernel_sources"]) != data.get("kernel_sources_sha256"):
+            return None
+    except (OSError, KeyError, ValueError):
+        return None
+    t = data["bytes_per_launch"].get(dtype)
+    if t is None or t.get("launch_shape") != shape:
         return None
     return t["read"] + t["write"]
 
@@ -345,14 +377,16 @@ def time_3d(pk, torch, n=256, steps=100, warmup=10, dtypes=("f64", "f32"), trial
         dt = ctx.stable_dt(w.safety)
         sweep = {}
         for rows in (1, 2, 4):
-            for zs in (0, 16, 32, 64):
-                ctx.set_tuning(zs, rows)
-                ctx.step(dt, 2)
-                torch.cuda.synchronize()
-                sweep[f"rows={rows},zs={zs}"] = timed(ctx, dt, trial_steps) * 1e3 / trial_steps
+            for zs in (16, 32, 64):
+                for wx, wy in ((1, 1), (1, 2), (1, 4), (5, 1), (4, 2), (2, 2)):
+                    ctx.set_tuning(zs, rows, wx, wy)
+                    ctx.step(dt, 2)
+                    torch.cuda.synchronize()
+                    sweep[f"rows={rows},zs={zs},wx={wx},wy={wy}"] = timed(ctx, dt, trial_steps) * 1e3 / trial_steps
         best = min(sweep, key=sweep.get)
-        rows, zs = (int(v.split("=")[1]) for v in best.split(","))
-        ctx.set_tuning(zs, rows)
+        rows, zs, wx, wy = (int(v.split("=")[1]) for v in best.split(","))
+        ctx.set_tuning(zs, rows, wx, wy)
+        shape = ctx.get_tuning()
         ctx.set_state(w.u0, w.v0, w.w0)
         ctx.step(dt, warmup)
         torch.cuda.synchronize()
@@ -364,9 +398,9 @@ def time_3d(pk, torch, n=256, steps=100, warmup=10, dtypes=("f64", "f32"), trial
         gbs = w.cells * per / (us * 1e-6) / 1e9
         out["variants"][dt_name] = {
             "value": w.cells * steps / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "kernel_avg_us": us,
-            "launch_shape": {"rows_per_wave": rows, "z_per_strip": zs},
+            "launch_shape": shape, "kernel": f"step3_pencil_kernel<{'double' if dt_name == 'f64' else 'float'}, {rows}>",
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": gbs / PEAK_HBM_GBS, "traffic": None},
+                         "frac": gbs / PEAK_HBM_GBS, "traffic": measured_traffic3(dt_name, shape)},
             "bytes_per_cell_update": per, "dt": dt, "mass": list(mass),
             "shape_sweep_us": {k: round(v, 1) for k, v in sweep.items()}}
     return out
@@ -471,7 +505,7 @@ PROFILE_COMMANDS = {
              "-- python3 $R/bench.py --steps 200 --warmup 12 --no-cpu-baseline --no-fronts > $P/trace_bench.json",
     "fronts": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/fronts -o fronts "
               "-- python3 $R/bench.py --variants f64 --no-tune --steps 4 --warmup 4 --no-cpu-baseline --no-adjoint "
-              "--no-ensemble --no-adaptive --no-copy-ceiling --fronts-t 0.02 > $P/fronts_bench.json",
+              "--no-ensemble --no-adaptive --no-copy-ceiling --no-3d --fronts-t 0.02 > $P/fronts_bench.json",
     "fetch": "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $P/fetch -o fetch "
              "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble "
              "--no-adaptive --no-fronts",
@@ -482,7 +516,8 @@ PROFILE_COMMANDS = {
 
 
 def _short(name):
-    name = name.replace("ggfv::(anonymous namespace)::", "").replace("void ", "")
+    name = name.replace("ggfv::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    name = name.replace("void ", "")
     depth, out = 0, []
     for ch in name:                      # drop the argument list
         if ch == "(" and depth == 0 and out:
@@ -628,6 +663,62 @@ def summarize_profiles(pdir):
                     "`front_row_kernel` / `front_final_kernel` are the front and gap diagnostics (one wave per row, "
                     f"then a fixed-order reduction).  bench.py in the same run: {fb['value']:.1f} Gcell/s over "
                     f"{fb['workload']}.\n")
+    three = bench.get("three_d")
+    if three:
+        # per-dispatch durations of the 3D kernel, by launch shape (grid size)
+        durs = collections.defaultdict(list)
+        with open(os.path.join(pdir, "trace", "trace_kernel_trace.csv")) as f:
+            for row in csv.DictReader(f):
+                name = _short(row["Kernel_Name"])
+                if name.startswith("step3_pencil_kernel"):
+                    durs[(name, int(row["Grid_Size_X"]))].append(
+                        (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+        n3 = [int(x) for x in three["workload"].split()[2].rstrip(",").split("x")]
+        cells3 = n3[0] * n3[1] * n3[2]
+        rows3, traffic3 = [], {}
+        for dt_name, vr in three["variants"].items():
+            shape = vr["launch_shape"]
+            key = (vr["kernel"], shape["workgroups"] * 64)
+            d = durs.get(key, [])
+            alg = vr["bytes_per_cell_update"] * cells3
+            alg_w = alg // 4                       # 3 of the 12 values are written
+            rd = fetch.get(key, float("nan")) * 1024 * f_scale
+            wr = write.get(key, float("nan")) * 1024 * w_scale
+            if key in fetch:
+                traffic3[dt_name] = {"kernel": vr["kernel"], "launch_shape": shape, "read": rd, "write": wr,
+                                     "fetch_kib": fetch[key], "write_kib": write.get(key, 0.0)}
+            avg = sum(d) / len(d) if d else float("nan")
+            rows3.append(f"| {dt_name} | {vr['kernel']} | {shape['rows_per_wave']} | {shape['z_per_strip']} | "
+                         f"{shape['workgroups']} | {len(d)} | {avg:.1f} | {vr['kernel_avg_us']:.1f} | "
+                         f"{alg / avg / 1e3:.0f} | {fetch.get(key, float('nan')):.0f} | "
+                         f"{write.get(key, float('nan')):.0f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
+                         f"{(alg - alg_w) / 1e6:.1f} / {alg_w / 1e6:.1f} | {(rd + wr) / alg:.3f} |")
+        srcs3 = traffic_sources(here, "3d")
+        with open(os.path.join(here, "profiles", "step3_kernel_traffic.json"), "w") as f:
+            json.dump({"note": f"HBM bytes per launch of the 3D step kernel on the {three['workload'].split(',')[0]} "
+                               "grid, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (separate runs), scaled by "
+                               f"the 1 GiB copyBuffer calibration (FETCH x{f_scale:.3f}, WRITE x{w_scale:.3f}); "
+                               "valid for the kernel sources with this digest and the launch shape given.",
+                       "kernel_sources": srcs3, "kernel_sources_sha256": sources_digest(here, srcs3),
+                       "bytes_per_launch": traffic3}, f, indent=1)
+        sweep = "\n".join(f"| {dt_name} | " + " | ".join(f"{k}: {v}" for k, v in vr["shape_sweep_us"].items()) + " |"
+                          for dt_name, vr in three["variants"].items())
+        with open(os.path.join(here, "profiles", "step3_kernels_256cube_slab_tissue.md"), "w") as f:
+            f.write("# Three-dimensional step kernel, 256^3 slab tissue (rocprofv3)\n\n"
+                    "Commands (from /tmp with TMPDIR=/tmp; $R = repository root, $P = output folder):\n\n"
+                    f"```\n{cmds}\n```\n\nSummary written by `python bench.py --summarize-profiles $P`.\n\n"
+                    "The trace and counter rows are the dispatches of the launch shape bench.py picked in the "
+                    "traced run (a short sweep of rows per wave x planes per strip precedes the timed steps).  "
+                    "Algorithmic bytes per cell-update: u, v, w and the six tensor entries read once, u, v, w "
+                    "written once (96 B in FP64, 48 B in FP32).\n\n"
+                    "| dtype | kernel | rows per wave | planes per strip | workgroups | dispatches (trace) | "
+                    "average (us, trace) | average (us, live HIP events) | algorithmic GB/s (trace) | "
+                    "FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | scaled read (MB) | scaled write (MB) | "
+                    "algorithmic read / write (MB) | traffic / algorithmic |\n"
+                    "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|\n" + "\n".join(rows3) +
+                    "\n\n## Launch-shape sweep in the traced run (us per step)\n\n| dtype | shapes |\n|---|---|\n"
+                    + sweep + "\n")
+        traffic["three_d"] = traffic3
     print(json.dumps({"calibration": {"fetch": f_scale, "write": w_scale}, "traffic": traffic}, indent=1))
 
 

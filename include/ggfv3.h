@@ -63,10 +63,17 @@ int ggfv3_step(ggfv3_ctx *ctx, double dt, long long nsteps);
 int ggfv3_mass(ggfv3_ctx *ctx, double *mass3);
 /* Simulated time and step count of the context. */
 int ggfv3_time(const ggfv3_ctx *ctx, double *t, long long *steps);
-/* Launch shape: the number of planes each wave marches through and the number
- * of rows each wave holds (1, 2 or 4); 0 leaves the library's choice.  Results
- * are identical for every shape.  EINVAL on other values. */
-int ggfv3_set_tuning(ggfv3_ctx *ctx, int z_per_strip, int rows_per_wave);
+/* Launch shape: the number of planes each wave marches through, the number of
+ * rows each wave holds (1, 2 or 4), and the waves of one workgroup along x and
+ * y (which march in step); 0 leaves the library's choice.  Results are
+ * identical for every shape.  EINVAL on negative values, other row counts or
+ * more than 8 waves per workgroup. */
+int ggfv3_set_tuning(ggfv3_ctx *ctx, int z_per_strip, int rows_per_wave, int waves_x, int waves_y);
+/* The launch shape the next step uses, defaults resolved, and the number of
+ * workgroups a step launches (any pointer may be NULL).  EINVAL on a NULL
+ * context. */
+int ggfv3_get_tuning(const ggfv3_ctx *ctx, int *z_per_strip, int *rows_per_wave, int *waves_x, int *waves_y,
+                     long long *workgroups);
 /* Last failure message of ctx ("" if none); ctx == NULL: the last failed
  * ggfv3_create on the calling thread. */
 const char *ggfv3_last_error(const ggfv3_ctx *ctx);

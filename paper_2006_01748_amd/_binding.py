@@ -76,7 +76,8 @@ _SIGNATURES = [
     ("ggfv3_step", _c.c_int, [_VP, _c.c_double, _c.c_longlong]),
     ("ggfv3_mass", _c.c_int, [_VP, _c.POINTER(_c.c_double)]),
     ("ggfv3_time", _c.c_int, [_VP, _c.POINTER(_c.c_double), _c.POINTER(_c.c_longlong)]),
-    ("ggfv3_set_tuning", _c.c_int, [_VP, _c.c_int, _c.c_int]),
+    ("ggfv3_set_tuning", _c.c_int, [_VP, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    ("ggfv3_get_tuning", _c.c_int, [_VP] + [_c.POINTER(_c.c_int)] * 4 + [_c.POINTER(_c.c_longlong)]),
     ("ggfv3_last_error", _c.c_char_p, [_VP]),
 ]
 
@@ -593,5 +594,14 @@ class Context3:
         self._check(self._lib.ggfv3_time(self._h, ctypes.byref(t), ctypes.byref(n)))
         return t.value, n.value
 
-    def set_tuning(self, z_per_strip=0, rows_per_wave=0):
-        self._check(self._lib.ggfv3_set_tuning(self._h, int(z_per_strip), int(rows_per_wave)))
+    def set_tuning(self, z_per_strip=0, rows_per_wave=0, waves_x=0, waves_y=0):
+        self._check(self._lib.ggfv3_set_tuning(self._h, int(z_per_strip), int(rows_per_wave), int(waves_x),
+                                               int(waves_y)))
+
+    def get_tuning(self):
+        """Effective launch shape, with the number of workgroups a step launches."""
+        v = [ctypes.c_int() for _ in range(4)]
+        g = ctypes.c_longlong()
+        self._check(self._lib.ggfv3_get_tuning(self._h, *(ctypes.byref(x) for x in v), ctypes.byref(g)))
+        return {"z_per_strip": v[0].value, "rows_per_wave": v[1].value, "waves_x": v[2].value,
+                "waves_y": v[3].value, "workgroups": g.value}

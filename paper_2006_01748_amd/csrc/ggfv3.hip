@@ -72,6 +72,7 @@ struct ggfv3_ctx {
     long long steps = 0;
     int zs = 0;                    // planes per strip (0: default)
     int rows = 0;                  // rows per wave (0: default)
+    int wx = 0, wy = 0;            // waves per workgroup along x, y (0: default)
     std::string err;
 };
 
@@ -175,16 +176,29 @@ __device__ __forceinline__ void gst(__amdgpu_buffer_rsrc_t r, unsigned voff, uns
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
+// Pencils of one workgroup: wx x-strips by wy row groups, marching in step (one
+// barrier per plane) so that the columns and rows they share are read from
+// the caches at about the same time.
+struct PencilGrid {
+    int nbx, nby, nzb;             // workgroups along x, y, z
+    int wx, wy;                    // waves per workgroup along x, y
+};
+
+constexpr int kMaxWaves3 = 8;
+
 template <typename T, int R>
-__global__ __launch_bounds__(64) void step3_pencil_kernel(Step3Args<T> A, int nsx, int ngy, int nzb)
+__global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args<T> A, PencilGrid G)
 {
     using ggfv::from_left;
     using ggfv::from_right;
     constexpr int NR = R + 2;                      // rows held: j0-1 .. j0+R
-    const int lid = xcd_local_id3(blockIdx.x, nsx * ngy * nzb);
-    const int sx = lid % nsx, rest = lid / nsx;
-    const int gy = rest % ngy, zb = rest / ngy;
-    const int lane = threadIdx.x;
+    const int lid = xcd_local_id3(blockIdx.x, G.nbx * G.nby * G.nzb);
+    const int bx = lid % G.nbx, rest = lid / G.nbx;
+    const int by = rest % G.nby, zb = rest / G.nby;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sx = bx * G.wx + wave % G.wx;        // strips and row groups past the grid
+    const int gy = by * G.wy + wave / G.wx;        // read clamped and store nothing
+    const bool sync = G.wx * G.wy > 1;
     const int x = sx * kStrip - 1 + lane;
     const int xl = min(max(x, 0), A.nx - 1);
     const bool east_edge = x >= A.nx - 1, west_edge = x <= 0;
@@ -359,6 +373,7 @@ __global__ __launch_bounds__(64) void step3_pencil_kernel(Step3Args<T> A, int ns
             FZb[r] = FZt[r];
             GZb[r] = GZt[r];
         }
+        if (sync) __syncthreads();                 // workgroup-uniform
     }
 }
 
@@ -581,30 +596,49 @@ Step3Args<T> args3(const ggfv3_ctx *ctx, double dt)
 }
 
 struct Shape3 {
-    int rows, nsx, ngy, nzb, zs;
+    int rows, nsx, ngy, zs;
+    PencilGrid G;
 };
 
-// Pencil shape: rows per wave (1, 2 or 4) and planes per strip.  By default
-// enough strips of z that the grid holds about 16 waves per CU on 256 CUs.
+// Pencil shape: rows per wave (1, 2 or 4), planes per strip and waves per
+// workgroup.  Defaults (measured on the 256^3 workload): two rows per wave;
+// FP64 with two row groups per workgroup and about 2560 waves in the grid,
+// FP32 with every x-strip of a row group in one workgroup (up to 8) and about
+// 5120 waves.
 Shape3 shape3(const ggfv3_ctx *ctx)
 {
     Shape3 S{};
+    const bool f64 = ctx->dtype == GGFV_F64;
     S.rows = ctx->rows > 0 ? ctx->rows : 2;
     S.nsx = (ctx->nx + kStrip - 1) / kStrip;
     S.ngy = (ctx->ny + S.rows - 1) / S.rows;
+    if (ctx->wx > 0 || ctx->wy > 0) {
+        S.G.wx = ctx->wx > 0 ? ctx->wx : 1;
+        S.G.wy = ctx->wy > 0 ? ctx->wy : 1;
+    } else if (f64) {
+        S.G.wx = 1;
+        S.G.wy = 2;
+    } else {
+        S.G.wx = S.nsx <= kMaxWaves3 ? S.nsx : 1;
+        S.G.wy = 1;
+    }
     int zs = ctx->zs;
     if (zs <= 0) {
         const long pencils = (long)S.nsx * S.ngy;
-        const long target = 4096;
+        const long target = f64 ? 2560 : 5120;
         long nzb = (target + pencils - 1) / pencils;
         if (nzb < 1) nzb = 1;
         zs = (int)((ctx->nz + nzb - 1) / nzb);
         if (zs < 8) zs = 8;
     }
     S.zs = zs > ctx->nz ? ctx->nz : zs;
-    S.nzb = (ctx->nz + S.zs - 1) / S.zs;
+    S.G.nbx = (S.nsx + S.G.wx - 1) / S.G.wx;
+    S.G.nby = (S.ngy + S.G.wy - 1) / S.G.wy;
+    S.G.nzb = (ctx->nz + S.zs - 1) / S.zs;
     return S;
 }
+
+long long workgroups3(const Shape3 &S) { return (long long)S.G.nbx * S.G.nby * S.G.nzb; }
 
 template <typename T>
 hipError_t launch3(ggfv3_ctx *ctx, double dt)
@@ -612,18 +646,18 @@ hipError_t launch3(ggfv3_ctx *ctx, double dt)
     Step3Args<T> A = args3<T>(ctx, dt);
     const Shape3 S = shape3(ctx);
     A.zs = S.zs;
-    const long nb = (long)S.nsx * S.ngy * S.nzb;
-    if (nb > 0x7fffffffL) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)nb), block(64);
+    const long long nb = workgroups3(S);
+    if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nb), block(64 * S.G.wx * S.G.wy);
     switch (S.rows) {
     case 1:
-        hipLaunchKernelGGL((step3_pencil_kernel<T, 1>), grid, block, 0, ctx->stream, A, S.nsx, S.ngy, S.nzb);
+        hipLaunchKernelGGL((step3_pencil_kernel<T, 1>), grid, block, 0, ctx->stream, A, S.G);
         break;
     case 2:
-        hipLaunchKernelGGL((step3_pencil_kernel<T, 2>), grid, block, 0, ctx->stream, A, S.nsx, S.ngy, S.nzb);
+        hipLaunchKernelGGL((step3_pencil_kernel<T, 2>), grid, block, 0, ctx->stream, A, S.G);
         break;
     default:
-        hipLaunchKernelGGL((step3_pencil_kernel<T, 4>), grid, block, 0, ctx->stream, A, S.nsx, S.ngy, S.nzb);
+        hipLaunchKernelGGL((step3_pencil_kernel<T, 4>), grid, block, 0, ctx->stream, A, S.G);
         break;
     }
     return hipGetLastError();
@@ -830,14 +864,32 @@ int ggfv3_time(const ggfv3_ctx *ctx, double *t, long long *steps)
     return GGFV_OK;
 }
 
-int ggfv3_set_tuning(ggfv3_ctx *ctx, int z_per_strip, int rows_per_wave)
+int ggfv3_set_tuning(ggfv3_ctx *ctx, int z_per_strip, int rows_per_wave, int waves_x, int waves_y)
 {
     if (!ctx) return GGFV_EINVAL;
     if (z_per_strip < 0) return fail3(ctx, GGFV_EINVAL, "z_per_strip must be >= 0");
     if (rows_per_wave != 0 && rows_per_wave != 1 && rows_per_wave != 2 && rows_per_wave != 4)
         return fail3(ctx, GGFV_EINVAL, "rows_per_wave must be 0, 1, 2 or 4");
+    if (waves_x < 0 || waves_y < 0 || (waves_x > 0 ? waves_x : 1) * (waves_y > 0 ? waves_y : 1) > kMaxWaves3)
+        return fail3(ctx, GGFV_EINVAL, "waves_x and waves_y must be >= 0 with at most %d waves per workgroup",
+                     kMaxWaves3);
     ctx->zs = z_per_strip;
     ctx->rows = rows_per_wave;
+    ctx->wx = waves_x;
+    ctx->wy = waves_y;
+    return GGFV_OK;
+}
+
+int ggfv3_get_tuning(const ggfv3_ctx *ctx, int *z_per_strip, int *rows_per_wave, int *waves_x, int *waves_y,
+                     long long *workgroups)
+{
+    if (!ctx) return GGFV_EINVAL;
+    const Shape3 S = shape3(ctx);
+    if (z_per_strip) *z_per_strip = S.zs;
+    if (rows_per_wave) *rows_per_wave = S.rows;
+    if (waves_x) *waves_x = S.G.wx;
+    if (waves_y) *waves_y = S.G.wy;
+    if (workgroups) *workgroups = workgroups3(S);
     return GGFV_OK;
 }
 

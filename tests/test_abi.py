@@ -109,6 +109,6 @@ def test_null_context3_is_rejected(built):
     assert lib.ggfv3_step(None, 1e-3, 1) == pk.GGFV_EINVAL
     assert lib.ggfv3_set_params(None, None) == pk.GGFV_EINVAL
     assert lib.ggfv3_mass(None, None) == pk.GGFV_EINVAL
-    assert lib.ggfv3_set_tuning(None, 4, 0) == pk.GGFV_EINVAL
+    assert lib.ggfv3_set_tuning(None, 4, 0, 0, 0) == pk.GGFV_EINVAL
     assert lib.ggfv3_create(None, 4, 4, 4, 1.0, 1.0, 1.0, pk.GGFV_F64, 0, None) == pk.GGFV_EINVAL
     lib.ggfv3_destroy(None)

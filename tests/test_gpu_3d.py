@@ -35,12 +35,12 @@ def inputs(nx, ny, nz, k):
     return (u, v, w), A
 
 
-def ctx_of(nx, ny, nz, state, A, dtype="f64", prm=PRM, L=(1.0, 1.0, 1.0), zs=0, rows=0):
+def ctx_of(nx, ny, nz, state, A, dtype="f64", prm=PRM, L=(1.0, 1.0, 1.0), zs=0, rows=0, wx=0, wy=0):
     ctx = pk.Context3(nx, ny, nz, *L, dtype=dtype)
     ctx.set_params(prm)
     ctx.set_tensor(*A)
     ctx.set_state(*state)
-    ctx.set_tuning(zs, rows)
+    ctx.set_tuning(zs, rows, wx, wy)
     return ctx
 
 
@@ -59,13 +59,14 @@ SHAPES = [(1, 1, 1), (5, 3, 2), (62, 4, 3), (63, 2, 2), (70, 9, 13), (130, 7, 5)
 
 
 @pytest.mark.parametrize("nx,ny,nz", SHAPES)
-@pytest.mark.parametrize("zs,rows", [(0, 0), (1, 1), (3, 2), (2, 4), (5, 1)])
-def test_step3_f64_bitwise(nx, ny, nz, zs, rows):
-    print(f"step3 f64 {nx}x{ny}x{nz} zs={zs} rows={rows}", flush=True)
+@pytest.mark.parametrize("zs,rows,wx,wy", [(0, 0, 0, 0), (1, 1, 1, 1), (3, 2, 2, 2), (2, 4, 1, 4), (5, 1, 4, 2),
+                                            (4, 2, 3, 1)])
+def test_step3_f64_bitwise(nx, ny, nz, zs, rows, wx, wy):
+    print(f"step3 f64 {nx}x{ny}x{nz} zs={zs} rows={rows} waves={wx}x{wy}", flush=True)
     state, A = inputs(nx, ny, nz, nx + 7 * ny + 13 * nz)
     L = (1.3, 0.7, 0.9)
     dt = 0.5 * oracle.stable_dt3(A, PRM[2], 0.9, *L)
-    with ctx_of(nx, ny, nz, state, A, L=L, zs=zs, rows=rows) as ctx:
+    with ctx_of(nx, ny, nz, state, A, L=L, zs=zs, rows=rows, wx=wx, wy=wy) as ctx:
         ctx.step(dt, 1)
         got = ctx.get_state()
         bitwise(got, oracle.step3(*state, A, PRM, dt, *L))
@@ -79,8 +80,9 @@ def test_step3_launch_shape_does_not_change_results():
     nx, ny, nz = 67, 10, 23
     state, A = inputs(nx, ny, nz, 1)
     outs = []
-    for zs, rows in ((0, 0), (1, 1), (2, 2), (5, 4), (23, 2), (100, 1), (7, 4)):
-        with ctx_of(nx, ny, nz, state, A, zs=zs, rows=rows) as ctx:
+    for zs, rows, wx, wy in ((0, 0, 0, 0), (1, 1, 1, 1), (2, 2, 2, 4), (5, 4, 8, 1), (23, 2, 1, 8), (100, 1, 2, 2),
+                             (7, 4, 2, 3)):
+        with ctx_of(nx, ny, nz, state, A, zs=zs, rows=rows, wx=wx, wy=wy) as ctx:
             ctx.step(1e-6, 3)
             outs.append(ctx.get_state())
     for o in outs[1:]:
@@ -198,5 +200,15 @@ def test_step3_errors():
             ctx.set_tuning(-1)
         with pytest.raises(pk.GGFVError):
             ctx.set_tuning(0, 3)
+        with pytest.raises(pk.GGFVError):
+            ctx.set_tuning(0, 0, 3, 3)
+        ctx.set_tuning(3, 4, 1, 1)
+        assert ctx.get_tuning() == {"z_per_strip": 3, "rows_per_wave": 4, "waves_x": 1, "waves_y": 1,
+                                    "workgroups": 1 * 2 * 3}
+        ctx.set_tuning(3, 1, 1, 4)
+        assert ctx.get_tuning()["workgroups"] == 1 * 2 * 3
+        ctx.set_tuning(0, 0)
+        t = ctx.get_tuning()
+        assert t["rows_per_wave"] in (1, 2, 4) and 1 <= t["z_per_strip"] <= 8
         with pytest.raises(ValueError):
             ctx.set_state(state[0][:4], state[1], state[2])
