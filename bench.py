@@ -512,6 +512,13 @@ PROFILE_COMMANDS = {
     "write": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/write -o write "
              "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble "
              "--no-adaptive --no-fronts",
+    # the three-dimensional kernel alone (with the copy used for calibration)
+    "trace3": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/trace3 -o trace3 "
+              "-- python3 $R/bench.py --only-3d > $P/trace3_bench.json",
+    "fetch3": "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $P/fetch3 -o fetch3 "
+              "-- python3 $R/bench.py --only-3d",
+    "write3": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/write3 -o write3 "
+              "-- python3 $R/bench.py --only-3d",
 }
 
 
@@ -528,10 +535,108 @@ def _short(name):
     return "".join(out).strip()
 
 
+def _counter_means(pdir, kind):
+    """Mean counter value per (kernel, grid size) over the dispatches of one --pmc run."""
+    import csv
+    import collections
+    vals, meta = collections.defaultdict(float), {}
+    with open(os.path.join(pdir, kind, f"{kind}_counter_collection.csv")) as f:
+        for row in csv.DictReader(f):
+            d = int(row["Dispatch_Id"])
+            vals[d] += float(row["Counter_Value"])
+            meta[d] = (_short(row["Kernel_Name"]), int(row["Grid_Size"]))
+    agg = collections.defaultdict(list)
+    for d, v in vals.items():
+        agg[meta[d]].append(v)
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def _copy_calibration(fetch, write, copy_bytes=1 << 30):
+    cal = [k for k in fetch if k[0] == "__amd_rocclr_copyBuffer"]
+    ck = max(cal, key=lambda k: k[1])
+    return ck, copy_bytes / (fetch[ck] * 1024), copy_bytes / (write[ck] * 1024)
+
+
+def summarize_3d(pdir, tdir, fdir, wdir, bench_json):
+    """profiles/step3_kernels_256cube_slab_tissue.md and profiles/step3_kernel_traffic.json."""
+    import csv
+    import collections
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(pdir, bench_json)) as f:
+        three = json.loads(f.read().strip().splitlines()[-1])["three_d"]
+    fetch, write = _counter_means(pdir, fdir), _counter_means(pdir, wdir)
+    ck, f_scale, w_scale = _copy_calibration(fetch, write)
+    durs = collections.defaultdict(list)
+    with open(os.path.join(pdir, tdir, f"{tdir}_kernel_trace.csv")) as f:
+        for row in csv.DictReader(f):
+            name = _short(row["Kernel_Name"])
+            if name.startswith("step3_pencil_kernel"):
+                durs[(name, int(row["Grid_Size_X"]))].append(
+                    (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+    n3 = [int(x) for x in three["workload"].split()[2].rstrip(",").split("x")]
+    cells3 = n3[0] * n3[1] * n3[2]
+    rows3, traffic3 = [], {}
+    for dt_name, vr in three["variants"].items():
+        shape = vr["launch_shape"]
+        threads = shape["workgroups"] * 64 * shape["waves_x"] * shape["waves_y"]
+        key = (vr["kernel"], threads)
+        d = durs.get(key, [])
+        alg = vr["bytes_per_cell_update"] * cells3
+        alg_w = alg // 4                           # 3 of the 12 values are written
+        rd = fetch.get(key, float("nan")) * 1024 * f_scale
+        wr = write.get(key, float("nan")) * 1024 * w_scale
+        if key in fetch and key in write:
+            traffic3[dt_name] = {"kernel": vr["kernel"], "launch_shape": shape, "read": rd, "write": wr,
+                                 "fetch_kib": fetch[key], "write_kib": write[key]}
+        avg = sum(d) / len(d) if d else float("nan")
+        rows3.append(f"| {dt_name} | {vr['kernel']} | {shape['rows_per_wave']} | {shape['z_per_strip']} | "
+                     f"{shape['waves_x']}x{shape['waves_y']} | {shape['workgroups']} | {len(d)} | {avg:.1f} | "
+                     f"{vr['kernel_avg_us']:.1f} | {alg / avg / 1e3:.0f} | {fetch.get(key, float('nan')):.0f} | "
+                     f"{write.get(key, float('nan')):.0f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
+                     f"{(alg - alg_w) / 1e6:.1f} / {alg_w / 1e6:.1f} | {(rd + wr) / alg:.3f} |")
+    srcs3 = traffic_sources(here, "3d")
+    with open(os.path.join(here, "profiles", "step3_kernel_traffic.json"), "w") as f:
+        json.dump({"note": f"HBM bytes per launch of the 3D step kernel on the {three['workload'].split(',')[0]} "
+                           "grid, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (separate runs), scaled by "
+                           f"the 1 GiB copyBuffer calibration (FETCH x{f_scale:.3f}, WRITE x{w_scale:.3f}); "
+                           "valid for the kernel sources with this digest and the launch shape given.",
+                   "kernel_sources": srcs3, "kernel_sources_sha256": sources_digest(here, srcs3),
+                   "bytes_per_launch": traffic3}, f, indent=1)
+    sweep = []
+    for dt_name, vr in three["variants"].items():
+        best = sorted(vr["shape_sweep_us"].items(), key=lambda x: x[1])
+        sweep.append(f"| {dt_name} | " + "; ".join(f"{k}: {v}" for k, v in best[:6]) + " | " +
+                     "; ".join(f"{k}: {v}" for k, v in best[-2:]) + " |")
+    cmds = "\n".join(PROFILE_COMMANDS[k] for k in (tdir, fdir, wdir))
+    with open(os.path.join(here, "profiles", "step3_kernels_256cube_slab_tissue.md"), "w") as f:
+        f.write("# Three-dimensional step kernel, 256^3 slab tissue (rocprofv3)\n\n"
+                "Commands (from /tmp with TMPDIR=/tmp; $R = repository root, $P = output folder):\n\n"
+                f"```\n{cmds}\n```\n\nSummary written by `python bench.py --summarize-profiles $P`.\n\n"
+                "The trace and counter rows are the dispatches of the launch shape bench.py picked in the "
+                "traced run (a short sweep of rows per wave x planes per strip x waves per workgroup "
+                "precedes the timed steps).  Algorithmic bytes per cell-update: u, v, w and the six tensor "
+                "entries read once, u, v, w written once (96 B in FP64, 48 B in FP32).  Counter calibration: "
+                f"the 1 GiB `__amd_rocclr_copyBuffer` reads FETCH_SIZE = {fetch[ck]:.0f} KiB and WRITE_SIZE = "
+                f"{write[ck]:.0f} KiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.\n\n"
+                "| dtype | kernel | rows per wave | planes per strip | waves per workgroup | workgroups | "
+                "dispatches (trace) | average (us, trace) | average (us, live HIP events) | algorithmic GB/s "
+                "(trace) | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | scaled read (MB) | scaled write (MB) | "
+                "algorithmic read / write (MB) | traffic / algorithmic |\n"
+                "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|\n" + "\n".join(rows3) +
+                "\n\n## Launch-shape sweep in the traced run (us per step): six fastest; two slowest\n\n"
+                "| dtype | fastest | slowest |\n|---|---|---|\n" + "\n".join(sweep) + "\n")
+    return traffic3
+
+
 def summarize_profiles(pdir):
     """Write profiles/*.md and profiles/step_kernel_traffic.json from the CSV
     output of PROFILE_COMMANDS (trace/, fetch/, write/ and trace_bench.json
-    under pdir)."""
+    under pdir; trace3/, fetch3/, write3/ and trace3_bench.json for the 3D
+    kernel, which may be present alone)."""
+    if not os.path.isdir(os.path.join(pdir, "trace")):
+        print(json.dumps({"three_d": summarize_3d(pdir, "trace3", "fetch3", "write3", "trace3_bench.json")},
+                         indent=1))
+        return
     import csv
     import collections
     here = os.path.dirname(os.path.abspath(__file__))
@@ -663,62 +768,10 @@ def summarize_profiles(pdir):
                     "`front_row_kernel` / `front_final_kernel` are the front and gap diagnostics (one wave per row, "
                     f"then a fixed-order reduction).  bench.py in the same run: {fb['value']:.1f} Gcell/s over "
                     f"{fb['workload']}.\n")
-    three = bench.get("three_d")
-    if three:
-        # per-dispatch durations of the 3D kernel, by launch shape (grid size)
-        durs = collections.defaultdict(list)
-        with open(os.path.join(pdir, "trace", "trace_kernel_trace.csv")) as f:
-            for row in csv.DictReader(f):
-                name = _short(row["Kernel_Name"])
-                if name.startswith("step3_pencil_kernel"):
-                    durs[(name, int(row["Grid_Size_X"]))].append(
-                        (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
-        n3 = [int(x) for x in three["workload"].split()[2].rstrip(",").split("x")]
-        cells3 = n3[0] * n3[1] * n3[2]
-        rows3, traffic3 = [], {}
-        for dt_name, vr in three["variants"].items():
-            shape = vr["launch_shape"]
-            key = (vr["kernel"], shape["workgroups"] * 64)
-            d = durs.get(key, [])
-            alg = vr["bytes_per_cell_update"] * cells3
-            alg_w = alg // 4                       # 3 of the 12 values are written
-            rd = fetch.get(key, float("nan")) * 1024 * f_scale
-            wr = write.get(key, float("nan")) * 1024 * w_scale
-            if key in fetch:
-                traffic3[dt_name] = {"kernel": vr["kernel"], "launch_shape": shape, "read": rd, "write": wr,
-                                     "fetch_kib": fetch[key], "write_kib": write.get(key, 0.0)}
-            avg = sum(d) / len(d) if d else float("nan")
-            rows3.append(f"| {dt_name} | {vr['kernel']} | {shape['rows_per_wave']} | {shape['z_per_strip']} | "
-                         f"{shape['workgroups']} | {len(d)} | {avg:.1f} | {vr['kernel_avg_us']:.1f} | "
-                         f"{alg / avg / 1e3:.0f} | {fetch.get(key, float('nan')):.0f} | "
-                         f"{write.get(key, float('nan')):.0f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
-                         f"{(alg - alg_w) / 1e6:.1f} / {alg_w / 1e6:.1f} | {(rd + wr) / alg:.3f} |")
-        srcs3 = traffic_sources(here, "3d")
-        with open(os.path.join(here, "profiles", "step3_kernel_traffic.json"), "w") as f:
-            json.dump({"note": f"HBM bytes per launch of the 3D step kernel on the {three['workload'].split(',')[0]} "
-                               "grid, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (separate runs), scaled by "
-                               f"the 1 GiB copyBuffer calibration (FETCH x{f_scale:.3f}, WRITE x{w_scale:.3f}); "
-                               "valid for the kernel sources with this digest and the launch shape given.",
-                       "kernel_sources": srcs3, "kernel_sources_sha256": sources_digest(here, srcs3),
-                       "bytes_per_launch": traffic3}, f, indent=1)
-        sweep = "\n".join(f"| {dt_name} | " + " | ".join(f"{k}: {v}" for k, v in vr["shape_sweep_us"].items()) + " |"
-                          for dt_name, vr in three["variants"].items())
-        with open(os.path.join(here, "profiles", "step3_kernels_256cube_slab_tissue.md"), "w") as f:
-            f.write("# Three-dimensional step kernel, 256^3 slab tissue (rocprofv3)\n\n"
-                    "Commands (from /tmp with TMPDIR=/tmp; $R = repository root, $P = output folder):\n\n"
-                    f"```\n{cmds}\n```\n\nSummary written by `python bench.py --summarize-profiles $P`.\n\n"
-                    "The trace and counter rows are the dispatches of the launch shape bench.py picked in the "
-                    "traced run (a short sweep of rows per wave x planes per strip precedes the timed steps).  "
-                    "Algorithmic bytes per cell-update: u, v, w and the six tensor entries read once, u, v, w "
-                    "written once (96 B in FP64, 48 B in FP32).\n\n"
-                    "| dtype | kernel | rows per wave | planes per strip | workgroups | dispatches (trace) | "
-                    "average (us, trace) | average (us, live HIP events) | algorithmic GB/s (trace) | "
-                    "FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | scaled read (MB) | scaled write (MB) | "
-                    "algorithmic read / write (MB) | traffic / algorithmic |\n"
-                    "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|\n" + "\n".join(rows3) +
-                    "\n\n## Launch-shape sweep in the traced run (us per step)\n\n| dtype | shapes |\n|---|---|\n"
-                    + sweep + "\n")
-        traffic["three_d"] = traffic3
+    if os.path.isdir(os.path.join(pdir, "trace3")):
+        traffic["three_d"] = summarize_3d(pdir, "trace3", "fetch3", "write3", "trace3_bench.json")
+    elif bench.get("three_d"):
+        traffic["three_d"] = summarize_3d(pdir, "trace", "fetch", "write", "trace_bench.json")
     print(json.dumps({"calibration": {"fetch": f_scale, "write": w_scale}, "traffic": traffic}, indent=1))
 
 
@@ -737,6 +790,8 @@ def main():
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-fronts", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="time the three-dimensional step and the copy ceiling only (for its profiles)")
     ap.add_argument("--fronts-t", type=float, default=0.5, help="simulated time of the invasion sweep")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
     ap.add_argument("--autotune", action="store_true",
@@ -766,6 +821,10 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.only_3d:
+        three = time_3d(pk, torch)
+        print(json.dumps({"three_d": three, "copy_ceiling_GBs": copy_ceiling(torch)}), flush=True)
+        return
     log(f"generating {args.n}x{args.n} layered-tissue workload")
     w = wl.cfg2(n=args.n)
     variants = [v for v in args.variants.split(",") if v]
