@@ -34,9 +34,9 @@ PEAK_HBM_GBS = 8000.0            # MI355X HBM3E peak
 # v and w).
 BYTES_PER_CELL = {"f64": 72, "f32c": 60, "f32": 36}
 # Launch shapes of the headline runs: (rows per strip, threads, steps per
-# launch, lane-shift kernels), as the autotuner picks them on MI355X for this
-# workload.
-HEADLINE_SHAPE = {"f64": (32, 64, 4, 1), "f32c": (16, 64, 4, 1), "f32": (32, 64, 4, 1)}
+# launch, lane-shift kernels: 1, or 2 for wide lanes).  Rows 0 is the library's
+# height, the tallest strips whose waves fill the resident slots once.
+HEADLINE_SHAPE = {"f64": (0, 64, 4, 2), "f32c": (0, 64, 4, 1), "f32": (0, 64, 4, 2)}
 METRIC = "Gcell-updates/s + % HBM peak, 4096² aniso FV step FP32/FP64; adjoint/fwd ratio"
 # Algorithmic floating-point operations per cell-update (each face flux counted
 # once, shared by its two cells): x/y faces of W 2 x 10, tangential differences
@@ -58,6 +58,8 @@ def kernel_name(variant, tuning):
     comp = "true" if variant == "f32c" else "false"
     cpl = 1 if variant == "f64" else 2
     K = max(1, tuning.get("fused_steps", 1))
+    if tuning.get("lane_shift") == 2:          # wide lanes: 16 bytes of columns per lane
+        return f"fused_dpp_kernel<{T}, {comp}, {2 * cpl}, {K}>", f"wide{K}"
     if tuning.get("lane_shift"):
         return f"fused_dpp_kernel<{T}, {comp}, {cpl}, {K}>", f"lanes{K}"
     if K > 1:

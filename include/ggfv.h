@@ -266,7 +266,9 @@ int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const v
                       void *g_th, int where, int io_dtype);
 
 /* Launch shape of the step.  rows_per_strip is the number of grid rows one
- * workgroup sweeps (0 = chosen from the grid size).  threads is the workgroup
+ * workgroup sweeps (0 = chosen from the grid size; for the lane-shift kernels,
+ * the tallest strips whose workgroups fill the device's resident slots once,
+ * from the kernel's occupancy and the number of compute units).  threads is the workgroup
  * width, 64, 128 or 256 (0 = chosen from the grid size); fused launches use 64
  * or 128 (256 acts as 128, and depth 4 always uses 64).  fused_steps (1..4, 0 =
  * 1) is the number of time steps computed per launch: the old state is read
@@ -275,8 +277,11 @@ int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const v
  * uses n / fused_steps fused launches and single steps for the remainder.
  * lane_shift = 1 selects the one-wave kernels that keep the rows of every time
  * level in registers and exchange x-neighbours by lane shifts (threads is then
- * ignored; fused_steps 1..4 applies).  Every shape gives the same results bit
- * for bit.  EINVAL for values outside these sets. */
+ * ignored; fused_steps 1..4 applies); lane_shift = 2 the same kernels with
+ * wide lanes, 16 bytes of columns per lane (two FP64 or four FP32 columns:
+ * half the lane shifts and halo columns per cell, twice the registers; not for
+ * GGFV_F32C).  Every shape gives the same results bit for bit.  EINVAL for
+ * values outside these sets. */
 typedef struct {
     int rows_per_strip;
     int threads;
@@ -288,10 +293,11 @@ int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
 int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
 
 /* Time `trial_steps` steps for each candidate shape (fused depths 1..4, widths
- * 64, 128, 256 and the lane-shift kernels, strip heights 2..128 (2, 4, 8, 16, 24, 32,
- * 48, 64, 128) and the
- * default) on the context's own data, keep the fastest per step as the
- * context's tuning and return it.  The state, simulated time and step count are restored
+ * 64, 128, 256 and the lane-shift kernels, strip heights 2, 4, 8, 16, 24, 32,
+ * 48, 64, 128, the default, and for the lane-shift kernels the heights that
+ * fill the resident slots half a round, 1.5 and 2 rounds over) on the
+ * context's own data, keep the fastest per step as the context's tuning and
+ * return it (with the height it ran).  The state, simulated time and step count are restored
  * afterwards.  Needs state, tensor and parameters.  Synchronizes. */
 int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best);
 

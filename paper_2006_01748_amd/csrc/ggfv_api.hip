@@ -192,8 +192,14 @@ int ggfv_create(ggfv_ctx **out, int nx, int ny, double lx, double ly, int dtype,
     if (device < 0 || device >= ndev)
         return fail(nullptr, GGFV_EHIP, "device %d out of range (%d devices)", device, ndev);
 
+    int cus = 0;
+    he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (he != hipSuccess || cus < 1)
+        return fail(nullptr, GGFV_EHIP, "cannot query the compute units of device %d", device);
+
     ggfv_ctx *ctx = new (std::nothrow) ggfv_ctx;
     if (!ctx) return GGFV_ENOMEM;
+    ctx->cus = cus;
     ctx->nx = nx;
     ctx->ny = ny;
     ctx->lx = lx;
@@ -616,8 +622,10 @@ int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tn)
         return fail(ctx, GGFV_EINVAL, "threads must be 0, 64, 128 or 256 (got %d)", tn->threads);
     if (tn->fused_steps < 0 || tn->fused_steps > 4)
         return fail(ctx, GGFV_EINVAL, "fused_steps must be 0..4 (got %d)", tn->fused_steps);
-    if (tn->lane_shift != 0 && tn->lane_shift != 1)
-        return fail(ctx, GGFV_EINVAL, "lane_shift must be 0 or 1 (got %d)", tn->lane_shift);
+    if (tn->lane_shift < 0 || tn->lane_shift > 2)
+        return fail(ctx, GGFV_EINVAL, "lane_shift must be 0, 1 or 2 (got %d)", tn->lane_shift);
+    if (tn->lane_shift == 2 && ctx->dtype == GGFV_F32C)
+        return fail(ctx, GGFV_EINVAL, "wide lanes (lane_shift 2) are for FP64 and plain FP32 contexts");
     ctx->rows_per_strip = tn->rows_per_strip;
     ctx->threads = tn->threads;
     ctx->fused_steps = tn->fused_steps < 1 ? 1 : tn->fused_steps;
@@ -665,22 +673,30 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
         cleanup();
         return fail(ctx, GGFV_EHIP, "autotune setup failed");
     }
-    const int heights[10] = {0, 2, 4, 8, 16, 24, 32, 48, 64, 128};
-    const int widths[4] = {64, 128, 256, 0};     // 0: lane-shift kernels
+    // negative heights (lane-shift kernels only): strips that fill the resident
+    // wave slots half a round, 1.5 and 2 rounds over (0 is the one-round fit)
+    const int heights[13] = {0, 2, 4, 8, 16, 24, 32, 48, 64, 128, -1, -3, -4};
+    const int widths[5] = {64, 128, 256, 0, -1};     // 0: lane-shift kernels; -1: wide lanes
     bool first = true;
     for (int K = 1; K <= 4 && rc == GGFV_OK; ++K)
         for (int wdt : widths)
             for (int h : heights) {
-                const bool lanes = wdt == 0;
+                const bool lanes = wdt <= 0;
+                if (wdt < 0 && ctx->dtype == GGFV_F32C) continue;
                 if (!lanes && K > 1 && wdt == 256) continue;   // fused LDS widths are 64 and 128
                 if (!lanes && K == 4 && wdt != 64) continue;
+                if (h < 0) {
+                    if (!lanes) continue;
+                    ctx->lane_shift = wdt < 0 ? 2 : 1;           // the fit depends on the kernel
+                    h = ggfv::lane_shift_fit_rows(ctx, K, -h);
+                }
                 if (h > ctx->ny) continue;
                 if (K > 1 && h != 0 && h < 4 * K) continue;
                 if (lanes && h != 0 && h < 8) continue;
                 ctx->threads = lanes ? 64 : wdt;
-                ctx->rows_per_strip = h;
                 ctx->fused_steps = K;
-                ctx->lane_shift = lanes ? 1 : 0;
+                ctx->lane_shift = wdt < 0 ? 2 : lanes ? 1 : 0;
+                ctx->rows_per_strip = h;
                 const long long n = (long long)trial_steps * K;
                 hipError_t e = advance_steps(ctx, dt, K);       // warm-up
                 if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);

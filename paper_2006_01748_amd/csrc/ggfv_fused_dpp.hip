@@ -109,24 +109,15 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
                                           const int r)
 {
     const int q = r - 2 * S + 1;
-    if (q < g.lo[S] - 1 || q > g.hi[S]) return;                  // uniform
+    // Row hi[S] is not computed: it lies past the level's range, or it is row
+    // ny, whose mirrored value only the y-difference of row ny-1 would read (the
+    // faces through the top boundary are zero), and that difference takes row
+    // ny-1 itself.  Leaving every register untouched on this path keeps the
+    // register allocator from copying the rings on the common path.
+    if (q < g.lo[S] - 1 || q >= g.hi[S]) return;                 // uniform
     constexpr int m3 = pmod(PH - 2 * S, 3), q3 = pmod(PH - 2 * S + 1, 3), p3 = pmod(PH - 2 * S + 2, 3);
     constexpr int q2 = pmod(PH + 1, 2), p2 = pmod(PH, 2);       // rows q and q +- 1
     constexpr int I = S - 1;
-
-    if (q == g.hi[S]) {                      // mirror row ny for level S+1
-        if constexpr (S < K) {
-            if (q == g.ny) {
-#pragma unroll
-                for (int k = 0; k < CPL; ++k) {
-                    R.W[S][q3][k] = R.W[S][m3][k];
-                    R.U[S][q2][k] = R.U[S][p2][k];
-                    R.V[S][q2][k] = R.V[S][p2][k];
-                }
-            }
-        }
-        return;
-    }
 
     // Row q = lo[S]-1 (the pre-row) runs the same code: what it carries to the
     // next row is the x-difference and right neighbour of row q+1 = lo[S], which
@@ -136,6 +127,7 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
     const T half = T(0.5), one = T(1);
     const bool real = q >= g.re[S];
     const bool has_n = q >= 0 && q + 1 < g.ny;
+    const bool top = q + 1 >= g.ny;          // row q+1 is the mirror of row q
     const int ts = tslot<RTA>(q), tp = tslot<RTA>(q + 1), tc = tslot<RTC>(q);
 
     T W0[CPL], Wp[CPL], U0[CPL], V0[CPL], TY[CPL], BT[CPL], B0[CPL];
@@ -146,7 +138,8 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         U0[k] = R.U[I][q2][k];
         V0[k] = R.V[I][q2][k];
         B0[k] = L.B[ts][g.own + k];
-        TY[k] = (Wp[k] - R.W[I][m3][k]) * A.hy;
+        const T Wn = top ? W0[k] : Wp[k];
+        TY[k] = (Wn - R.W[I][m3][k]) * A.hy;
         BT[k] = B0[k] * TY[k];
     }
     // shifts: b*ty, u and v from the right; x-difference of row q+1
@@ -411,20 +404,47 @@ __global__ __launch_bounds__(kWave) void fused_dpp_batch_kernel(const StepArgs<T
     dpp_strip<T, COMP, CPL, K>(A, local % nbx, local / nbx, L);
 }
 
+// Resident one-wave workgroups of a lane-shift kernel per CU (its registers and
+// LDS ring decide), queried once per kernel.
+template <typename T, bool COMP, int CPL, int K>
+int lane_shift_blocks_per_cu()
+{
+    static const int n = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fused_dpp_kernel<T, COMP, CPL, K>, kWave, 0) !=
+                hipSuccess ||
+            b < 1)
+            b = 1;
+        return b;
+    }();
+    return n;
+}
+
+// The tallest strips whose waves still fill the resident slots rounds2/2 times
+// over, so that the last round is not a partial one: every strip repeats the
+// 2K+2-row pipeline fill, and a partial last round leaves CUs idle.  Never
+// below 8K rows nor above ny.
+template <typename T, bool COMP, int CPL, int K>
+int fit_rows_typed(const ggfv_ctx *ctx, int rounds2)
+{
+    constexpr int OUTW = DppShape<CPL, K>::OUTW;
+    const long nbx = (ctx->nx + OUTW - 1) / OUTW;
+    const long slots = (long)lane_shift_blocks_per_cu<T, COMP, CPL, K>() * (ctx->cus > 0 ? ctx->cus : 1);
+    long strips = slots * rounds2 / 2 / nbx;
+    if (strips < 1) strips = 1;
+    long rows = (ctx->ny + strips - 1) / strips;
+    if (rows < 8 * K) rows = 8 * K;
+    if (rows > ctx->ny) rows = ctx->ny;
+    return (int)rows;
+}
+
 template <typename T, bool COMP, int CPL, int K>
 hipError_t launch_dpp_typed(ggfv_ctx *ctx, const void *in, void *out, double dt)
 {
     constexpr int OUTW = DppShape<CPL, K>::OUTW;
     const int nbx = (ctx->nx + OUTW - 1) / OUTW;
     int rows = ctx->rows_per_strip;
-    if (rows <= 0) {
-        // one-wave workgroups: aim for about 16 per CU on 256 CUs, tall enough
-        // to amortise the 2K-row pipeline fill
-        const long target = 4096;
-        long per = ((long)ctx->ny * nbx + target - 1) / target;
-        const int floor_rows = 8 * K;
-        rows = (int)(per < floor_rows ? floor_rows : per);
-    }
+    if (rows <= 0) rows = fit_rows_typed<T, COMP, CPL, K>(ctx, 2);
     if (rows > ctx->ny) rows = ctx->ny;
     const StepArgs<T> A = make_args<T>(ctx, in, out, dt, rows);
     const int nby = (ctx->ny + rows - 1) / rows;
@@ -466,11 +486,40 @@ hipError_t launch_dpp_batch_depth(const BatchLaunch &b, hipStream_t stream)
 
 }  // namespace
 
+template <typename T, bool COMP, int CPL>
+int fit_rows_depth(const ggfv_ctx *ctx, int K, int rounds2)
+{
+    switch (K) {
+    case 1: return fit_rows_typed<T, COMP, CPL, 1>(ctx, rounds2);
+    case 2: return fit_rows_typed<T, COMP, CPL, 2>(ctx, rounds2);
+    case 3: return fit_rows_typed<T, COMP, CPL, 3>(ctx, rounds2);
+    default: return fit_rows_typed<T, COMP, CPL, 4>(ctx, rounds2);
+    }
+}
+
+// lane_shift 1: 8 bytes of columns per lane (one FP64 or two FP32 columns);
+// lane_shift 2 (wide lanes): 16 bytes (two FP64 or four FP32 columns), which
+// halves the lane shifts, edge selects and halo columns per cell at twice the
+// registers.  The compensated state keeps 8 bytes per lane.
+int lane_shift_fit_rows(const ggfv_ctx *ctx, int K, int rounds2)
+{
+    const bool wide = ctx->lane_shift == 2;
+    if (ctx->dtype == GGFV_F64)
+        return wide ? fit_rows_depth<double, false, 2>(ctx, K, rounds2) : fit_rows_depth<double, false, 1>(ctx, K, rounds2);
+    if (ctx->dtype == GGFV_F32C) return fit_rows_depth<float, true, 2>(ctx, K, rounds2);
+    return wide ? fit_rows_depth<float, false, 4>(ctx, K, rounds2) : fit_rows_depth<float, false, 2>(ctx, K, rounds2);
+}
+
 hipError_t launch_step_fused_dpp(ggfv_ctx *ctx, const void *in, void *out, double dt, int K)
 {
+    const bool wide = ctx->lane_shift == 2;
     switch (ctx->dtype) {
-    case GGFV_F64: return launch_dpp_depth<double, false, 1>(ctx, in, out, dt, K);
-    case GGFV_F32: return launch_dpp_depth<float, false, 2>(ctx, in, out, dt, K);
+    case GGFV_F64:
+        return wide ? launch_dpp_depth<double, false, 2>(ctx, in, out, dt, K)
+                    : launch_dpp_depth<double, false, 1>(ctx, in, out, dt, K);
+    case GGFV_F32:
+        return wide ? launch_dpp_depth<float, false, 4>(ctx, in, out, dt, K)
+                    : launch_dpp_depth<float, false, 2>(ctx, in, out, dt, K);
     case GGFV_F32C: return launch_dpp_depth<float, true, 2>(ctx, in, out, dt, K);
     default: return hipErrorInvalidValue;
     }

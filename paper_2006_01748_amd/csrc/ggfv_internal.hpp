@@ -65,10 +65,11 @@ struct ggfv_ctx {
     double t = 0.0;
     long long steps = 0;
     double last_dt = 0.0;
+    int cus = 0;             // compute units of the device
     int rows_per_strip = 0;  // 0: chosen per launch
     int threads = 0;         // workgroup width of the step kernel: 64, 128, 256, or 0 (by grid size)
     int fused_steps = 1;     // time steps per launch (1..4)
-    int lane_shift = 0;      // 1: one-wave register/lane-shift kernels (ggfv_fused_dpp.hip)
+    int lane_shift = 0;      // 1: one-wave register/lane-shift kernels (ggfv_fused_dpp.hip); 2: wide lanes
     ggfv::AdaptCtl *adapt = nullptr;   // adaptive-step control block (lazily allocated)
     double *front = nullptr;           // front diagnostics: 4 * ny per-row values + 16 results (lazily)
 
@@ -97,6 +98,9 @@ hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double d
 hipError_t launch_step_fused(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);
 // K (1..4) steps per launch with rows in registers and lane shifts (ggfv_fused_dpp.hip).
 hipError_t launch_step_fused_dpp(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);
+// Strip height at which the lane-shift kernel of depth K fills the device's
+// resident wave slots `rounds2 / 2` times over (rounds2 = 1: half a round).
+int lane_shift_fit_rows(const ggfv_ctx *ctx, int K, int rounds2);
 // n steps of the context's current state with its tuning (fused launches plus
 // single steps for the remainder); flips ctx->cur once per launch.
 hipError_t advance_steps(ggfv_ctx *ctx, double dt, long long n);

@@ -366,12 +366,13 @@ def test_fused_steps_bitwise(dtype, K, threads):
         ctx.close()
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32c", "f32"])
+@pytest.mark.parametrize("dtype,lanes", [("f64", 1), ("f32c", 1), ("f32", 1), ("f64", 2), ("f32", 2)])
 @pytest.mark.parametrize("K", [1, 2, 3, 4])
-def test_lane_shift_steps_bitwise(dtype, K):
-    """The one-wave kernels with register rows and lane shifts give the bits of
-    single steps, for every fused depth, strip height and ragged shape (widths
-    spanning several waves, one column, one row)."""
+def test_lane_shift_steps_bitwise(dtype, lanes, K):
+    """The one-wave kernels with register rows and lane shifts (8 or, with wide
+    lanes, 16 bytes of columns per lane) give the bits of single steps, for
+    every fused depth, strip height and ragged shape (widths spanning several
+    waves, one column, one row)."""
     shapes = [(300, 77), (1, 50), (50, 1), (513, 130), (3, 700), (129, 129), (125, 9)]
     for (nx, ny) in shapes:
         g = rng(nx * 17 + ny + K)
@@ -383,7 +384,7 @@ def test_lane_shift_steps_bitwise(dtype, K):
         ctx.step(dt, n)
         ref = ctx.get_state()
         for rows in (0, 1, 3, 2 * K + 1, 37):
-            ctx.set_tuning(rows, 0, K, lane_shift=1)
+            ctx.set_tuning(rows, 0, K, lane_shift=lanes)
             ctx.set_state(u, v, w)
             ctx.step(dt, n)
             got = ctx.get_state()
@@ -392,17 +393,28 @@ def test_lane_shift_steps_bitwise(dtype, K):
                     bad = np.argwhere(x != y)
                     raise AssertionError(f"{name} differs at {len(bad)} cells, first {bad[:4].tolist()} "
                                          f"(shape {nx}x{ny}, rows {rows})")
-            assert ctx.get_tuning()["lane_shift"] == 1
+            assert ctx.get_tuning()["lane_shift"] == lanes
         ctx.close()
 
 
-def test_lane_shift_full_size_against_oracle_patches():
-    """4096^2 layered tissue, four steps per launch on the lane-shift kernels,
-    40 steps; windows at corners and edges against the oracle."""
+def test_wide_lanes_rejected_for_compensated_state():
+    ctx = gpu_ctx(64, 64, "f32c", PRM, wl.random_state(rng(5), 64, 64), abc=wl.random_abc(rng(6), 64, 64))
+    with pytest.raises(pk.GGFVError):
+        ctx.set_tuning(0, 0, 4, lane_shift=2)
+    with pytest.raises(pk.GGFVError):
+        ctx.set_tuning(0, 0, 4, lane_shift=3)
+    ctx.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_lane_shift_full_size_against_oracle_patches(lanes):
+    """4096^2 layered tissue, four steps per launch on the lane-shift kernels
+    (default strip height, as the benchmark runs them), 40 steps; windows at
+    corners and edges against the oracle."""
     w = wl.cfg2(steps=40)
     a, b, c = oracle.tensor_from_eig(*w.eig)
     ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), eig=w.eig)
-    ctx.set_tuning(0, 0, 4, lane_shift=1)
+    ctx.set_tuning(0, 0, 4, lane_shift=lanes)
     dt = ctx.stable_dt(0.9)
     ctx.step(dt, w.steps)
     got = ctx.get_state()
