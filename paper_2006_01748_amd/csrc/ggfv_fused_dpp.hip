@@ -69,6 +69,8 @@ struct LaneGeom {
 
 template <typename T, int CPL, int RTA, int RTC>
 struct TensorRing {
+    // a row holds column k of every lane at [k * 64 + lane]: the 64 lanes of
+    // one access touch consecutive words, free of bank conflicts
     T hA[RTA][kWave * CPL];       // (a_i + a_i+1) / 2
     T B[RTA][kWave * CPL];        // b
     T hC[RTC][kWave * CPL];       // (c_j + c_j+1) / 2
@@ -84,6 +86,25 @@ struct ColumnMasks {
 
 template <int RT>
 __device__ __forceinline__ int tslot(int row) { return ((row % RT) + RT) % RT; }
+
+// Ring slot of row rb + D, where rb is a multiple of the unroll period and
+// base = tslot<RT>(rb) (0 when RT divides the period: then the slot is a
+// constant).  One conditional subtract instead of a division per use.
+template <int RT, int D>
+__device__ __forceinline__ int ring_slot(int base)
+{
+    constexpr int d = pmod(D, RT);
+    if constexpr (kPeriod % RT == 0) return d;
+    const int x = base + d;
+    return x >= RT ? x - RT : x;
+}
+
+template <int RT>
+__device__ __forceinline__ int ring_base(int rb)
+{
+    if constexpr (kPeriod % RT == 0) return 0;
+    return tslot<RT>(rb);
+}
 
 // x-difference of w along one row (mirrored at the domain edges) and the raw
 // right-lane neighbour of the last column.
@@ -106,7 +127,7 @@ __device__ __forceinline__ void x_difference(const T (&X)[CPL], const ColumnMask
 template <typename T, bool COMP, int CPL, int K, int PH, int S, int RTA, int RTC>
 __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL> &m,
                                           LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RTA, RTC> &L,
-                                          const int r)
+                                          const int r, const int ba, const int bc)
 {
     const int q = r - 2 * S + 1;
     // Row hi[S] is not computed: it lies past the level's range, or it is row
@@ -128,7 +149,9 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
     const bool real = q >= g.re[S];
     const bool has_n = q >= 0 && q + 1 < g.ny;
     const bool top = q + 1 >= g.ny;          // row q+1 is the mirror of row q
-    const int ts = tslot<RTA>(q), tp = tslot<RTA>(q + 1), tc = tslot<RTC>(q);
+    // r = rb + PH with rb a multiple of the unroll period (ba, bc: its ring slots)
+    const int ts = ring_slot<RTA, PH - 2 * S + 1>(ba), tp = ring_slot<RTA, PH - 2 * S + 2>(ba);
+    const int tc = ring_slot<RTC, PH - 2 * S + 1>(bc);
 
     T W0[CPL], Wp[CPL], U0[CPL], V0[CPL], TY[CPL], BT[CPL], B0[CPL];
 #pragma unroll
@@ -137,7 +160,7 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         Wp[k] = R.W[I][p3][k];
         U0[k] = R.U[I][q2][k];
         V0[k] = R.V[I][q2][k];
-        B0[k] = L.B[ts][g.own + k];
+        B0[k] = L.B[ts][k * kWave + g.own];
         const T Wn = top ? W0[k] : Wp[k];
         TY[k] = (Wn - R.W[I][m3][k]) * A.hy;
         BT[k] = B0[k] * TY[k];
@@ -156,7 +179,7 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         const T btr = k + 1 < CPL ? BT[k1] : btR;
         const T ur = k + 1 < CPL ? U0[k1] : uR;
         const T vr = k + 1 < CPL ? V0[k1] : vR;
-        const T hA = L.hA[ts][g.own + k];
+        const T hA = L.hA[ts][k * kWave + g.own];
         const T fx = (hA * ((wr - W0[k]) * A.idx) + half * (BT[k] + btr));
         const T gx = ((one - half * (U0[k] + ur)) * ((vr - V0[k]) * A.idx));
         FXe[k] = m.ve[k] ? fx : T(0);
@@ -170,7 +193,7 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const T Up = R.U[I][p2][k], Vp = R.V[I][p2][k];
-        const T Bp = L.B[tp][g.own + k], hC = L.hC[tc][g.own + k];
+        const T Bp = L.B[tp][k * kWave + g.own], hC = L.hC[tc][k * kWave + g.own];
         const T FXw = k > 0 ? FXe[k > 0 ? k - 1 : 0] : FXl;
         const T GXw = k > 0 ? GXe[k > 0 ? k - 1 : 0] : GXl;
         const T Wc = W0[k], Uc = U0[k], Vc = V0[k];
@@ -245,29 +268,30 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
 template <typename T, bool COMP, int CPL, int K, int PH, int RTA, int RTC>
 __device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL> &m,
                                           LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RTA, RTC> &L,
-                                          const int r, const int r_start, const int r_end)
+                                          const int r, const int r_start, const int r_end, const int ba,
+                                          const int bc)
 {
     if (r < r_start || r > r_end) return;                        // uniform
-    if constexpr (K >= 4) level_row<T, COMP, CPL, K, PH, 4, RTA, RTC>(A, g, m, R, L, r);
-    if constexpr (K >= 3) level_row<T, COMP, CPL, K, PH, 3, RTA, RTC>(A, g, m, R, L, r);
-    if constexpr (K >= 2) level_row<T, COMP, CPL, K, PH, 2, RTA, RTC>(A, g, m, R, L, r);
+    if constexpr (K >= 4) level_row<T, COMP, CPL, K, PH, 4, RTA, RTC>(A, g, m, R, L, r, ba, bc);
+    if constexpr (K >= 3) level_row<T, COMP, CPL, K, PH, 3, RTA, RTC>(A, g, m, R, L, r, ba, bc);
+    if constexpr (K >= 2) level_row<T, COMP, CPL, K, PH, 2, RTA, RTC>(A, g, m, R, L, r, ba, bc);
 
     // tensor row r (requested one iteration ago) into the ring; the c face sum
     // of row r-1 needs row r
     if (r >= r_start + 1 && r <= g.last0) {
         const T half = T(0.5);
         const T aRs = from_right(R.ta[0]);
-        const int ts = tslot<RTA>(r), tm = tslot<RTC>(r - 1);
+        const int ts = ring_slot<RTA, PH>(ba), tm = ring_slot<RTC, PH - 1>(bc);
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             const T ar = k + 1 < CPL ? R.ta[k + 1 < CPL ? k + 1 : k] : aRs;
-            L.hA[ts][g.own + k] = half * (R.ta[k] + ar);
-            L.B[ts][g.own + k] = R.tb[k];
-            L.hC[tm][g.own + k] = half * (R.cprev[k] + R.tc[k]);
+            L.hA[ts][k * kWave + g.own] = half * (R.ta[k] + ar);
+            L.B[ts][k * kWave + g.own] = R.tb[k];
+            L.hC[tm][k * kWave + g.own] = half * (R.cprev[k] + R.tc[k]);
             R.cprev[k] = R.tc[k];
         }
     }
-    level_row<T, COMP, CPL, K, PH, 1, RTA, RTC>(A, g, m, R, L, r);
+    level_row<T, COMP, CPL, K, PH, 1, RTA, RTC>(A, g, m, R, L, r, ba, bc);
 
     // request old-state row r+1 (clamped: rows -1 and ny load their mirrors)
     if (r + 1 <= g.last0) {
@@ -310,7 +334,7 @@ __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, co
     LaneGeom<K> g;
     g.nx = A.nx;
     g.ny = A.ny;
-    g.own = threadIdx.x * CPL;
+    g.own = threadIdx.x;
     g.cbase = e0 + (int)threadIdx.x * CPL;
     g.lcol = min(max(g.cbase, 0), A.pitch - CPL);
     g.store_ok = g.cbase >= o0 && g.cbase < o0 + Sh::OUTW && g.cbase < A.pitch;
@@ -365,12 +389,13 @@ __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, co
     const int r_end = g.hi[K] + 2 * K - 2;
     const int r0 = r_start - pmod(r_start, kPeriod);
     for (int rb = r0; rb <= r_end; rb += kPeriod) {
-        lane_iter<T, COMP, CPL, K, 0, RTA, RTC>(A, g, m, R, L, rb + 0, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 1, RTA, RTC>(A, g, m, R, L, rb + 1, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 2, RTA, RTC>(A, g, m, R, L, rb + 2, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 3, RTA, RTC>(A, g, m, R, L, rb + 3, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 4, RTA, RTC>(A, g, m, R, L, rb + 4, r_start, r_end);
-        lane_iter<T, COMP, CPL, K, 5, RTA, RTC>(A, g, m, R, L, rb + 5, r_start, r_end);
+        const int ba = ring_base<RTA>(rb), bc = ring_base<RTC>(rb);
+        lane_iter<T, COMP, CPL, K, 0, RTA, RTC>(A, g, m, R, L, rb + 0, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 1, RTA, RTC>(A, g, m, R, L, rb + 1, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 2, RTA, RTC>(A, g, m, R, L, rb + 2, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 3, RTA, RTC>(A, g, m, R, L, rb + 3, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 4, RTA, RTC>(A, g, m, R, L, rb + 4, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 5, RTA, RTC>(A, g, m, R, L, rb + 5, r_start, r_end, ba, bc);
     }
 }
 
