@@ -76,7 +76,9 @@ struct TensorRing {
     T hC[RTC][kWave * CPL];       // (c_j + c_j+1) / 2
 };
 
-template <int CPL>
+// EDGE = false: the wave's columns and the strip's rows stay clear of the
+// domain boundary, so every boundary mask is true and compiles away.
+template <int CPL, bool EDGE = true>
 struct ColumnMasks {
     bool ve[CPL];                 // column >= 0 and its east face inside the domain
     bool he[CPL];                 // column has an east neighbour
@@ -108,24 +110,24 @@ __device__ __forceinline__ int ring_base(int rb)
 
 // x-difference of w along one row (mirrored at the domain edges) and the raw
 // right-lane neighbour of the last column.
-template <typename T, int CPL>
-__device__ __forceinline__ void x_difference(const T (&X)[CPL], const ColumnMasks<CPL> &m, const T hx,
+template <typename T, int CPL, bool EDGE>
+__device__ __forceinline__ void x_difference(const T (&X)[CPL], const ColumnMasks<CPL, EDGE> &m, const T hx,
                                              T (&TXo)[CPL], T &WRo)
 {
     const T WLs = from_left(X[CPL - 1]);
     const T WRs = from_right(X[0]);
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
-        const T wl = k > 0 ? X[k > 0 ? k - 1 : 0] : (m.hw0 ? WLs : X[0]);
+        const T wl = k > 0 ? X[k > 0 ? k - 1 : 0] : ((!EDGE || m.hw0) ? WLs : X[0]);
         const T nb = k + 1 < CPL ? X[k + 1 < CPL ? k + 1 : k] : WRs;
-        const T wr = m.he[k] ? nb : X[k];
+        const T wr = (!EDGE || m.he[k]) ? nb : X[k];
         TXo[k] = (wr - wl) * hx;
     }
     WRo = WRs;
 }
 
-template <typename T, bool COMP, int CPL, int K, int PH, int S, int RTA, int RTC>
-__device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL> &m,
+template <typename T, bool COMP, int CPL, int K, int PH, int S, int RTA, int RTC, bool EDGE>
+__device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL, EDGE> &m,
                                           LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RTA, RTC> &L,
                                           const int r, const int ba, const int bc)
 {
@@ -147,8 +149,8 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
     // boundary face of row 0).
     const T half = T(0.5), one = T(1);
     const bool real = q >= g.re[S];
-    const bool has_n = q >= 0 && q + 1 < g.ny;
-    const bool top = q + 1 >= g.ny;          // row q+1 is the mirror of row q
+    const bool has_n = !EDGE || (q >= 0 && q + 1 < g.ny);
+    const bool top = EDGE && q + 1 >= g.ny;  // row q+1 is the mirror of row q
     // r = rb + PH with rb a multiple of the unroll period (ba, bc: its ring slots)
     const int ts = ring_slot<RTA, PH - 2 * S + 1>(ba), tp = ring_slot<RTA, PH - 2 * S + 2>(ba);
     const int tc = ring_slot<RTC, PH - 2 * S + 1>(bc);
@@ -168,7 +170,7 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
     // shifts: b*ty, u and v from the right; x-difference of row q+1
     const T btR = from_right(BT[0]), uR = from_right(U0[0]), vR = from_right(V0[0]);
     T TXn[CPL], WRn;
-    x_difference<T, CPL>(Wp, m, A.hx, TXn, WRn);
+    x_difference<T, CPL, EDGE>(Wp, m, A.hx, TXn, WRn);
 
     // east faces of every column
     T FXe[CPL], GXe[CPL];
@@ -182,8 +184,8 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         const T hA = L.hA[ts][k * kWave + g.own];
         const T fx = (hA * ((wr - W0[k]) * A.idx) + half * (BT[k] + btr));
         const T gx = ((one - half * (U0[k] + ur)) * ((vr - V0[k]) * A.idx));
-        FXe[k] = m.ve[k] ? fx : T(0);
-        GXe[k] = m.ve[k] ? gx : T(0);
+        FXe[k] = (!EDGE || m.ve[k]) ? fx : T(0);
+        GXe[k] = (!EDGE || m.ve[k]) ? gx : T(0);
     }
     // west face of the first column: the left lane's last east face (0 left of
     // column 0, where that face lies outside the domain)
@@ -236,7 +238,7 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
                 R.Vl[S][q2][k] = ovl[k];
             }
         }
-        if (q == 0) {                        // mirror row -1 for level S+1
+        if (EDGE && q == 0) {                // mirror row -1 for level S+1
 #pragma unroll
             for (int k = 0; k < CPL; ++k) R.W[S][m3][k] = ow[k];
         }
@@ -265,16 +267,16 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
     }
 }
 
-template <typename T, bool COMP, int CPL, int K, int PH, int RTA, int RTC>
-__device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL> &m,
+template <typename T, bool COMP, int CPL, int K, int PH, int RTA, int RTC, bool EDGE>
+__device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K> &g, const ColumnMasks<CPL, EDGE> &m,
                                           LaneRows<T, COMP, CPL, K> &R, TensorRing<T, CPL, RTA, RTC> &L,
                                           const int r, const int r_start, const int r_end, const int ba,
                                           const int bc)
 {
     if (r < r_start || r > r_end) return;                        // uniform
-    if constexpr (K >= 4) level_row<T, COMP, CPL, K, PH, 4, RTA, RTC>(A, g, m, R, L, r, ba, bc);
-    if constexpr (K >= 3) level_row<T, COMP, CPL, K, PH, 3, RTA, RTC>(A, g, m, R, L, r, ba, bc);
-    if constexpr (K >= 2) level_row<T, COMP, CPL, K, PH, 2, RTA, RTC>(A, g, m, R, L, r, ba, bc);
+    if constexpr (K >= 4) level_row<T, COMP, CPL, K, PH, 4, RTA, RTC, EDGE>(A, g, m, R, L, r, ba, bc);
+    if constexpr (K >= 3) level_row<T, COMP, CPL, K, PH, 3, RTA, RTC, EDGE>(A, g, m, R, L, r, ba, bc);
+    if constexpr (K >= 2) level_row<T, COMP, CPL, K, PH, 2, RTA, RTC, EDGE>(A, g, m, R, L, r, ba, bc);
 
     // tensor row r (requested one iteration ago) into the ring; the c face sum
     // of row r-1 needs row r
@@ -291,7 +293,7 @@ __device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K
             R.cprev[k] = R.tc[k];
         }
     }
-    level_row<T, COMP, CPL, K, PH, 1, RTA, RTC>(A, g, m, R, L, r, ba, bc);
+    level_row<T, COMP, CPL, K, PH, 1, RTA, RTC, EDGE>(A, g, m, R, L, r, ba, bc);
 
     // request old-state row r+1 (clamped: rows -1 and ny load their mirrors)
     if (r + 1 <= g.last0) {
@@ -323,7 +325,7 @@ struct DppShape {
 
 // One workgroup's strip: output columns [sx*OUTW, sx*OUTW + OUTW) of rows
 // [sy*A.rows, sy*A.rows + A.rows), K steps from A's input to A's output planes.
-template <typename T, bool COMP, int CPL, int K>
+template <typename T, bool COMP, int CPL, int K, bool EDGE>
 __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, const int sy,
                                           TensorRing<T, CPL, DppShape<CPL, K>::RTA, DppShape<CPL, K>::RTC> &L)
 {
@@ -347,7 +349,7 @@ __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, co
     }
     g.lo[0] = g.re[0] = g.hi[0] = 0;
     g.last0 = g.hi[1];                     // last old-state row level 1 reads
-    ColumnMasks<CPL> m;
+    ColumnMasks<CPL, EDGE> m;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const int i = g.cbase + k;
@@ -390,13 +392,41 @@ __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, co
     const int r0 = r_start - pmod(r_start, kPeriod);
     for (int rb = r0; rb <= r_end; rb += kPeriod) {
         const int ba = ring_base<RTA>(rb), bc = ring_base<RTC>(rb);
-        lane_iter<T, COMP, CPL, K, 0, RTA, RTC>(A, g, m, R, L, rb + 0, r_start, r_end, ba, bc);
-        lane_iter<T, COMP, CPL, K, 1, RTA, RTC>(A, g, m, R, L, rb + 1, r_start, r_end, ba, bc);
-        lane_iter<T, COMP, CPL, K, 2, RTA, RTC>(A, g, m, R, L, rb + 2, r_start, r_end, ba, bc);
-        lane_iter<T, COMP, CPL, K, 3, RTA, RTC>(A, g, m, R, L, rb + 3, r_start, r_end, ba, bc);
-        lane_iter<T, COMP, CPL, K, 4, RTA, RTC>(A, g, m, R, L, rb + 4, r_start, r_end, ba, bc);
-        lane_iter<T, COMP, CPL, K, 5, RTA, RTC>(A, g, m, R, L, rb + 5, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 0, RTA, RTC, EDGE>(A, g, m, R, L, rb + 0, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 1, RTA, RTC, EDGE>(A, g, m, R, L, rb + 1, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 2, RTA, RTC, EDGE>(A, g, m, R, L, rb + 2, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 3, RTA, RTC, EDGE>(A, g, m, R, L, rb + 3, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 4, RTA, RTC, EDGE>(A, g, m, R, L, rb + 4, r_start, r_end, ba, bc);
+        lane_iter<T, COMP, CPL, K, 5, RTA, RTC, EDGE>(A, g, m, R, L, rb + 5, r_start, r_end, ba, bc);
     }
+}
+
+// Whether strip (sx, sy) keeps every column of the wave and every row that any
+// level touches (warm-up rows included) clear of the domain boundary.
+template <int CPL, int K, typename T>
+__device__ __forceinline__ bool strip_interior(const StepArgs<T> &A, const int sx, const int sy)
+{
+    using Sh = DppShape<CPL, K>;
+    const int e0 = sx * Sh::OUTW - Sh::H;
+    const int j0 = sy * A.rows, j1 = min(A.ny, j0 + A.rows);
+    return e0 >= 1 && e0 + Sh::TXW < A.nx && j0 >= K + 2 && j1 + K < A.ny;
+}
+
+// Interior strips run a copy of the sweep with the boundary masks compiled
+// out.  Only for 8-byte lanes of the plain state: the wide-lane and
+// compensated sweeps are large enough that two copies would crowd the
+// instruction cache.
+template <typename T, bool COMP, int CPL, int K>
+__device__ __forceinline__ void run_strip(const StepArgs<T> &A, const int sx, const int sy,
+                                          TensorRing<T, CPL, DppShape<CPL, K>::RTA, DppShape<CPL, K>::RTC> &L)
+{
+    if constexpr (sizeof(T) * CPL <= 8 && !COMP) {
+        if (strip_interior<CPL, K>(A, sx, sy)) {                // uniform
+            dpp_strip<T, COMP, CPL, K, false>(A, sx, sy, L);
+            return;
+        }
+    }
+    dpp_strip<T, COMP, CPL, K, true>(A, sx, sy, L);
 }
 
 template <typename T, bool COMP, int CPL, int K>
@@ -405,7 +435,7 @@ __global__ __launch_bounds__(kWave) void fused_dpp_kernel(StepArgs<T> A)
     __shared__ TensorRing<T, CPL, DppShape<CPL, K>::RTA, DppShape<CPL, K>::RTC> L;
     const int nbx = gridDim.x;
     const int lid = xcd_local_id(blockIdx.x + nbx * blockIdx.y, gridDim.x * gridDim.y);
-    dpp_strip<T, COMP, CPL, K>(A, lid % nbx, lid / nbx, L);
+    run_strip<T, COMP, CPL, K>(A, lid % nbx, lid / nbx, L);
 }
 
 // Ensemble form: the workgroups of all instances in one launch.  Instance i owns
@@ -426,7 +456,7 @@ __global__ __launch_bounds__(kWave) void fused_dpp_batch_kernel(const StepArgs<T
     const StepArgs<T> A = D[lo];
     const int nbx = (A.nx + DppShape<CPL, K>::OUTW - 1) / DppShape<CPL, K>::OUTW;
     const int local = lid - prefix[lo];
-    dpp_strip<T, COMP, CPL, K>(A, local % nbx, local / nbx, L);
+    run_strip<T, COMP, CPL, K>(A, local % nbx, local / nbx, L);
 }
 
 // Resident one-wave workgroups of a lane-shift kernel per CU (its registers and
