@@ -29,7 +29,9 @@
 //     row group are also evaluated by the neighbouring groups, from the same
 //     operands in the same order;
 //   * the state of plane k+1, the tz-difference of plane k and the tensor
-//     entries of plane k+1 that the z-face needs are carried in registers;
+//     entries of plane k+1 that the z-face needs are carried in registers, and
+//     in FP64 so are u, v and ayz of the halo rows, read one plane ahead
+//     together with the neighbouring groups that own them;
 //     every input value enters the wave once per plane (halo rows and halo
 //     lanes aside), and the neighbouring row groups of a plane run on the same
 //     XCD so that halo rows come from its L2.
@@ -192,6 +194,9 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
     using ggfv::from_left;
     using ggfv::from_right;
     constexpr int NR = R + 2;                      // rows held: j0-1 .. j0+R
+    // FP64: read u, v, ayz of the halo rows one plane ahead (see below); FP32's
+    // working set stays in L2 either way, and the later read is faster there
+    constexpr bool AHEAD = sizeof(T) == 8;
     const int lid = xcd_local_id3(blockIdx.x, G.nbx * G.nby * G.nzb);
     const int bx = lid % G.nbx, rest = lid / G.nbx;
     const int by = rest % G.nby, zb = rest / G.nby;
@@ -258,6 +263,14 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             FZb[r] = T(0);
             GZb[r] = T(0);
         }
+        if constexpr (AHEAD) {
+#pragma unroll
+            for (int r = 0; r < NR; r += R + 1) {
+                Uc[r] = gld<T>(Sc, off[r], fU);
+                Vc[r] = gld<T>(Sc, off[r], fV);
+                yz[r] = gld<T>(Tc, off[r], fYZ);
+            }
+        }
     }
 
     for (int k = kstart; k < k1; ++k) {
@@ -271,15 +284,24 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             W2[r] = gld<T>(S2, off[r], fW);
             TZn[r] = (W2[r] - Wc[r]) * A.hz;
         }
-        // values of plane k+1 for the top faces
+        // values of plane k+1: the top faces' (own rows), and (AHEAD) u, v, ayz
+        // of the halo rows, which the y-faces of plane k+1 need one iteration
+        // later.  Reading those together with the neighbouring groups, which
+        // read the same rows as their own now, keeps the re-read within the
+        // L2's reach: a plane-iteration later, an FP64 XCD has streamed about
+        // its L2's size and they would have been evicted.
         T Un[NR], Vn[NR], zzn[NR], xzn[NR], yzn[NR];
+        constexpr int r0 = AHEAD ? 0 : 1, r1 = AHEAD ? NR : R + 1;
 #pragma unroll
-        for (int r = 1; r <= R; ++r) {
+        for (int r = r0; r < r1; ++r) {
             Un[r] = gld<T>(Sn, off[r], fU);
             Vn[r] = gld<T>(Sn, off[r], fV);
+            yzn[r] = gld<T>(Tn, off[r], fYZ);
+        }
+#pragma unroll
+        for (int r = 1; r <= R; ++r) {
             zzn[r] = gld<T>(Tn, off[r], fZZ);
             xzn[r] = gld<T>(Tn, off[r], fXZ);
-            yzn[r] = gld<T>(Tn, off[r], fYZ);
         }
         // top faces (also in the warm-up plane)
         T FZt[NR], GZt[NR], TXn[NR];
@@ -299,7 +321,7 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
         }
         if (k >= k0) {                             // wave-uniform
             const auto Sk = state_at(k), Tk = tensor_at(k);
-            // halo rows of plane k: u, v, tx and the y-face tensor entries
+            // plane k: tx of the halo rows and the y-face tensor entries
             T yy[NR], xy[NR];
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -308,9 +330,11 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             }
 #pragma unroll
             for (int r = 0; r < NR; r += R + 1) {
-                Uc[r] = gld<T>(Sk, off[r], fU);
-                Vc[r] = gld<T>(Sk, off[r], fV);
-                yz[r] = gld<T>(Tk, off[r], fYZ);
+                if constexpr (!AHEAD) {
+                    Uc[r] = gld<T>(Sk, off[r], fU);
+                    Vc[r] = gld<T>(Sk, off[r], fV);
+                    yz[r] = gld<T>(Tk, off[r], fYZ);
+                }
                 const T e = from_right(Wc[r]), w = from_left(Wc[r]);
                 const T er = east_edge ? Wc[r] : e;
                 const T wl = west_edge ? Wc[r] : w;
@@ -361,15 +385,17 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             Wc[r] = Wn[r];
             Wn[r] = W2[r];
             TZc[r] = TZn[r];
+            if (AHEAD || (r >= 1 && r <= R)) {
+                Uc[r] = Un[r];
+                Vc[r] = Vn[r];
+                yz[r] = yzn[r];
+            }
         }
 #pragma unroll
         for (int r = 1; r <= R; ++r) {
             TX[r] = TXn[r];
-            Uc[r] = Un[r];
-            Vc[r] = Vn[r];
             zz[r] = zzn[r];
             xz[r] = xzn[r];
-            yz[r] = yzn[r];
             FZb[r] = FZt[r];
             GZb[r] = GZt[r];
         }
