@@ -136,6 +136,37 @@ def test_full_size_layered_tissue_patches(dtype):
             assert np.max(np.abs(s - r)) <= 1e-12 * max(np.max(np.abs(r)), 1.0)
 
 
+@pytest.mark.parametrize("dtype,shape,tol", [("f32", (0, 64, 4, 2), 5e-4), ("f32c", (0, 64, 4, 1), 1e-5)])
+def test_full_size_fp32_headline_shapes(dtype, shape, tol):
+    """4096^2 layered tissue in the FP32 launch shapes the benchmark times (wide
+    lanes for plain FP32, 8-byte lanes for the compensated state, the library's
+    strip height), 40 steps: bit for bit the single-step kernel's result, and
+    sampled windows within the FP32 bars of the FP64 oracle run on the device's
+    own FP32 tensor, state and step."""
+    import dataclasses
+    w = wl.cfg2(steps=40)
+    ctx = gpu_ctx(w.nx, w.ny, dtype, w.params, (w.u0, w.v0, w.w0), eig=w.eig)
+    dt = float(np.float32(ctx.stable_dt(0.9)))
+    ctx.step(dt, w.steps)
+    single = ctx.get_state()
+    ctx.set_state(w.u0, w.v0, w.w0)
+    ctx.set_tuning(*shape)
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    for name, x, y in zip("uvw", got, single):
+        assert np.array_equal(x, y), f"{name}: headline shape differs from single steps"
+    a, b, c = ctx.get_tensor()
+    ctx.close()
+    r32 = lambda x: np.float64(np.float32(x))
+    w32 = dataclasses.replace(w, u0=r32(w.u0), v0=r32(w.v0), w0=r32(w.w0),
+                              params=tuple(float(np.float32(p)) for p in w.params))
+    n = w.nx
+    for (j0, j1, i0, i1) in [(0, 30, 0, 30), (n - 30, n, 2000, 2030), (2030, 2060, 2030, 2060)]:
+        ref = _patch_reference(w32, a, b, c, dt, w.steps, j0, j1, i0, i1)
+        for x, r in zip((x[j0:j1, i0:i1] for x in got), ref):
+            assert np.max(np.abs(x - r)) <= tol * max(np.max(np.abs(r)), 1.0)
+
+
 # ---------------------------------------------------------------------------
 # FP32: compensated state meets 1e-5 after 1e4 steps; plain FP32 does not
 
