@@ -326,6 +326,17 @@ void ggfv_batch_destroy(ggfv_batch *b);
 ggfv_ctx *ggfv_batch_instance(ggfv_batch *b, int i);
 /* Step size of instance i (rounded to FP32 for FP32 batches).  EINVAL unless finite and > 0. */
 int ggfv_batch_set_dt(ggfv_batch *b, int i, double dt);
+/* Instance i in one call: parameters (eq. (1)), the tensor (a, b, c) of eq. (2)
+ * as in ggfv_set_tensor, the state as in ggfv_set_state (which resets the
+ * instance's time and step count) and its step size as in ggfv_batch_set_dt.
+ * Arrays of nx[i]*ny[i] values, host or device (where), FP32 or FP64
+ * (io_dtype), read during the call.  EINVAL for i out of range or a bad dt
+ * (nothing changed), otherwise the status of the first setter that fails. */
+int ggfv_batch_set(ggfv_batch *b, int i, const ggfv_params *params, double dt, const void *a, const void *bb,
+                   const void *c, const void *u, const void *v, const void *w, int where, int io_dtype);
+/* Copy the state of instance i out, as ggfv_get_state does (host outputs
+ * synchronize).  EINVAL for i out of range; ESTATE before its state is set. */
+int ggfv_batch_get_state(ggfv_batch *b, int i, void *u, void *v, void *w, int where, int io_dtype);
 /* Advance every instance by nsteps steps (each with its own dt).  Enqueues and
  * returns.  ESTATE if an instance lacks state, tensor, parameters or dt. */
 int ggfv_batch_run(ggfv_batch *b, long long nsteps);

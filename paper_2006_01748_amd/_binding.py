@@ -52,6 +52,8 @@ _SIGNATURES = [
     ("ggfv_batch_destroy", None, [_VP]),
     ("ggfv_batch_instance", _VP, [_VP, _c.c_int]),
     ("ggfv_batch_set_dt", _c.c_int, [_VP, _c.c_int, _c.c_double]),
+    ("ggfv_batch_set", _c.c_int, [_VP, _c.c_int, _VP, _c.c_double] + [_VP] * 6 + [_c.c_int, _c.c_int]),
+    ("ggfv_batch_get_state", _c.c_int, [_VP, _c.c_int, _VP, _VP, _VP, _c.c_int, _c.c_int]),
     ("ggfv_batch_run", _c.c_int, [_VP, _c.c_longlong]),
     ("ggfv_batch_set_tuning", _c.c_int, [_VP, _c.c_int, _c.c_int, _c.c_int]),
     ("ggfv_batch_autotune", _c.c_int, [_VP, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
@@ -471,6 +473,29 @@ class Batch:
 
     def set_dt(self, i, dt):
         self._check(self._lib.ggfv_batch_set_dt(self._h, int(i), float(dt)))
+
+    def set(self, i, params, dt, abc, state):
+        """Parameters, tensor (a, b, c), state (u, v, w) and dt of instance i in one
+        call (ggfv_batch_set)."""
+        i = int(i)
+        p = Params(*[float(x) for x in params])
+        if not 0 <= i < len(self.sizes):     # let the library report the bad index
+            self._check(self._lib.ggfv_batch_set(self._h, i, ctypes.byref(p), float(dt), *([None] * 6),
+                                                 GGFV_HOST, GGFV_F64))
+        nx, ny = self.sizes[i]
+        ptrs, where, io, keep = _prep_arrays(tuple(abc) + tuple(state), nx * ny)
+        self._check(self._lib.ggfv_batch_set(self._h, i, ctypes.byref(p), float(dt), *ptrs, where, io))
+
+    def get_state(self, i, out=None, dtype="f64"):
+        """State of instance i (ggfv_batch_get_state)."""
+        idx = int(i)
+        if not 0 <= idx < len(self.sizes):   # let the library report the bad index
+            self._check(self._lib.ggfv_batch_get_state(self._h, idx, None, None, None, GGFV_HOST, GGFV_F64))
+        nx, ny = self.sizes[idx]
+        if out is None:
+            dt = np.float64 if dtype == "f64" else np.float32
+            out = [np.empty((ny, nx), dtype=dt) for _ in range(3)]
+        return _call_out3(self, lambda h, *rest: self._lib.ggfv_batch_get_state(h, idx, *rest), out, nx * ny)
 
     def run(self, nsteps):
         self._check(self._lib.ggfv_batch_run(self._h, int(nsteps)))

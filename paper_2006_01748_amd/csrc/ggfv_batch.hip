@@ -288,6 +288,30 @@ int ggfv_batch_set_dt(ggfv_batch *b, int i, double dt)
     return GGFV_OK;
 }
 
+int ggfv_batch_set(ggfv_batch *b, int i, const ggfv_params *params, double dt, const void *a, const void *bb,
+                   const void *c, const void *u, const void *v, const void *w, int where, int io_dtype)
+{
+    if (!b) return GGFV_EINVAL;
+    if (i < 0 || i >= b->n) return bfail(b, GGFV_EINVAL, "instance %d out of range", i);
+    if (!(dt > 0.0) || !std::isfinite(dt)) return bfail(b, GGFV_EINVAL, "dt must be finite and > 0");
+    ggfv_ctx *ctx = b->inst[i];
+    b->dirty = true;
+    int rc = ggfv_set_params(ctx, params);
+    if (rc == GGFV_OK) rc = ggfv_set_tensor(ctx, a, bb, c, where, io_dtype);
+    if (rc == GGFV_OK) rc = ggfv_set_state(ctx, u, v, w, where, io_dtype);
+    if (rc != GGFV_OK) return bfail(b, rc, "instance %d: %s", i, ggfv_last_error(ctx));
+    return ggfv_batch_set_dt(b, i, dt);
+}
+
+int ggfv_batch_get_state(ggfv_batch *b, int i, void *u, void *v, void *w, int where, int io_dtype)
+{
+    if (!b) return GGFV_EINVAL;
+    if (i < 0 || i >= b->n) return bfail(b, GGFV_EINVAL, "instance %d out of range", i);
+    const int rc = ggfv_get_state(b->inst[i], u, v, w, where, io_dtype);
+    if (rc != GGFV_OK) return bfail(b, rc, "instance %d: %s", i, ggfv_last_error(b->inst[i]));
+    return GGFV_OK;
+}
+
 int ggfv_batch_set_tuning(ggfv_batch *b, int threads, int rows_per_strip, int graph_steps)
 {
     if (!b) return GGFV_EINVAL;

@@ -112,3 +112,9 @@ def test_null_context3_is_rejected(built):
     assert lib.ggfv3_set_tuning(None, 4, 0, 0, 0) == pk.GGFV_EINVAL
     assert lib.ggfv3_create(None, 4, 4, 4, 1.0, 1.0, 1.0, pk.GGFV_F64, 0, None) == pk.GGFV_EINVAL
     lib.ggfv3_destroy(None)
+
+
+def test_null_batch_calls_are_rejected(built):
+    lib = pk.lib()
+    assert lib.ggfv_batch_set(None, 0, None, 1e-3, *([None] * 6), pk.GGFV_HOST, pk.GGFV_F64) == pk.GGFV_EINVAL
+    assert lib.ggfv_batch_get_state(None, 0, None, None, None, pk.GGFV_HOST, pk.GGFV_F64) == pk.GGFV_EINVAL

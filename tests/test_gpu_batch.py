@@ -210,3 +210,43 @@ def test_batch_errors():
     with pytest.raises(pk.GGFVError):
         b.set_dt(0, -1.0)
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32c"])
+def test_batch_set_and_get_state_calls(dtype):
+    """ggfv_batch_set (parameters, tensor, state and dt of an instance in one
+    call) and ggfv_batch_get_state give the bits of the per-instance calls."""
+    g = np.random.Generator(np.random.PCG64(wl.BASE_SEED + 77))
+    sizes = [(70, 33), (1, 20), (129, 64)]
+    prms = [(12.5, 1.0, 0.01, 70.0, 70.0), (3.0, 1.0, 0.05, 40.0, 30.0), (0.5, 1.0, 0.002, 90.0, 90.0)]
+    cases = []
+    for (nx, ny), prm in zip(sizes, prms):
+        abc = wl.random_abc(g, nx, ny)
+        st = wl.random_state(g, nx, ny)
+        dt = oracle.stable_dt(*abc, prm[2], 0.8)
+        cases.append((prm, dt, abc, st))
+    b = pk.Batch(sizes, dtype=dtype)
+    for i, (prm, dt, abc, st) in enumerate(cases):
+        b.set(i, prm, dt, abc, st)
+    b.run(9)
+    for i, (prm, dt, abc, st) in enumerate(cases):
+        nx, ny = sizes[i]
+        ctx = pk.Context(nx, ny, dtype=dtype)
+        ctx.set_params(prm)
+        ctx.set_tensor(*abc)
+        ctx.set_state(*st)
+        ctx.step(dt, 9)
+        ref = ctx.get_state()
+        ctx.close()
+        got = b.get_state(i)
+        assert all(np.array_equal(x, y) for x, y in zip(got, ref)), i
+        assert all(np.array_equal(x, y) for x, y in zip(b[i].get_state(), ref)), i
+    with pytest.raises(pk.GGFVError) as e:
+        b.set(3, prms[0], 1e-6, cases[0][2], cases[0][3])
+    assert e.value.status == pk.GGFV_EINVAL
+    with pytest.raises(pk.GGFVError) as e:
+        b.set(0, prms[0], 0.0, cases[0][2], cases[0][3])
+    assert e.value.status == pk.GGFV_EINVAL
+    with pytest.raises(pk.GGFVError):
+        b.get_state(-1)
+    b.close()
