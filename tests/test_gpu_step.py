@@ -136,6 +136,28 @@ def test_full_size_layered_tissue_patches(dtype):
             assert np.max(np.abs(s - r)) <= 1e-12 * max(np.max(np.abs(r)), 1.0)
 
 
+@pytest.mark.parametrize("delta1", [1.0, 12.5, 20.0])
+def test_full_size_500_steps_headline_shape_each_delta1(delta1):
+    """4096^2 layered tissue, 500 FP64 steps in the benchmark's launch shape
+    (four steps per launch, wide lanes, the library's strip height), for each
+    kill rate of the workload recipe; an 8x8 window on the tumour disk's edge
+    (and, for the largest rate, a corner) recomputed exactly by the oracle on a
+    sub-grid grown by 500 cells: equal bit for bit."""
+    w = wl.cfg2(delta1=delta1, steps=500)
+    a, b, c = oracle.tensor_from_eig(*w.eig)
+    ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), abc=(a, b, c))
+    ctx.set_tuning(0, 64, 4, lane_shift=2)
+    dt = ctx.stable_dt(0.9)
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    ctx.close()
+    windows = [(2044, 2052, 2250, 2258)] + ([(0, 8, 0, 8)] if delta1 == 20.0 else [])
+    for (j0, j1, i0, i1) in windows:
+        ref = _patch_reference(w, a, b, c, dt, w.steps, j0, j1, i0, i1)
+        for name, x, r in zip("uvw", (x[j0:j1, i0:i1] for x in got), ref):
+            assert np.array_equal(x, r), (name, j0, i0, float(np.max(np.abs(x - r))))
+
+
 @pytest.mark.parametrize("dtype,shape,tol", [("f32", (0, 64, 4, 2), 5e-4), ("f32c", (0, 64, 4, 1), 1e-5)])
 def test_full_size_fp32_headline_shapes(dtype, shape, tol):
     """4096^2 layered tissue in the FP32 launch shapes the benchmark times (wide
