@@ -136,6 +136,23 @@ def test_full_size_layered_tissue_patches(dtype):
             assert np.max(np.abs(s - r)) <= 1e-12 * max(np.max(np.abs(r)), 1.0)
 
 
+def test_smooth_anisotropic_1024_2000_steps_headline_shape():
+    """The smooth anisotropic workload at its full 1024^2, 2000 FP64 steps in the
+    headline launch shape (four steps per launch, wide lanes, the library's
+    strip height), against a full oracle run: equal bit for bit."""
+    w = wl.cfg1(n=1024, steps=2000)
+    a, b, c = oracle.tensor_from_eig(*w.eig)
+    dt = oracle.stable_dt(a, b, c, w.params[2], 0.9)
+    ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), abc=(a, b, c))
+    ctx.set_tuning(0, 64, 4, lane_shift=2)
+    ctx.step(dt, w.steps)
+    got = ctx.get_state()
+    ctx.close()
+    ref = oracle.run(w.u0, w.v0, w.w0, a, b, c, w.params, dt, w.steps)[:3]
+    for name, x, r in zip("uvw", got, ref):
+        assert np.array_equal(x, r), (name, float(np.max(np.abs(x - r))))
+
+
 @pytest.mark.parametrize("delta1", [1.0, 12.5, 20.0])
 def test_full_size_500_steps_headline_shape_each_delta1(delta1):
     """4096^2 layered tissue, 500 FP64 steps in the benchmark's launch shape
