@@ -225,6 +225,41 @@ def time_variant(pk, torch, w, dtype, steps, warmup, tune, force=None):
     }
 
 
+def time_host_inclusive(pk, torch, w, dtype, steps, tuning, dt):
+    """The same job with the host buffers in the timed region: the tensor (as
+    eigenvalues and angle) and the state go up from pageable numpy arrays, the
+    steps and the mass diagnostics run in the given launch shape, and the state
+    comes back to numpy.  Wall clock, after one untimed round trip."""
+    stream = torch.cuda.current_stream()
+    ctx = pk.Context(w.nx, w.ny, w.lx, w.ly, dtype=dtype, stream=stream.cuda_stream)
+    ctx.set_params(w.params)
+    ctx.set_tuning(tuning["rows_per_strip"], tuning["threads"], tuning["fused_steps"], tuning["lane_shift"])
+    out = [np.empty((w.ny, w.nx)) for _ in range(3)]
+    walls = []
+    for rep in range(2):                       # the first pass warms the path up
+        n_steps = 10 if rep == 0 else steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.set_tensor_eig(*w.eig)
+        ctx.set_state(w.u0, w.v0, w.w0)
+        done = 0
+        while done < n_steps:
+            n = min(n_steps - done, MASS_EVERY - (done % MASS_EVERY))
+            ctx.step(dt, n)
+            done += n
+            if done % MASS_EVERY == 0:
+                ctx.diagnostics()
+        ctx.get_state(out)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    ctx.close()
+    cells = w.nx * w.ny
+    up = 6 * cells * 8                          # FP64 host arrays: three eigen fields, three state fields
+    down = 3 * cells * 8
+    return {"value": cells * steps / walls[-1] / 1e9, "wall_ms": 1e3 * walls[-1], "steps": steps,
+            "host_bytes_up": up, "host_bytes_down": down, "tuning": tuning}
+
+
 def time_adjoint(pk, torch, steps=5000):
     """Gradient workload: 512^2 smooth anisotropic tensor, `steps` steps, loss of
     the final v and w; forward with square-root checkpoints, then the native
@@ -787,6 +822,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--no-host-inclusive", action="store_true",
+                    help="skip the run with host buffers (upload and download) inside the timed region")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
@@ -850,6 +887,14 @@ def main():
                 f"({res[v]['fused_steps']} steps), effective {res[v]['effective_GBs']:.0f} GB/s")
         else:
             res[v] = single[v]
+    host = None
+    if not args.no_host_inclusive and not args.no_tune:
+        hv = variants[0]
+        log(f"timing {hv} with host buffers in the timed region (upload, {args.steps} steps, download)")
+        host = time_host_inclusive(pk, torch, w, hv, args.steps, res[hv]["tuning"], res[hv]["dt"])
+        host["vs_resident"] = host["value"] / res[hv]["value"]
+        log(f"  {host['value']:.2f} Gcell/s ({host['wall_ms']:.1f} ms wall, {host['vs_resident']:.3f} of the "
+            "HBM-resident rate)")
     adj = None
     if not args.no_adjoint:
         log("timing the gradient workload (forward with checkpoints, reverse sweep)")
@@ -926,6 +971,7 @@ def main():
                                          "frac": single[v]["achieved_GBs"] / PEAK_HBM_GBS,
                                          "traffic": measured_traffic(v, single[v]["tuning"], single[v]["rows"])}}
                      for v in variants},
+        "host_inclusive": host,
         "adjoint": adj,
         "adaptive": adaptive,
         "front_sweep": fronts,
