@@ -573,7 +573,9 @@ def _short(name):
 
 
 def _counter_means(pdir, kind):
-    """Mean counter value per (kernel, grid size) over the dispatches of one --pmc run."""
+    """Mean counter value per (kernel, grid size, workgroup size) over the
+    dispatches of one --pmc run (launch shapes with equal thread counts differ
+    in workgroup size)."""
     import csv
     import collections
     vals, meta = collections.defaultdict(float), {}
@@ -581,7 +583,7 @@ def _counter_means(pdir, kind):
         for row in csv.DictReader(f):
             d = int(row["Dispatch_Id"])
             vals[d] += float(row["Counter_Value"])
-            meta[d] = (_short(row["Kernel_Name"]), int(row["Grid_Size"]))
+            meta[d] = (_short(row["Kernel_Name"]), int(row["Grid_Size"]), int(row["Workgroup_Size"]))
     agg = collections.defaultdict(list)
     for d, v in vals.items():
         agg[meta[d]].append(v)
@@ -608,7 +610,7 @@ def summarize_3d(pdir, tdir, fdir, wdir, bench_json):
         for row in csv.DictReader(f):
             name = _short(row["Kernel_Name"])
             if name.startswith("step3_pencil_kernel"):
-                durs[(name, int(row["Grid_Size_X"]))].append(
+                durs[(name, int(row["Grid_Size_X"]), int(row["Workgroup_Size_X"]))].append(
                     (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
     n3 = [int(x) for x in three["workload"].split()[2].rstrip(",").split("x")]
     cells3 = n3[0] * n3[1] * n3[2]
@@ -616,7 +618,7 @@ def summarize_3d(pdir, tdir, fdir, wdir, bench_json):
     for dt_name, vr in three["variants"].items():
         shape = vr["launch_shape"]
         threads = shape["workgroups"] * 64 * shape["waves_x"] * shape["waves_y"]
-        key = (vr["kernel"], threads)
+        key = (vr["kernel"], threads, 64 * shape["waves_x"] * shape["waves_y"])
         d = durs.get(key, [])
         alg = vr["bytes_per_cell_update"] * cells3
         alg_w = alg // 4                           # 3 of the 12 values are written
@@ -685,25 +687,8 @@ def summarize_profiles(pdir):
     with open(os.path.join(pdir, "trace_bench.json")) as f:
         bench = json.loads(f.read().strip().splitlines()[-1])
 
-    def per_dispatch(kind):
-        vals = collections.defaultdict(float)
-        meta = {}
-        with open(os.path.join(pdir, kind, f"{kind}_counter_collection.csv")) as f:
-            for row in csv.DictReader(f):
-                d = int(row["Dispatch_Id"])
-                vals[d] += float(row["Counter_Value"])
-                meta[d] = (_short(row["Kernel_Name"]), int(row["Grid_Size"]))
-        agg = collections.defaultdict(list)
-        for d, v in vals.items():
-            agg[meta[d]].append(v)
-        return {k: sum(v) / len(v) for k, v in agg.items()}
-
-    fetch, write = per_dispatch("fetch"), per_dispatch("write")
-    copy_bytes = 1 << 30                  # the copy-ceiling probe: 1 GiB read and 1 GiB written
-    cal = [k for k in fetch if k[0] == "__amd_rocclr_copyBuffer"]
-    ck = max(cal, key=lambda k: k[1])
-    f_scale = copy_bytes / (fetch[ck] * 1024)
-    w_scale = copy_bytes / (write[ck] * 1024)
+    fetch, write = _counter_means(pdir, "fetch"), _counter_means(pdir, "write")
+    ck, f_scale, w_scale = _copy_calibration(fetch, write)
     cells = bench["config"]["grid"][0] * bench["config"]["grid"][1]
 
     # kernels of the 4096^2 runs: single-step and headline shapes of each variant

@@ -197,6 +197,12 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
     // FP64: read u, v, ayz of the halo rows one plane ahead (see below); FP32's
     // working set stays in L2 either way, and the later read is faster there
     constexpr bool AHEAD = sizeof(T) == 8;
+    // FP32 with four rows per wave issues all of a plane's loads in one round
+    // trip (11% faster than reading the face tensors in the output branch).
+    // FP64 keeps them there: with two rows the early loads raise the registers
+    // from 168 to 170, one wave per SIMD fewer, and the step is slower; with
+    // four they spill.  FP32 with one or two rows measured no gain.
+    constexpr bool EARLY = sizeof(T) == 4 && R == 4;
     const int lid = xcd_local_id3(blockIdx.x, G.nbx * G.nby * G.nzb);
     const int bx = lid % G.nbx, rest = lid / G.nbx;
     const int by = rest % G.nby, zb = rest / G.nby;
@@ -303,6 +309,40 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             zzn[r] = gld<T>(Tn, off[r], fZZ);
             xzn[r] = gld<T>(Tn, off[r], fXZ);
         }
+        // the x- and y-face tensor entries of plane k and (not AHEAD) u, v, ayz
+        // of its halo rows
+        const auto Tk = tensor_at(k);
+        T yy[NR], xy[NR], xx[NR];
+        auto load_plane_k = [&]() {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                yy[r] = gld<T>(Tk, off[r], fYY);
+                xy[r] = gld<T>(Tk, off[r], fXY);
+            }
+            if constexpr (EARLY) {
+#pragma unroll
+                for (int r = 1; r <= R; ++r) xx[r] = gld<T>(Tk, off[r], fXX);
+            }
+            if constexpr (!AHEAD) {
+                const auto Sk = state_at(k);
+#pragma unroll
+                for (int r = 0; r < NR; r += R + 1) {
+                    Uc[r] = gld<T>(Sk, off[r], fU);
+                    Vc[r] = gld<T>(Sk, off[r], fV);
+                    yz[r] = gld<T>(Tk, off[r], fYZ);
+                }
+            }
+        };
+        if constexpr (EARLY) {
+            // issued with the loads above, so that one memory round trip
+            // serves the whole plane.  The empty statement that may write
+            // memory keeps them here: the optimizer would otherwise move each
+            // load next to its only use in the output branch below, where it
+            // waits for a second (and third) round trip.  It emits no
+            // instruction and no wait.
+            load_plane_k();
+            asm volatile("" ::: "memory");
+        }
         // top faces (also in the warm-up plane)
         T FZt[NR], GZt[NR], TXn[NR];
 #pragma unroll
@@ -320,21 +360,10 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             GZt[r] = top ? gz : T(0);
         }
         if (k >= k0) {                             // wave-uniform
-            const auto Sk = state_at(k), Tk = tensor_at(k);
-            // plane k: tx of the halo rows and the y-face tensor entries
-            T yy[NR], xy[NR];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                yy[r] = gld<T>(Tk, off[r], fYY);
-                xy[r] = gld<T>(Tk, off[r], fXY);
-            }
+            if constexpr (!EARLY) load_plane_k();
+            // plane k: tx of the halo rows
 #pragma unroll
             for (int r = 0; r < NR; r += R + 1) {
-                if constexpr (!AHEAD) {
-                    Uc[r] = gld<T>(Sk, off[r], fU);
-                    Vc[r] = gld<T>(Sk, off[r], fV);
-                    yz[r] = gld<T>(Tk, off[r], fYZ);
-                }
                 const T e = from_right(Wc[r]), w = from_left(Wc[r]);
                 const T er = east_edge ? Wc[r] : e;
                 const T wl = west_edge ? Wc[r] : w;
@@ -353,12 +382,12 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             const auto Ok = group_rsrc(A.o + (size_t)k * 3 * P, 3 * PB);
 #pragma unroll
             for (int r = 1; r <= R; ++r) {
-                const T xx = gld<T>(Tk, off[r], fXX);
+                if constexpr (!EARLY) xx[r] = gld<T>(Tk, off[r], fXX);   // at its use: fewer live registers
                 const T ty = (Wc[r + 1] - Wc[r - 1]) * A.hy;
-                const T xxE = from_right(xx), xyE = from_right(xy[r]), xzE = from_right(xz[r]);
+                const T xxE = from_right(xx[r]), xyE = from_right(xy[r]), xzE = from_right(xz[r]);
                 const T wE = from_right(Wc[r]), tyE = from_right(ty), tzE = from_right(TZc[r]);
                 const T uE = from_right(Uc[r]), vE = from_right(Vc[r]);
-                const T fx = half * (xx + xxE) * ((wE - Wc[r]) * A.idx) + half * (xy[r] * ty + xyE * tyE) +
+                const T fx = half * (xx[r] + xxE) * ((wE - Wc[r]) * A.idx) + half * (xy[r] * ty + xyE * tyE) +
                              half * (xz[r] * TZc[r] + xzE * tzE);
                 const T gx = (one - half * (Uc[r] + uE)) * ((vE - Vc[r]) * A.idx);
                 const T FXe = east_edge ? T(0) : fx;
@@ -627,15 +656,15 @@ struct Shape3 {
 };
 
 // Pencil shape: rows per wave (1, 2 or 4), planes per strip and waves per
-// workgroup.  Defaults (measured on the 256^3 workload): two rows per wave;
-// FP64 with two row groups per workgroup and about 2560 waves in the grid,
-// FP32 with every x-strip of a row group in one workgroup (up to 8) and about
-// 5120 waves.
+// workgroup.  Defaults (measured on the 256^3 workload): about 2560 waves in
+// the grid; FP64 with two rows per wave and two row groups per workgroup,
+// FP32 with four rows per wave and every x-strip of a row group in one
+// workgroup (up to 8).
 Shape3 shape3(const ggfv3_ctx *ctx)
 {
     Shape3 S{};
     const bool f64 = ctx->dtype == GGFV_F64;
-    S.rows = ctx->rows > 0 ? ctx->rows : 2;
+    S.rows = ctx->rows > 0 ? ctx->rows : (f64 ? 2 : 4);
     S.nsx = (ctx->nx + kStrip - 1) / kStrip;
     S.ngy = (ctx->ny + S.rows - 1) / S.rows;
     if (ctx->wx > 0 || ctx->wy > 0) {
@@ -651,7 +680,7 @@ Shape3 shape3(const ggfv3_ctx *ctx)
     int zs = ctx->zs;
     if (zs <= 0) {
         const long pencils = (long)S.nsx * S.ngy;
-        const long target = f64 ? 2560 : 5120;
+        const long target = 2560;
         long nzb = (target + pencils - 1) / pencils;
         if (nzb < 1) nzb = 1;
         zs = (int)((ctx->nz + nzb - 1) / nzb);
