@@ -75,8 +75,9 @@ SOURCES_3D = ("ggfv3.hip", "ggfv_dpp.hpp", "ggfv_internal.hpp")
 
 
 def traffic_sources(here, family="2d"):
-    """Kernel sources whose change invalidates a counter summary of `family`."""
-    out = []
+    """Kernel sources whose change invalidates a counter summary of `family`
+    (with the build script, whose flags shape the compiled kernels)."""
+    out = [os.path.join("paper_2006_01748_amd", "build.py")]
     for d, _, fs in os.walk(os.path.join(here, "paper_2006_01748_amd", "csrc")):
         for f in fs:
             if not f.endswith((".hip", ".hpp")):
