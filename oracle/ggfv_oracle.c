@@ -255,7 +255,7 @@ void orc_diag(int nx, int ny, double lx, double ly, const double *u, const doubl
               double Delta2, double dt, double *out)
 {
     size_t n = (size_t)nx * ny;
-    double dx = lx / nx, dy = ly / ny, idx = nx / lx, idy = ny / ly;
+    double dx = lx / nx, dy = ly / ny;
     const double *f[3] = {u, v, w};
     double nonfinite = 0.0;
     for (int q = 0; q < 3; ++q) {
