@@ -41,7 +41,12 @@ void ggfv3_destroy(ggfv3_ctx *ctx);
 /* Parameters of eq. (1) (delta1, rho2, Delta2, rho3, delta3).  EINVAL if not finite. */
 int ggfv3_set_params(ggfv3_ctx *ctx, const ggfv_params *p);
 /* The six tensor fields (read, not kept).  EINVAL on NULL pointers or bad
- * where / io_dtype; the tensor is not checked for definiteness. */
+ * where / io_dtype, and EINVAL if the tensor is not positive definite in some
+ * cell (Section 1 asks for a positive definite tensor; checked by Sylvester's
+ * criterion, axx > 0, axx*ayy - axy^2 > 0 and det > 0, in FP64 on the entries
+ * after rounding to the context precision).  Synchronizes.  After a failed call
+ * the context has no tensor (ESTATE for step and stable_dt) until a valid one
+ * is set. */
 int ggfv3_set_tensor(ggfv3_ctx *ctx, const void *axx, const void *ayy, const void *azz, const void *axy,
                      const void *axz, const void *ayz, int where, int io_dtype);
 /* The state (u, v, w); resets the time and the step count. */

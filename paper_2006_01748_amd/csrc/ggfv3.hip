@@ -83,6 +83,7 @@ namespace {
 thread_local std::string g3_create_error;
 constexpr int kRed3 = 256;         // reduction workgroup
 constexpr int kRed3Blocks = 512;   // reduction partial blocks
+constexpr int kRed3Slots = 5;      // three state sums, the Gershgorin max, non-definite cells
 
 int fail3(ggfv3_ctx *ctx, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 
@@ -476,13 +477,16 @@ __device__ __forceinline__ double wave_max(double x)
 }
 
 // Per-block partial sums of the three state fields (fixed partition and order),
-// and of the Gershgorin bound of the tensor (max), written to parts[block*4 + q].
+// the Gershgorin bound of the tensor (max) and the number of cells whose tensor
+// is not positive definite, written to parts[block*kRed3Slots + q].  A cell is
+// positive definite when all three leading principal minors are positive
+// (Sylvester's criterion), evaluated in FP64 on the stored entries.
 template <typename T>
 __global__ __launch_bounds__(kRed3) void reduce3_kernel(const T *__restrict__ st, const T *__restrict__ ten, int nx,
                                                        int ny, int nz, int pitch, double *__restrict__ parts)
 {
-    __shared__ double sm[kRed3 / 64][4];
-    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    __shared__ double sm[kRed3 / 64][kRed3Slots];
+    double x[kRed3Slots] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const long n = (long)nx * ny * nz;
     const size_t P = (size_t)ny * pitch;
     for (long q = blockIdx.x * (long)kRed3 + threadIdx.x; q < n; q += (long)gridDim.x * kRed3) {
@@ -503,24 +507,33 @@ __global__ __launch_bounds__(kRed3) void reduce3_kernel(const T *__restrict__ st
             const double r1 = fabs(axy) + fabs(ayy) + fabs(ayz);
             const double r2 = fabs(axz) + fabs(ayz) + fabs(azz);
             x[3] = fmax(x[3], fmax(r0, fmax(r1, r2)));
+            const double m2 = axx * ayy - axy * axy;
+            const double m3 = axx * (ayy * azz - ayz * ayz) - axy * (axy * azz - ayz * axz) +
+                              axz * (axy * ayz - ayy * axz);
+            const bool finite = isfinite(axx) && isfinite(ayy) && isfinite(azz) && isfinite(axy) &&
+                                isfinite(axz) && isfinite(ayz);
+            if (!(finite && axx > 0.0 && m2 > 0.0 && m3 > 0.0)) x[4] += 1.0;
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int f = 0; f < 3; ++f) x[f] = wave_sum(x[f]);
     x[3] = wave_max(x[3]);
+    x[4] = wave_sum(x[4]);
     if (lane == 0) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) sm[wv][f] = x[f];
+        for (int f = 0; f < kRed3Slots; ++f) sm[wv][f] = x[f];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s[4] = {sm[0][0], sm[0][1], sm[0][2], sm[0][3]};
+        double s[kRed3Slots];
+        for (int f = 0; f < kRed3Slots; ++f) s[f] = sm[0][f];
         for (int w = 1; w < kRed3 / 64; ++w) {
             for (int f = 0; f < 3; ++f) s[f] += sm[w][f];
             s[3] = fmax(s[3], sm[w][3]);
+            s[4] += sm[w][4];
         }
-        for (int f = 0; f < 4; ++f) parts[(size_t)blockIdx.x * 4 + f] = s[f];
+        for (int f = 0; f < kRed3Slots; ++f) parts[(size_t)blockIdx.x * kRed3Slots + f] = s[f];
     }
 }
 
@@ -528,12 +541,14 @@ __global__ __launch_bounds__(kRed3) void reduce3_kernel(const T *__restrict__ st
 __global__ void reduce3_final_kernel(const double *__restrict__ parts, int nb, double *__restrict__ out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[kRed3Slots] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = 0; b < nb; ++b) {
-        for (int f = 0; f < 3; ++f) s[f] += parts[(size_t)b * 4 + f];
-        s[3] = fmax(s[3], parts[(size_t)b * 4 + 3]);
+        const double *p = parts + (size_t)b * kRed3Slots;
+        for (int f = 0; f < 3; ++f) s[f] += p[f];
+        s[3] = fmax(s[3], p[3]);
+        s[4] += p[4];
     }
-    for (int f = 0; f < 4; ++f) out[f] = s[f];
+    for (int f = 0; f < kRed3Slots; ++f) out[f] = s[f];
 }
 
 size_t io_bytes(int io) { return io == GGFV_F64 ? 8 : 4; }
@@ -602,9 +617,11 @@ int pack_fields(ggfv3_ctx *ctx, const void *const *src, int n, int where, int io
     return GGFV_OK;
 }
 
-int reduce3(ggfv3_ctx *ctx, bool state, bool tensor, double *host4)
+// Reduction over the state and/or tensor: host[0..2] masses' sums, host[3]
+// the Gershgorin max, host[4] the count of non-definite cells (synchronizes).
+int reduce3(ggfv3_ctx *ctx, bool state, bool tensor, double *host)
 {
-    double *parts = ctx->scratch, *res = ctx->scratch + (size_t)kRed3Blocks * 4;
+    double *parts = ctx->scratch, *res = ctx->scratch + (size_t)kRed3Blocks * kRed3Slots;
     const void *st = state ? ctx->state[ctx->cur] : nullptr;
     const void *tn = tensor ? ctx->tensor : nullptr;
     if (ctx->dtype == GGFV_F64)
@@ -616,7 +633,7 @@ int reduce3(ggfv3_ctx *ctx, bool state, bool tensor, double *host4)
     GGFV3_HIP(ctx, hipGetLastError());
     hipLaunchKernelGGL(reduce3_final_kernel, dim3(1), dim3(64), 0, ctx->stream, parts, kRed3Blocks, res);
     GGFV3_HIP(ctx, hipGetLastError());
-    GGFV3_HIP(ctx, hipMemcpyAsync(host4, res, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GGFV3_HIP(ctx, hipMemcpyAsync(host, res, kRed3Slots * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     GGFV3_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return GGFV_OK;
 }
@@ -759,7 +776,8 @@ int ggfv3_create(ggfv3_ctx **out, int nx, int ny, int nz, double lx, double ly, 
     bool ok = hipMalloc(&c->state[0], 3 * field * c->elem) == hipSuccess &&
               hipMalloc(&c->state[1], 3 * field * c->elem) == hipSuccess &&
               hipMalloc(&c->tensor, 6 * field * c->elem) == hipSuccess &&
-              hipMalloc(reinterpret_cast<void **>(&c->scratch), ((size_t)kRed3Blocks * 4 + 8) * sizeof(double)) ==
+              hipMalloc(reinterpret_cast<void **>(&c->scratch),
+                        ((size_t)kRed3Blocks * kRed3Slots + 8) * sizeof(double)) ==
                   hipSuccess;
     if (ok) ok = hipMemset(c->state[0], 0, 3 * field * c->elem) == hipSuccess &&
                  hipMemset(c->state[1], 0, 3 * field * c->elem) == hipSuccess &&
@@ -806,7 +824,14 @@ int ggfv3_set_tensor(ggfv3_ctx *ctx, const void *axx, const void *ayy, const voi
     for (const void *p : src)
         if (!p) return fail3(ctx, GGFV_EINVAL, "null tensor field");
     Guard3 g(ctx->device);
+    ctx->has_tensor = false;
     if ((rc = pack_fields(ctx, src, 6, where, io, ctx->tensor))) return rc;
+    double r[kRed3Slots];
+    if ((rc = reduce3(ctx, false, true, r))) return rc;
+    if (r[4] > 0.0)
+        return fail3(ctx, GGFV_EINVAL,
+                     "tensor is not positive definite in %.0f cells (need axx > 0, axx*ayy - axy^2 > 0, det > 0)",
+                     r[4]);
     ctx->has_tensor = true;
     return GGFV_OK;
 }
@@ -868,7 +893,7 @@ int ggfv3_stable_dt(ggfv3_ctx *ctx, double safety, double *dt)
     if (!(safety > 0.0) || !std::isfinite(safety)) return fail3(ctx, GGFV_EINVAL, "safety must be > 0");
     if (!ctx->has_tensor || !ctx->has_params) return fail3(ctx, GGFV_ESTATE, "tensor and parameters must be set");
     Guard3 g(ctx->device);
-    double r[4];
+    double r[kRed3Slots];
     int rc = reduce3(ctx, false, true, r);
     if (rc) return rc;
     double gmax = ctx->prm.Delta2;
@@ -903,7 +928,7 @@ int ggfv3_mass(ggfv3_ctx *ctx, double *mass3)
     if (!mass3) return fail3(ctx, GGFV_EINVAL, "null output");
     if (!ctx->has_state) return fail3(ctx, GGFV_ESTATE, "state not set");
     Guard3 g(ctx->device);
-    double r[4];
+    double r[kRed3Slots];
     int rc = reduce3(ctx, true, false, r);
     if (rc) return rc;
     const double vol = (ctx->lx / ctx->nx) * (ctx->ly / ctx->ny) * (ctx->lz / ctx->nz);

@@ -212,3 +212,58 @@ def test_step3_errors():
         assert t["rows_per_wave"] in (1, 2, 4) and 1 <= t["z_per_strip"] <= 8
         with pytest.raises(ValueError):
             ctx.set_state(state[0][:4], state[1], state[2])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_step3_set_tensor_rejects_non_definite_cells(dtype):
+    """Section 1 asks for a positive definite tensor: one bad cell in a valid
+    field makes set_tensor fail, for each leading minor of Sylvester's
+    criterion and for a non-finite entry; the context then refuses to step
+    until a valid tensor is set."""
+    nx, ny, nz = 33, 7, 5
+    npdt = np.float64 if dtype == "f64" else np.float32
+    state, A = inputs(nx, ny, nz, 7)
+    at = (4, 3, 30)                                   # (k, j, i) of the bad cell
+    bad_cells = {
+        "axx <= 0": {0: 0.0},
+        "2x2 minor <= 0": {0: 1.0, 1: 1.0, 3: 1.0},   # axy^2 = axx ayy
+        "det <= 0": {0: 1.0, 1: 1.0, 2: 1.0, 3: -0.6, 4: -0.6, 5: -0.6},   # (1-r)^2 (1+2r) < 0
+        "non-finite": {5: float("nan")},
+    }
+    with pk.Context3(nx, ny, nz, dtype=dtype) as ctx:
+        ctx.set_params(PRM)
+        ctx.set_state(*[x.astype(npdt) for x in state])
+        for name, entries in bad_cells.items():
+            T = [x.copy() for x in A]
+            for q, val in entries.items():
+                T[q][at] = val
+            with pytest.raises(pk.GGFVError) as e:
+                ctx.set_tensor(*[x.astype(npdt) for x in T])
+            assert e.value.status == pk.GGFV_EINVAL, name
+            assert "in 1 cells" in str(e.value), (name, str(e.value))
+            with pytest.raises(pk.GGFVError) as e:
+                ctx.step(1e-6)
+            assert e.value.status == pk.GGFV_ESTATE
+            with pytest.raises(pk.GGFVError) as e:
+                ctx.stable_dt(0.9)
+            assert e.value.status == pk.GGFV_ESTATE
+        ctx.set_tensor(*[x.astype(npdt) for x in A])
+        ctx.step(1e-6, 2)
+
+
+def test_step3_definiteness_is_checked_after_rounding():
+    """An entry pair that is definite in FP64 but not once rounded to FP32:
+    axx = ayy = 1, axy = 1 - 2^-30 gives axx ayy - axy^2 = 2^-29 (1 - 2^-31) > 0
+    in FP64, while axy rounds to 1 in FP32 and the minor becomes 0."""
+    nx, ny, nz = 9, 4, 3
+    state, A = inputs(nx, ny, nz, 8)
+    T = [x.copy() for x in A]
+    for q, val in {0: 1.0, 1: 1.0, 2: 1.0, 3: 1.0 - 2.0 ** -30, 4: 0.0, 5: 0.0}.items():
+        T[q][1, 2, 3] = val
+    assert np.float32(T[3][1, 2, 3]) == np.float32(1.0)
+    with ctx_of(nx, ny, nz, state, T) as ctx:           # FP64: accepted
+        ctx.step(1e-6)
+    with pk.Context3(nx, ny, nz, dtype="f32") as ctx:
+        with pytest.raises(pk.GGFVError) as e:
+            ctx.set_tensor(*T)                           # FP64 arrays, rounded on the way in
+        assert e.value.status == pk.GGFV_EINVAL and "in 1 cells" in str(e.value)
