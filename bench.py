@@ -557,7 +557,75 @@ PROFILE_COMMANDS = {
               "-- python3 $R/bench.py --only-3d",
     "write3": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/write3 -o write3 "
               "-- python3 $R/bench.py --only-3d",
+    # instruction counts of the 2D kernels (six SQ counters, one pass)
+    "valu": "timeout -s KILL 300 rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD "
+            "SQ_INSTS_VMEM_WR SQ_WAVES --output-format csv -d $P/valu -o valu "
+            "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble "
+            "--no-adaptive --no-fronts --no-3d --no-host-inclusive --no-copy-ceiling",
 }
+
+# MI355X: 256 CUs, each issuing at most one wave64 vector instruction per cycle
+# over its four SIMDs (16 lanes, 4 cycles per instruction), at 2.4 GHz.
+VALU_ISSUE_PER_S = 256 * 2.4e9
+
+
+def summarize_valu(pdir, n=4096):
+    """profiles/valu_step_kernels_4096_layered_tissue.md from the valu/ counter
+    pass: instructions per cell-update of the single-step and headline kernels
+    and the vector issue utilisation (instructions over 256 CUs x the
+    dispatch's duration x 2.4 GHz)."""
+    import csv
+    import collections
+    here = os.path.dirname(os.path.abspath(__file__))
+    vals = collections.defaultdict(lambda: collections.defaultdict(float))
+    meta = {}
+    with open(os.path.join(pdir, "valu", "valu_counter_collection.csv")) as f:
+        for row in csv.DictReader(f):
+            d = int(row["Dispatch_Id"])
+            vals[d][row["Counter_Name"]] += float(row["Counter_Value"])
+            meta[d] = (_short(row["Kernel_Name"]), int(row["Grid_Size"]), int(row["Workgroup_Size"]),
+                       (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+    agg = collections.defaultdict(list)
+    for d, c in vals.items():
+        agg[meta[d][:3]].append((c, meta[d][3]))
+    counters = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR")
+    rows, out = [], {}
+    for v in ("f64", "f32c", "f32"):
+        for label, tuning in (("single step", {"fused_steps": 1, "threads": 0}),
+                              ("headline", dict(zip(("rows_per_strip", "threads", "fused_steps", "lane_shift"),
+                                                    HEADLINE_SHAPE[v])))):
+            kname, _ = kernel_name(v, tuning)
+            keys = [k for k in agg if k[0] == kname]
+            if not keys:
+                continue
+            k = max(keys, key=lambda x: x[1])         # the 4096^2 dispatches
+            runs = agg[k]
+            mean = {c: sum(r[0][c] for r in runs) / len(runs) for c in counters}
+            us = sum(r[1] for r in runs) / len(runs)
+            updates = n * n * max(1, tuning["fused_steps"])
+            per = {c: mean[c] * 64 / updates for c in counters}
+            util = mean["SQ_INSTS_VALU"] / (VALU_ISSUE_PER_S * us * 1e-6)
+            out[f"{v}/{label}"] = {"kernel": kname, "dispatches": len(runs), "duration_us": us,
+                                   "valu_per_cell_update": per["SQ_INSTS_VALU"], "valu_issue_util": util}
+            rows.append(f"| {v} | {label} | {kname} | {len(runs)} | {us:.1f} | {mean['SQ_INSTS_VALU']:.4g} | "
+                        f"{per['SQ_INSTS_VALU']:.1f} | {per['SQ_INSTS_SALU']:.1f} | {per['SQ_INSTS_LDS']:.2f} | "
+                        f"{per['SQ_INSTS_VMEM_RD']:.2f} | {per['SQ_INSTS_VMEM_WR']:.2f} | {100 * util:.0f}% |")
+    with open(os.path.join(here, "profiles", "valu_step_kernels_4096_layered_tissue.md"), "w") as f:
+        f.write("# Instruction counts of the 2D step kernels, 4096^2 layered tissue (rocprofv3 counters)\n\n"
+                f"Command (from /tmp with TMPDIR=/tmp):\n\n```\n{PROFILE_COMMANDS['valu']}\n```\n\n"
+                "Summary written by `python bench.py --summarize-profiles $P`.  Counts are wave instructions "
+                "per dispatch, averaged over the dispatches of the 4096^2 runs; per cell-update they are "
+                "lane instructions (x64) over 4096^2 x steps per launch.  Issue utilisation: VALU wave "
+                "instructions over the most the chip can issue in the dispatch's duration (256 CUs x one "
+                "wave instruction per cycle x 2.4 GHz x duration; every FP64 and non-packed FP32 "
+                "instruction takes four cycles of a 16-lane SIMD).  Durations are those of the counter "
+                "run.\n\n"
+                "| variant | kernel role | kernel | dispatches | duration (us) | VALU instructions | "
+                "VALU / cell-update | SALU / cell-update | LDS / cell-update | VMEM reads / cell-update | "
+                "VMEM writes / cell-update | VALU issue utilisation |\n"
+                "|---|---|---|---|---|---|---|---|---|---|---|---|\n" + "\n".join(rows) + "\n")
+    return out
+
 
 
 def _short(name):
@@ -672,10 +740,14 @@ def summarize_profiles(pdir):
     """Write profiles/*.md and profiles/step_kernel_traffic.json from the CSV
     output of PROFILE_COMMANDS (trace/, fetch/, write/ and trace_bench.json
     under pdir; trace3/, fetch3/, write3/ and trace3_bench.json for the 3D
-    kernel, which may be present alone)."""
+    kernel and valu/ for the instruction counts, each of which may be present
+    alone)."""
+    if os.path.isdir(os.path.join(pdir, "valu")):
+        print(json.dumps({"valu": summarize_valu(pdir)}, indent=1))
     if not os.path.isdir(os.path.join(pdir, "trace")):
-        print(json.dumps({"three_d": summarize_3d(pdir, "trace3", "fetch3", "write3", "trace3_bench.json")},
-                         indent=1))
+        if os.path.isdir(os.path.join(pdir, "trace3")):
+            print(json.dumps({"three_d": summarize_3d(pdir, "trace3", "fetch3", "write3", "trace3_bench.json")},
+                             indent=1))
         return
     import csv
     import collections
