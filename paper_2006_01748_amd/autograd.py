@@ -43,6 +43,9 @@ class FVRun(torch.autograd.Function):
     @staticmethod
     def backward(fctx, gu, gv, gw):
         params, lam1, lam2, theta = fctx.saved_tensors
+        if fctx.ckpt is None:
+            raise RuntimeError("a second backward through the same run is not supported: the first released "
+                               "its checkpoints (run the forward again)")
         gg = fctx.gg
         # the context may have been used in between: restore what this run used
         gg.set_params(params.detach().cpu().tolist())

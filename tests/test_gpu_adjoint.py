@@ -253,3 +253,31 @@ def test_f32c_gradients_stated_tolerance():
     errs += [float(np.linalg.norm(x.grad.cpu().numpy() - r) / np.linalg.norm(r)) for x, r in zip(t, ref)]
     print(f"f32c gradient rel errors: {['%.2e' % e for e in errs]}")
     assert max(errs) <= 2e-5
+
+
+def test_autograd_second_backward_is_refused():
+    """The first backward releases the run's checkpoints; a second one through
+    the same graph raises instead of reading released memory, and a fresh
+    forward gives the same gradient again."""
+    torch = pytest.importorskip("torch")
+    from paper_2006_01748_amd import autograd as ag
+    nx, ny, n = 40, 24, 30
+    eig = wl.random_eig(rng(20), nx, ny)
+    x0 = wl.random_state3(rng(21), nx, ny, 1)
+    ctx = pk.Context(nx, ny, dtype="f64")
+    ctx.set_params(PRM)
+    ctx.set_tensor_eig(*eig)
+    dt = 0.5 * ctx.stable_dt(0.9)
+    grads = []
+    for _ in range(2):
+        params = torch.tensor(PRM, dtype=torch.float64, requires_grad=True)
+        t = [torch.from_numpy(x).cuda() for x in eig]
+        s = [torch.from_numpy(x[0]).cuda() for x in x0]
+        u, v, w = ag.run(ctx, params, *t, *s, dt, n)
+        loss = (v * v).sum() + w.sum()
+        loss.backward(retain_graph=True)
+        grads.append(params.grad.clone())
+        with pytest.raises(RuntimeError, match="second backward"):
+            loss.backward()
+    ctx.close()
+    assert torch.equal(grads[0], grads[1])
