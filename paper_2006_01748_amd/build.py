@@ -46,8 +46,9 @@ HIPCC_FLAGS = [
 # sweep in registers at two or three waves per SIMD, so the order of
 # independent instructions inside one wave decides how busy the vector unit
 # is.  The scheduler's instruction-level-parallelism strategy measured faster
-# there on MI355X (compensated FP32 +5.5%, FP32 +2%, FP64 unchanged) and only
-# reorders instructions.
+# for the FP32 instances on MI355X (compensated FP32 +5.5%, FP32 +2%) and only
+# reorders instructions.  The FP64 instances (ggfv_fused_dpp_f64.hip) keep the
+# default schedule: with their late stores the ILP schedule spills.
 SOURCE_FLAGS = {
     "ggfv_fused_dpp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
 }

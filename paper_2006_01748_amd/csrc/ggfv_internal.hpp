@@ -96,7 +96,8 @@ hipError_t launch_step(ggfv_ctx *ctx, double dt);
 hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double dt);
 // K (2..4) steps fused into one launch, from `in` to `out` (ggfv_fused.hip).
 hipError_t launch_step_fused(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);
-// K (1..4) steps per launch with rows in registers and lane shifts (ggfv_fused_dpp.hip).
+// K (1..4) steps per launch with rows in registers and lane shifts (ggfv_fused_dpp.hpp;
+// FP32 in ggfv_fused_dpp.hip, FP64 in ggfv_fused_dpp_f64.hip).
 hipError_t launch_step_fused_dpp(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);
 // Strip height at which the lane-shift kernel of depth K fills the device's
 // resident wave slots `rounds2 / 2` times over (rounds2 = 1: half a round).
@@ -136,6 +137,12 @@ hipError_t launch_step_batch(const BatchLaunch &b, hipStream_t stream);
 // (ggfv_fused_dpp.hip); output columns per workgroup for a precision and depth.
 hipError_t launch_step_batch_dpp(const BatchLaunch &b, hipStream_t stream);
 int lane_shift_columns_per_group(int dtype, int K);
+// The FP64 instances of the lane-shift kernels live in their own source
+// (ggfv_fused_dpp_f64.hip, built with the default instruction schedule); the
+// three entry points above dispatch FP64 work to these.
+int lane_shift_fit_rows_f64(const ggfv_ctx *ctx, int K, int rounds2, bool wide);
+hipError_t launch_step_fused_dpp_f64(ggfv_ctx *ctx, const void *in, void *out, double dt, int K, bool wide);
+hipError_t launch_step_batch_dpp_f64(const BatchLaunch &b, hipStream_t stream);
 // Size of one step description, columns per workgroup, and filling one
 // description for a context (input planes, output planes, dt, strip height).
 size_t step_args_bytes(int dtype);

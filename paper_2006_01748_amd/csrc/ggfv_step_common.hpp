@@ -31,20 +31,24 @@ __device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&out)[CPL])
     for (int k = 0; k < CPL; ++k) out[k] = x.v[k];
 }
 
-// Output rows are written with non-temporal stores: the next step reads them
-// again, but the state of a large grid does not fit in any cache level, and
-// streaming stores keep the caches for the input rows' halos.
-template <typename T, int CPL>
+// Output rows are written with non-temporal stores by default: the next step
+// reads them again, but the state of a large grid does not fit in any cache
+// level, and streaming stores keep the caches for the input rows' halos.
+// NT = false writes through the caches (faster for the FP32 lane-shift
+// kernels, measured).
+template <typename T, int CPL, bool NT = true>
 __device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&in)[CPL])
 {
     if constexpr (CPL == 1) {
-        __builtin_nontemporal_store(in[0], p);
+        if constexpr (NT) __builtin_nontemporal_store(in[0], p);
+        else *p = in[0];
     } else {
         typedef T vec_t __attribute__((ext_vector_type(CPL)));
         vec_t x;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) x[k] = in[k];
-        __builtin_nontemporal_store(x, reinterpret_cast<vec_t *>(p));
+        if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<vec_t *>(p));
+        else *reinterpret_cast<vec_t *>(p) = x;
     }
 }
 
