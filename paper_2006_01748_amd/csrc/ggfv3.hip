@@ -203,6 +203,10 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
     // FP64 keeps them there: with two rows the early loads raise the registers
     // from 168 to 170, one wave per SIMD fewer, and the step is slower; with
     // four they spill.  FP32 with one or two rows measured no gain.
+    // FP64 recomputes the x-difference of w of its own rows every plane instead
+    // of carrying it (fewer live registers: two-row waves keep three waves per
+    // SIMD while loading axx before the first store of a plane); FP32 carries it.
+    constexpr bool RTX = sizeof(T) == 8;
     constexpr bool EARLY = sizeof(T) == 4 && R == 4;
     const int lid = xcd_local_id3(blockIdx.x, G.nbx * G.nby * G.nzb);
     const int bx = lid % G.nbx, rest = lid / G.nbx;
@@ -241,9 +245,9 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
     const int kstart = k0 > 0 ? k0 - 1 : 0;
     // registers carried from plane to plane
     T Wc[NR], Wn[NR], TZc[NR];                     // w of planes k and k+1, tz of plane k
-    T TX[NR];                                      // tx of plane k (own rows carried)
     T Uc[NR], Vc[NR];                              // u, v of plane k (own rows carried)
     T zz[NR], xz[NR], yz[NR];                      // azz, axz, ayz of plane k (own rows carried)
+    T TXc[NR];                                     // tx of plane k, own rows (carried when !RTX)
     T FZb[NR], GZb[NR];                            // fluxes through the bottom faces
     {
         const auto Sm = state_at(max(kstart - 1, 0)), Sc = state_at(kstart);
@@ -258,10 +262,12 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
         }
 #pragma unroll
         for (int r = 1; r <= R; ++r) {
-            const T e = from_right(Wc[r]), w = from_left(Wc[r]);
-            const T er = east_edge ? Wc[r] : e;
-            const T wl = west_edge ? Wc[r] : w;
-            TX[r] = (er - wl) * A.hx;
+            if constexpr (!RTX) {
+                const T e = from_right(Wc[r]), w = from_left(Wc[r]);
+                const T er = east_edge ? Wc[r] : e;
+                const T wl = west_edge ? Wc[r] : w;
+                TXc[r] = (er - wl) * A.hx;
+            }
             Uc[r] = gld<T>(Sc, off[r], fU);
             Vc[r] = gld<T>(Sc, off[r], fV);
             zz[r] = gld<T>(Tc, off[r], fZZ);
@@ -320,7 +326,11 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
                 yy[r] = gld<T>(Tk, off[r], fYY);
                 xy[r] = gld<T>(Tk, off[r], fXY);
             }
-            if constexpr (EARLY) {
+            // axx of every own row before the plane's first store: a load issued
+            // after a store waits for that store too (the memory counter drains
+            // in order).  Four FP64 rows load it at its use instead, for the
+            // registers.
+            if constexpr (EARLY || R <= 2) {
 #pragma unroll
                 for (int r = 1; r <= R; ++r) xx[r] = gld<T>(Tk, off[r], fXX);
             }
@@ -343,6 +353,19 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             // instruction and no wait.
             load_plane_k();
             asm volatile("" ::: "memory");
+        }
+        // tx of plane k, own rows
+        T TX[NR];
+#pragma unroll
+        for (int r = 1; r <= R; ++r) {
+            if constexpr (RTX) {
+                const T e = from_right(Wc[r]), w = from_left(Wc[r]);
+                const T er = east_edge ? Wc[r] : e;
+                const T wl = west_edge ? Wc[r] : w;
+                TX[r] = (er - wl) * A.hx;
+            } else {
+                TX[r] = TXc[r];
+            }
         }
         // top faces (also in the warm-up plane)
         T FZt[NR], GZt[NR], TXn[NR];
@@ -383,7 +406,7 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
             const auto Ok = group_rsrc(A.o + (size_t)k * 3 * P, 3 * PB);
 #pragma unroll
             for (int r = 1; r <= R; ++r) {
-                if constexpr (!EARLY) xx[r] = gld<T>(Tk, off[r], fXX);   // at its use: fewer live registers
+                if constexpr (!EARLY && R > 2) xx[r] = gld<T>(Tk, off[r], fXX);   // at its use: fewer live registers
                 const T ty = (Wc[r + 1] - Wc[r - 1]) * A.hy;
                 const T xxE = from_right(xx[r]), xyE = from_right(xy[r]), xzE = from_right(xz[r]);
                 const T wE = from_right(Wc[r]), tyE = from_right(ty), tzE = from_right(TZc[r]);
@@ -423,7 +446,7 @@ __global__ __launch_bounds__(64 * kMaxWaves3) void step3_pencil_kernel(Step3Args
         }
 #pragma unroll
         for (int r = 1; r <= R; ++r) {
-            TX[r] = TXn[r];
+            if constexpr (!RTX) TXc[r] = TXn[r];
             zz[r] = zzn[r];
             xz[r] = xzn[r];
             FZb[r] = FZt[r];
