@@ -24,8 +24,10 @@
 //     (c+c')/2 one iteration sooner; since levels K..2 read before the store of
 //     an iteration, rings of 2K-1 and 2K-2 rows suffice (2 and 1 for K = 1):
 //     10 KB for FP64 at K = 4, so 16 one-wave workgroups fit a CU's 160 KB;
-//   * the mirrored rows of the no-flux boundary (row -1 = row 0, row ny = row
-//     ny-1) are written into the rings, so rows need no per-row selects.
+//   * the mirrored row -1 (= row 0) of the no-flux boundary is written into
+//     the rings; row ny is never computed: the only value of it that matters,
+//     the y-difference of w at row ny-1, selects row ny-1 itself (the faces
+//     through the top boundary are zero).
 // Each level starts one row early (a warm-up row) to produce its carried south
 // face, and one row before that it takes the x-difference of its first row.
 // The lanes at the two ends of the wave receive no neighbour; they lie outside
@@ -35,6 +37,10 @@
 // The arithmetic per cell is the single-step kernel's, in the same order (the
 // shared sums and products are the same operations on the same operands), so K
 // fused steps equal K single steps bit for bit.
+//
+// The FP32 instances are built in ggfv_fused_dpp.hip and the FP64 ones in
+// ggfv_fused_dpp_f64.hip, each under the instruction schedule that measured
+// fastest for it.
 
 #ifndef GGFV_FUSED_DPP_HPP
 #define GGFV_FUSED_DPP_HPP
