@@ -118,3 +118,14 @@ def test_null_batch_calls_are_rejected(built):
     lib = pk.lib()
     assert lib.ggfv_batch_set(None, 0, None, 1e-3, *([None] * 6), pk.GGFV_HOST, pk.GGFV_F64) == pk.GGFV_EINVAL
     assert lib.ggfv_batch_get_state(None, 0, None, None, None, pk.GGFV_HOST, pk.GGFV_F64) == pk.GGFV_EINVAL
+
+
+def test_build_flags_name_existing_sources():
+    """Per-source compiler flags are keyed by file name: a renamed source would
+    silently lose its instruction schedule.  The lane-shift instances are split
+    by precision across exactly the two sources the flags distinguish."""
+    from paper_2006_01748_amd import build as b
+    names = {os.path.basename(p) for p in b.sources()}
+    assert set(b.SOURCE_FLAGS) <= names
+    assert {"ggfv_fused_dpp.hip", "ggfv_fused_dpp_f64.hip"} <= names
+    assert "ggfv_fused_dpp_f64.hip" not in b.SOURCE_FLAGS
