@@ -152,14 +152,20 @@ def roofline_of(variant, r):
                 "kernel": kname, "kernel_avg_us": r["kernel_avg_us"],
                 "bytes_per_cell_update": BYTES_PER_CELL[variant]}
     K = r["fused_steps"]
-    return {"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": traffic,
-            "kernel": kname,
-            "kernel_avg_us": r["kernel_avg_us"], "steps_per_launch": K,
-            "flops_per_cell_update": FLOPS_PER_CELL,
-            "hbm_algorithmic_bytes_per_launch": BYTES_PER_CELL[variant] * r["cells"],
-            "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_effective_GBs": r["effective_GBs"],
-            "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS}
+    out = {"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+           "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": traffic,
+           "kernel": kname,
+           "kernel_avg_us": r["kernel_avg_us"], "steps_per_launch": K,
+           "flops_per_cell_update": FLOPS_PER_CELL,
+           "hbm_algorithmic_bytes_per_launch": BYTES_PER_CELL[variant] * r["cells"],
+           "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_effective_GBs": r["effective_GBs"],
+           "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS}
+    if traffic is not None:
+        # the HBM bytes the kernel really moves (counters), per second: the
+        # second limit of the fused kernels, next to the vector ALU
+        out["hbm_measured_GBs"] = traffic / (r["kernel_avg_us"] * 1e-6) / 1e9
+        out["hbm_measured_frac"] = out["hbm_measured_GBs"] / PEAK_HBM_GBS
+    return out
 
 
 def log(msg):
