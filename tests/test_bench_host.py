@@ -1,0 +1,73 @@
+"""Host logic of bench.py, on the CPU: the roofline object of the JSON line,
+the kernel names the profile summaries are keyed by, the grouping of counter
+dispatches, and the refusal of more than one GPU."""
+import csv
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def fake_run(variant, tuning, kernel_us=250.0, n=4096):
+    cells = n * n
+    K = max(1, tuning.get("fused_steps", 1))
+    gbs = bench.BYTES_PER_CELL[variant] * cells / (kernel_us * 1e-6) / 1e9
+    return {"tuning": tuning, "fused_steps": K, "rows": tuning.get("rows_per_strip", 0), "cells": cells,
+            "kernel_avg_us": kernel_us, "achieved_GBs": gbs, "effective_GBs": K * gbs,
+            "achieved_TFLOPs": bench.FLOPS_PER_CELL * K * cells / (kernel_us * 1e-6) / 1e12}
+
+
+@pytest.mark.parametrize("variant", ["f64", "f32c", "f32"])
+def test_roofline_object_has_the_contract_keys(variant):
+    shape = dict(zip(("rows_per_strip", "threads", "fused_steps", "lane_shift"), bench.HEADLINE_SHAPE[variant]))
+    for tuning, bound in ((shape, "alu"), ({"fused_steps": 1, "threads": 0, "lane_shift": 0}, "hbm")):
+        r = fake_run(variant, tuning)
+        roof = bench.roofline_of(variant, r)
+        for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+            assert key in roof
+        assert roof["bound"] == bound
+        assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"])
+        assert roof["peak"] == (bench.PEAK_VALU_TFLOPS if bound == "alu" else bench.PEAK_HBM_GBS)
+        if roof["traffic"] is not None and bound == "alu":
+            assert roof["hbm_measured_GBs"] == pytest.approx(roof["traffic"] / (250e-6) / 1e9)
+
+
+def test_headline_kernel_names():
+    names = {v: bench.kernel_name(v, dict(zip(("rows_per_strip", "threads", "fused_steps", "lane_shift"),
+                                               bench.HEADLINE_SHAPE[v]))) for v in bench.HEADLINE_SHAPE}
+    assert names["f64"] == ("fused_dpp_kernel<double, false, 2, 4>", "wide4")
+    assert names["f32c"] == ("fused_dpp_kernel<float, true, 2, 4>", "lanes4")
+    assert names["f32"] == ("fused_dpp_kernel<float, false, 4, 4>", "wide4")
+    assert bench.kernel_name("f64", {"fused_steps": 1, "threads": 0}) == ("step_kernel<double, false, 1, 256>",
+                                                                           "single")
+
+
+def test_counter_means_separate_equal_thread_counts(tmp_path):
+    """Two launch shapes with the same thread count but different workgroup
+    sizes must not be averaged together."""
+    d = tmp_path / "fetch"
+    d.mkdir()
+    rows = []
+    for disp, wg, val in ((1, 64, 10.0), (2, 64, 14.0), (3, 128, 100.0)):
+        for counter, part in (("FETCH_SIZE", val),):
+            rows.append({"Dispatch_Id": disp, "Kernel_Name": "void ggfv::(anonymous namespace)::k<double, 2>(int)", "Grid_Size": 8192,
+                         "Workgroup_Size": wg, "Counter_Name": counter, "Counter_Value": part})
+    with open(d / "fetch_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    means = bench._counter_means(str(tmp_path), "fetch")
+    assert means[("k<double, 2>", 8192, 64)] == pytest.approx(12.0)
+    assert means[("k<double, 2>", 8192, 128)] == pytest.approx(100.0)
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
