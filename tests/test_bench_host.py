@@ -52,11 +52,10 @@ def test_counter_means_separate_equal_thread_counts(tmp_path):
     sizes must not be averaged together."""
     d = tmp_path / "fetch"
     d.mkdir()
-    rows = []
-    for disp, wg, val in ((1, 64, 10.0), (2, 64, 14.0), (3, 128, 100.0)):
-        for counter, part in (("FETCH_SIZE", val),):
-            rows.append({"Dispatch_Id": disp, "Kernel_Name": "void ggfv::(anonymous namespace)::k<double, 2>(int)", "Grid_Size": 8192,
-                         "Workgroup_Size": wg, "Counter_Name": counter, "Counter_Value": part})
+    name = "void ggfv::(anonymous namespace)::k<double, 2>(int)"
+    rows = [{"Dispatch_Id": disp, "Kernel_Name": name, "Grid_Size": 8192, "Workgroup_Size": wg,
+             "Counter_Name": "FETCH_SIZE", "Counter_Value": val}
+            for disp, wg, val in ((1, 64, 10.0), (2, 64, 14.0), (3, 128, 100.0))]
     with open(d / "fetch_counter_collection.csv", "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=list(rows[0]))
         w.writeheader()
