@@ -267,3 +267,28 @@ def test_step3_definiteness_is_checked_after_rounding():
         with pytest.raises(pk.GGFVError) as e:
             ctx.set_tensor(*T)                           # FP64 arrays, rounded on the way in
         assert e.value.status == pk.GGFV_EINVAL and "in 1 cells" in str(e.value)
+
+
+def test_step3_full_size_f32_default_shape():
+    """The 256^3 slab tissue in FP32 in the library's default launch shape
+    (four rows per wave, every x-strip of a row group in one workgroup),
+    5 steps, against the FP64 oracle run on the FP32-rounded inputs."""
+    w = wl.tissue3(n=256)
+    g = rng(98)
+    state = (np.clip(w.u0 + 0.1 * g.random(w.u0.shape), 0, 1), w.v0, 0.2 * g.random(w.u0.shape))
+    s32 = [x.astype(np.float32) for x in state]
+    A32 = [x.astype(np.float32) for x in w.tensor]
+    dt = float(np.float32(oracle.stable_dt3([x.astype(np.float64) for x in A32], w.params[2], w.safety)))
+    with pk.Context3(w.nx, w.ny, w.nz, dtype="f32") as ctx:
+        ctx.set_params(w.params)
+        ctx.set_tensor(*A32)
+        ctx.set_state(*s32)
+        t = ctx.get_tuning()
+        assert (t["rows_per_wave"], t["waves_x"], t["z_per_strip"]) == (4, 5, 32)
+        print(f"step3 f32 full size, shape {t}", flush=True)
+        ctx.step(dt, 5)
+        got = ctx.get_state()
+    ref = oracle.run3(*[x.astype(np.float64) for x in s32], [x.astype(np.float64) for x in A32], w.params, dt, 5)
+    for x, y in zip(got, ref):
+        scale = max(1.0, float(np.abs(y).max()))
+        assert np.abs(x - y).max() <= 5e-4 * scale
