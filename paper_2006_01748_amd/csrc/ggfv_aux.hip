@@ -337,7 +337,8 @@ __global__ __launch_bounds__(64) void front_row_kernel(const T *__restrict__ st,
 
 // Front diagnostics over rows: sums, minima and maxima of the per-row values
 // (each thread a fixed contiguous range of rows, then the fixed-order block
-// reduction), and the counts; out as the oracle's front diagnostics.
+// reduction), and the counts; out holds the 11 results of
+// ggfv_front_diagnostics in the order include/ggfv.h documents.
 __global__ __launch_bounds__(kReduceThreads) void front_final_kernel(const double *__restrict__ rows, int ny,
                                                                      double *__restrict__ out)
 {
