@@ -147,10 +147,10 @@ def roofline_of(variant, r):
     kname, _ = kernel_name(variant, r["tuning"])
     traffic = measured_traffic(variant, r["tuning"], r["rows"])
     if r["fused_steps"] == 1 and not r["tuning"].get("lane_shift"):
-        return {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
-                "kernel": kname, "kernel_avg_us": r["kernel_avg_us"],
-                "bytes_per_cell_update": BYTES_PER_CELL[variant]}
+        return with_measured({"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
+                              "kernel": kname, "kernel_avg_us": r["kernel_avg_us"],
+                              "bytes_per_cell_update": BYTES_PER_CELL[variant]}, r["kernel_avg_us"])
     K = r["fused_steps"]
     out = {"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
            "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": traffic,
@@ -160,12 +160,18 @@ def roofline_of(variant, r):
            "hbm_algorithmic_bytes_per_launch": BYTES_PER_CELL[variant] * r["cells"],
            "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_effective_GBs": r["effective_GBs"],
            "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS}
-    if traffic is not None:
-        # the HBM bytes the kernel really moves (counters), per second: the
-        # second limit of the fused kernels, next to the vector ALU
-        out["hbm_measured_GBs"] = traffic / (r["kernel_avg_us"] * 1e-6) / 1e9
-        out["hbm_measured_frac"] = out["hbm_measured_GBs"] / PEAK_HBM_GBS
-    return out
+    # the HBM bytes the kernel really moves, per second: the second limit of
+    # the fused kernels, next to the vector ALU
+    return with_measured(out, r["kernel_avg_us"])
+
+
+def with_measured(roof, kernel_us):
+    """Add the measured HBM rate (the counters' bytes per launch over the live
+    launch time) to a roofline object whose `traffic` is known."""
+    if roof.get("traffic") is not None:
+        roof["hbm_measured_GBs"] = roof["traffic"] / (kernel_us * 1e-6) / 1e9
+        roof["hbm_measured_frac"] = roof["hbm_measured_GBs"] / PEAK_HBM_GBS
+    return roof
 
 
 def log(msg):
@@ -443,8 +449,9 @@ def time_3d(pk, torch, n=256, steps=100, warmup=10, dtypes=("f64", "f32"), trial
         out["variants"][dt_name] = {
             "value": w.cells * steps / (ms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "kernel_avg_us": us,
             "launch_shape": shape, "kernel": f"step3_pencil_kernel<{'double' if dt_name == 'f64' else 'float'}, {rows}>",
-            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": gbs / PEAK_HBM_GBS, "traffic": measured_traffic3(dt_name, shape)},
+            "roofline": with_measured({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                       "frac": gbs / PEAK_HBM_GBS, "traffic": measured_traffic3(dt_name, shape)},
+                                      us),
             "bytes_per_cell_update": per, "dt": dt, "mass": list(mass),
             "shape_sweep_us": {k: round(v, 1) for k, v in sweep.items()}}
     return out
@@ -1020,13 +1027,13 @@ def main():
             "grid": [w.nx, w.ny], "params": list(w.params), "dt": r["dt"], "launch_shape": r["tuning"],
         },
         "roofline": roofline_of(head, r),
-        "single_step_kernel": {
+        "single_step_kernel": with_measured({
             "kernel": kernel_name(head, s1["tuning"])[0], "value": s1["value"],
             "kernel_avg_us": s1["kernel_avg_us"], "bound": "hbm",
             "achieved": s1["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": s1["achieved_GBs"] / PEAK_HBM_GBS,
             "traffic": measured_traffic(head, s1["tuning"], s1["rows"]),
-            "bytes_per_cell_update": BYTES_PER_CELL[head]},
+            "bytes_per_cell_update": BYTES_PER_CELL[head]}, s1["kernel_avg_us"]),
         "cpu_baseline": base,
         "variants": {v: {"tuned": res[v]["tuning"], "value": res[v]["value"],
                          "launch_avg_us": res[v]["kernel_avg_us"], "roofline": roofline_of(v, res[v]),

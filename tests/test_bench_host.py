@@ -33,8 +33,10 @@ def test_roofline_object_has_the_contract_keys(variant):
         assert roof["bound"] == bound
         assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"])
         assert roof["peak"] == (bench.PEAK_VALU_TFLOPS if bound == "alu" else bench.PEAK_HBM_GBS)
-        if roof["traffic"] is not None and bound == "alu":
+        if roof["traffic"] is not None:
             assert roof["hbm_measured_GBs"] == pytest.approx(roof["traffic"] / (250e-6) / 1e9)
+        else:
+            assert "hbm_measured_GBs" not in roof
 
 
 def test_headline_kernel_names():
