@@ -175,6 +175,41 @@ def test_full_size_500_steps_headline_shape_each_delta1(delta1):
             assert np.array_equal(x, r), (name, j0, i0, float(np.max(np.abs(x - r))))
 
 
+def test_full_size_10000_steps_transpose_and_reflection():
+    """The scheme is equivariant, bit for bit, under the transpose (x <-> y with
+    a <-> c) and the reflection x -> 1 - x (with b -> -b); the oracle pins both,
+    and the device matches the oracle bit for bit, so the device must keep them
+    exactly at any size and length.  4096^2 layered tissue with a perturbed,
+    asymmetric state, the workload's 10000 FP64 steps in the benchmark's launch
+    shape: the transposed and the mirrored problems (which fall on different
+    strips, lanes and strip seams) give the transposed and mirrored result."""
+    w = wl.cfg2(steps=10000)
+    a, b, c = oracle.tensor_from_eig(*w.eig)
+    g = rng(77)
+    u0 = np.clip(w.u0 + 0.05 * g.random(w.u0.shape), 0.0, 1.0)
+    w0 = 0.1 * g.random(w.u0.shape)
+    state = (u0, w.v0, w0)
+    C = np.ascontiguousarray
+
+    def run(st, abc, dt=None):
+        ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, [C(x) for x in st], abc=[C(x) for x in abc])
+        ctx.set_tuning(0, 64, 4, lane_shift=2)
+        dt = ctx.stable_dt(0.9) if dt is None else dt
+        ctx.step(dt, w.steps)
+        out = ctx.get_state()
+        ctx.close()
+        return out, dt
+
+    base, dt = run(state, (a, b, c))
+    print(f"base run done, dt={dt!r}", flush=True)
+    tr, _ = run([x.T for x in state], (c.T, b.T, a.T), dt)
+    for name, x, y in zip("uvw", tr, base):
+        assert np.array_equal(x, y.T), f"{name}: transposed run differs"
+    mi, _ = run([x[:, ::-1] for x in state], (a[:, ::-1], -b[:, ::-1], c[:, ::-1]), dt)
+    for name, x, y in zip("uvw", mi, base):
+        assert np.array_equal(x, y[:, ::-1]), f"{name}: mirrored run differs"
+
+
 @pytest.mark.parametrize("dtype,shape,tol", [("f32", (0, 64, 4, 2), 5e-4), ("f32c", (0, 64, 4, 1), 1e-5)])
 def test_full_size_fp32_headline_shapes(dtype, shape, tol):
     """4096^2 layered tissue in the FP32 launch shapes the benchmark times (wide
