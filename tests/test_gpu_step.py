@@ -175,14 +175,17 @@ def test_full_size_500_steps_headline_shape_each_delta1(delta1):
             assert np.array_equal(x, r), (name, j0, i0, float(np.max(np.abs(x - r))))
 
 
-def test_full_size_10000_steps_transpose_and_reflection():
+@pytest.mark.parametrize("dtype,shape", [("f64", (0, 64, 4, 2)), ("f32", (0, 64, 4, 2)), ("f32c", (0, 64, 4, 1))])
+def test_full_size_10000_steps_transpose_and_reflection(dtype, shape):
     """The scheme is equivariant, bit for bit, under the transpose (x <-> y with
     a <-> c) and the reflection x -> 1 - x (with b -> -b); the oracle pins both,
     and the device matches the oracle bit for bit, so the device must keep them
-    exactly at any size and length.  4096^2 layered tissue with a perturbed,
-    asymmetric state, the workload's 10000 FP64 steps in the benchmark's launch
-    shape: the transposed and the mirrored problems (which fall on different
-    strips, lanes and strip seams) give the transposed and mirrored result."""
+    exactly at any size and length (the FP32 kernels evaluate the same
+    expressions, so they keep them too).  4096^2 layered tissue with a
+    perturbed, asymmetric state, the workload's 10000 steps in the benchmark's
+    launch shape of each precision: the transposed and the mirrored problems
+    (which fall on different strips, lanes and strip seams) give the transposed
+    and mirrored result."""
     w = wl.cfg2(steps=10000)
     a, b, c = oracle.tensor_from_eig(*w.eig)
     g = rng(77)
@@ -192,8 +195,8 @@ def test_full_size_10000_steps_transpose_and_reflection():
     C = np.ascontiguousarray
 
     def run(st, abc, dt=None):
-        ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, [C(x) for x in st], abc=[C(x) for x in abc])
-        ctx.set_tuning(0, 64, 4, lane_shift=2)
+        ctx = gpu_ctx(w.nx, w.ny, dtype, w.params, [C(x) for x in st], abc=[C(x) for x in abc])
+        ctx.set_tuning(*shape)
         dt = ctx.stable_dt(0.9) if dt is None else dt
         ctx.step(dt, w.steps)
         out = ctx.get_state()
