@@ -213,6 +213,39 @@ def test_full_size_10000_steps_transpose_and_reflection(dtype, shape):
         assert np.array_equal(x, y[:, ::-1]), f"{name}: mirrored run differs"
 
 
+@pytest.mark.parametrize("dtype,shape,tol", [("f64", (0, 64, 4, 2), 1e-10), ("f32", (0, 64, 4, 2), 1e-4),
+                                             ("f32c", (0, 64, 4, 1), 1e-7)])
+def test_full_size_10000_steps_conservation_and_equilibria(dtype, shape, tol):
+    """Properties that hold at any size, at the benchmark's size and length in
+    each precision's headline shape.  With the reactions off, zero boundary
+    flux conserves the tumour-cell and acid masses: every face flux leaves one
+    cell and enters the other, so only the rounding of each cell's update moves
+    the sum (bars: 10^4 steps x 10 x the unit roundoff, FP64 1e-10, FP32 1e-4,
+    compensated FP32 1e-7).  The homogeneous equilibria (1, 0, 0) and
+    (0, 1, rho3/delta3) stay exactly in place."""
+    w = wl.cfg2(steps=10000)
+    g = rng(78)
+    state = (np.clip(w.u0 + 0.05 * g.random(w.u0.shape), 0.0, 1.0), w.v0, 0.1 * g.random(w.u0.shape))
+    off = (0.0, 0.0, w.params[2], 0.0, 0.0)               # no reactions, Delta2 kept
+    ctx = gpu_ctx(w.nx, w.ny, dtype, off, state, eig=w.eig)
+    ctx.set_tuning(*shape)
+    dt = ctx.stable_dt(0.9)
+    m0 = ctx.diagnostics()["mass"]
+    ctx.step(dt, w.steps)
+    m1 = ctx.diagnostics()["mass"]
+    drift = np.abs(m1[1:] - m0[1:]) / m0[1:]
+    print(f"{dtype}: relative mass drift of v, w after {w.steps} steps: {drift}", flush=True)
+    assert np.all(drift <= tol)
+    ctx.set_params(w.params)
+    rho3, delta3 = w.params[3], w.params[4]
+    for eq in ((1.0, 0.0, 0.0), (0.0, 1.0, rho3 / delta3)):
+        ctx.set_state(*[np.full((w.ny, w.nx), x) for x in eq])
+        ctx.step(dt, w.steps)
+        for name, x, e in zip("uvw", ctx.get_state(), eq):
+            assert np.all(x == np.float32(e) if dtype != "f64" else x == e), (dtype, eq, name)
+    ctx.close()
+
+
 @pytest.mark.parametrize("dtype,shape,tol", [("f32", (0, 64, 4, 2), 5e-4), ("f32c", (0, 64, 4, 1), 1e-5)])
 def test_full_size_fp32_headline_shapes(dtype, shape, tol):
     """4096^2 layered tissue in the FP32 launch shapes the benchmark times (wide
