@@ -292,3 +292,27 @@ def test_step3_full_size_f32_default_shape():
     for x, y in zip(got, ref):
         scale = max(1.0, float(np.abs(y).max()))
         assert np.abs(x - y).max() <= 5e-4 * scale
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-11), ("f32", 1e-4)])
+def test_step3_full_size_conservation(dtype, tol):
+    """256^3 slab tissue in the default launch shape, 500 steps with the
+    reactions off: the zero-flux scheme conserves the tumour-cell and acid
+    masses up to the rounding of each cell's update (bars: 500 steps x 10 x the
+    unit roundoff, rounded up)."""
+    w = wl.tissue3(n=256)
+    g = rng(97)
+    state = (np.clip(w.u0 + 0.1 * g.random(w.u0.shape), 0, 1), w.v0, 0.2 * g.random(w.u0.shape))
+    npdt = np.float64 if dtype == "f64" else np.float32
+    prm = (0.0, 0.0, w.params[2], 0.0, 0.0)
+    with pk.Context3(w.nx, w.ny, w.nz, dtype=dtype) as ctx:
+        ctx.set_params(prm)
+        ctx.set_tensor(*[x.astype(npdt) for x in w.tensor])
+        ctx.set_state(*[x.astype(npdt) for x in state])
+        dt = ctx.stable_dt(w.safety)
+        m0 = np.array(ctx.mass())
+        ctx.step(dt, 500)
+        m1 = np.array(ctx.mass())
+    drift = np.abs(m1[1:] - m0[1:]) / m0[1:]
+    print(f"3D {dtype}: relative mass drift of v, w after 500 steps: {drift}", flush=True)
+    assert np.all(drift <= tol)
