@@ -139,29 +139,27 @@ def measured_traffic3(dtype, shape):
 
 
 def roofline_of(variant, r):
-    """Roofline of the kernel that dominates a timed run.  A single-step launch
-    moves BYTES_PER_CELL bytes per cell and is HBM-bound; a fused launch reads
-    and writes the same bytes for K steps and is bound by vector arithmetic, so
-    it is placed against the non-FMA vector rate (FLOPS_PER_CELL per
-    cell-update), with its HBM figures beside it."""
+    """Roofline of the kernel that dominates a timed run.  Every launch, single
+    step or fused, is bound by HBM: it moves BYTES_PER_CELL bytes per cell (a
+    fused launch once for its K steps), and the fused launches take the same time
+    for K = 2, 3 and 4 although their arithmetic doubles.  `achieved` is those
+    algorithmic bytes over the launch time; a fused launch also carries its
+    vector-arithmetic figures (FLOPS_PER_CELL per cell-update against the
+    non-FMA vector rate) and the effective rate of K single steps."""
     kname, _ = kernel_name(variant, r["tuning"])
     traffic = measured_traffic(variant, r["tuning"], r["rows"])
-    if r["fused_steps"] == 1 and not r["tuning"].get("lane_shift"):
-        return with_measured({"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                              "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
-                              "kernel": kname, "kernel_avg_us": r["kernel_avg_us"],
-                              "bytes_per_cell_update": BYTES_PER_CELL[variant]}, r["kernel_avg_us"])
-    K = r["fused_steps"]
-    out = {"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-           "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS, "traffic": traffic,
-           "kernel": kname,
-           "kernel_avg_us": r["kernel_avg_us"], "steps_per_launch": K,
-           "flops_per_cell_update": FLOPS_PER_CELL,
-           "hbm_algorithmic_bytes_per_launch": BYTES_PER_CELL[variant] * r["cells"],
-           "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_effective_GBs": r["effective_GBs"],
-           "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS}
-    # the HBM bytes the kernel really moves, per second: the second limit of
-    # the fused kernels, next to the vector ALU
+    out = {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
+           "kernel": kname, "kernel_avg_us": r["kernel_avg_us"],
+           "bytes_per_cell_update": BYTES_PER_CELL[variant]}
+    if r["fused_steps"] > 1 or r["tuning"].get("lane_shift"):
+        out.update({"steps_per_launch": r["fused_steps"],
+                    "hbm_algorithmic_bytes_per_launch": BYTES_PER_CELL[variant] * r["cells"],
+                    "hbm_effective_GBs": r["effective_GBs"],
+                    "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS,
+                    "flops_per_cell_update": FLOPS_PER_CELL,
+                    "valu_TFLOPs": r["achieved_TFLOPs"], "valu_peak_TFLOPs": PEAK_VALU_TFLOPS,
+                    "valu_frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS})
     return with_measured(out, r["kernel_avg_us"])
 
 
