@@ -138,28 +138,39 @@ def measured_traffic3(dtype, shape):
     return t["read"] + t["write"]
 
 
+# The resource that bounds each precision's fused kernel, from the
+# measurements: FP64 and the compensated state are bound by HBM per launch
+# (FP64's launch time is flat for K = 2..4 while its arithmetic doubles; both
+# issue vector instructions at 66-84% of the rate), plain FP32 by vector issue
+# (95% of the rate).
+FUSED_BOUND = {"f64": "hbm", "f32c": "hbm", "f32": "alu"}
+
+
 def roofline_of(variant, r):
-    """Roofline of the kernel that dominates a timed run.  Every launch, single
-    step or fused, is bound by HBM: it moves BYTES_PER_CELL bytes per cell (a
-    fused launch once for its K steps), and the fused launches take the same time
-    for K = 2, 3 and 4 although their arithmetic doubles.  `achieved` is those
-    algorithmic bytes over the launch time; a fused launch also carries its
-    vector-arithmetic figures (FLOPS_PER_CELL per cell-update against the
-    non-FMA vector rate) and the effective rate of K single steps."""
+    """Roofline of the kernel that dominates a timed run.  A single-step launch
+    moves BYTES_PER_CELL bytes per cell and is bound by HBM.  A fused launch
+    moves the same bytes once for its K steps; it is placed against HBM
+    (algorithmic bytes over the launch time) or against the non-FMA vector rate
+    (FLOPS_PER_CELL per cell-update), as FUSED_BOUND says, with the other
+    figures beside it."""
     kname, _ = kernel_name(variant, r["tuning"])
     traffic = measured_traffic(variant, r["tuning"], r["rows"])
-    out = {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-           "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
-           "kernel": kname, "kernel_avg_us": r["kernel_avg_us"],
+    hbm = {"achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": r["achieved_GBs"] / PEAK_HBM_GBS}
+    out = {"bound": "hbm", **hbm, "traffic": traffic, "kernel": kname, "kernel_avg_us": r["kernel_avg_us"],
            "bytes_per_cell_update": BYTES_PER_CELL[variant]}
     if r["fused_steps"] > 1 or r["tuning"].get("lane_shift"):
         out.update({"steps_per_launch": r["fused_steps"],
                     "hbm_algorithmic_bytes_per_launch": BYTES_PER_CELL[variant] * r["cells"],
+                    "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_frac": hbm["frac"],
                     "hbm_effective_GBs": r["effective_GBs"],
                     "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS,
                     "flops_per_cell_update": FLOPS_PER_CELL,
                     "valu_TFLOPs": r["achieved_TFLOPs"], "valu_peak_TFLOPs": PEAK_VALU_TFLOPS,
                     "valu_frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS})
+        if FUSED_BOUND[variant] == "alu":
+            out.update({"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS,
+                        "unit": "TFLOP/s", "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS})
     return with_measured(out, r["kernel_avg_us"])
 
 

@@ -26,16 +26,17 @@ def fake_run(variant, tuning, kernel_us=250.0, n=4096):
 def test_roofline_object_has_the_contract_keys(variant):
     shape = dict(zip(("rows_per_strip", "threads", "fused_steps", "lane_shift"), bench.HEADLINE_SHAPE[variant]))
     for tuning in (shape, {"fused_steps": 1, "threads": 0, "lane_shift": 0}):
-        bound = "hbm"
+        bound = bench.FUSED_BOUND[variant] if tuning is shape else "hbm"
         r = fake_run(variant, tuning)
         roof = bench.roofline_of(variant, r)
         for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
             assert key in roof
         assert roof["bound"] == bound
         assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"])
-        assert roof["peak"] == bench.PEAK_HBM_GBS
+        assert roof["peak"] == (bench.PEAK_VALU_TFLOPS if bound == "alu" else bench.PEAK_HBM_GBS)
         if tuning is shape:
             assert roof["valu_frac"] == pytest.approx(roof["valu_TFLOPs"] / bench.PEAK_VALU_TFLOPS)
+            assert roof["hbm_frac"] == pytest.approx(roof["hbm_algorithmic_GBs"] / bench.PEAK_HBM_GBS)
         if roof["traffic"] is not None:
             assert roof["hbm_measured_GBs"] == pytest.approx(roof["traffic"] / (250e-6) / 1e9)
         else:
