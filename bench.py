@@ -138,11 +138,11 @@ def measured_traffic3(dtype, shape):
     return t["read"] + t["write"]
 
 
-# The resource that bounds each precision's fused kernel, from the
-# measurements: FP64 and the compensated state are bound by HBM per launch
-# (FP64's launch time is flat for K = 2..4 while its arithmetic doubles; both
-# issue vector instructions at 66-84% of the rate), plain FP32 by vector issue
-# (95% of the rate).
+# The resource that bounds each precision's fused kernel at K = 4, from the
+# launch time at K = 2, 3, 4 (4096^2, one box): FP64 266 / 259 / 268 us and
+# compensated FP32 249 / 248 / 241 us, flat while the arithmetic doubles, so
+# HBM per launch; plain FP32 143 / 143 / 158 us, flat until K = 4, where its
+# vector issue (95% of the rate) takes over.
 FUSED_BOUND = {"f64": "hbm", "f32c": "hbm", "f32": "alu"}
 
 
