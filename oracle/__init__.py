@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "ggfv_oracle.c")
 _SRC_ADJ = os.path.join(_HERE, "ggfv_oracle_adjoint.c")
 _SRC_3D = os.path.join(_HERE, "ggfv_oracle3d.c")
 LIB_PATH = os.path.join(_HERE, "libggfv_oracle.so")
-CFLAGS = ["-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-std=c11"]
+CFLAGS = ["-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp"]
 
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
@@ -97,6 +97,9 @@ def bind(lib):
                                      p, p, p, p, p, p, p, p, p, p]
     lib.orc_eig_backward.argtypes = [l, p, p, p, p, p, p, p, p, p]
     lib.orc_adjoint_run.argtypes = [i, i, d, d, p, d, l, p, p, p, p, p, p, p, p, p, p, p, p, p]
+    lib.orc_adjoint_run_ckpt.argtypes = [i, i, d, d, p, d, l, l, p, p, p, p, p, p, p, p, p, p, p, p, p]
+    lib.orc_set_threads.argtypes = [i]
+    lib.orc_set_threads.restype = i
     return lib
 
 
@@ -343,3 +346,26 @@ def adjoint_run(u0, v0, w0, a, b, c, params, dt, nsteps, lam_final, lx=1.0, ly=1
                             _ptr(w0), _ptr(a), _ptr(b), _ptr(c), _ptr(lu), _ptr(lv), _ptr(lw),
                             _ptr(ga), _ptr(gb), _ptr(gc), _ptr(gp))
     return (lu, lv, lw), (ga, gb, gc), gp
+
+
+def adjoint_run_ckpt(u0, v0, w0, a, b, c, params, dt, nsteps, lam_final, every, lx=1.0, ly=1.0):
+    """adjoint_run with the states stored every `every` steps and each segment
+    recomputed before its adjoint steps (same results; about nsteps/every +
+    every states in memory, so full-length sweeps on large grids fit)."""
+    u0, v0, w0, a, b, c = (_f64(x) for x in (u0, v0, w0, a, b, c))
+    lu, lv, lw = (np.array(x, dtype=np.float64, copy=True, order="C") for x in lam_final)
+    ny, nx = u0.shape
+    prm = _f64(params)
+    ga, gb, gc = (np.zeros_like(u0) for _ in range(3))
+    gp = np.zeros(5)
+    _load().orc_adjoint_run_ckpt(nx, ny, lx, ly, _ptr(prm), float(dt), int(nsteps), int(every), _ptr(u0),
+                                 _ptr(v0), _ptr(w0), _ptr(a), _ptr(b), _ptr(c), _ptr(lu), _ptr(lv), _ptr(lw),
+                                 _ptr(ga), _ptr(gb), _ptr(gc), _ptr(gp))
+    return (lu, lv, lw), (ga, gb, gc), gp
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads the oracle's per-face and per-cell loops may use (n < 1: leave
+    the current setting, by default OMP_NUM_THREADS or every core); returns
+    the number in effect.  Results do not depend on it."""
+    return int(_load().orc_set_threads(int(n)))

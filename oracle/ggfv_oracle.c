@@ -46,10 +46,18 @@
  *   W' = W + dt*( (rho3*V - delta3*W) + divW )
  *
  * Built with -ffp-contract=off: no fused multiply-add anywhere.
+ *
+ * Threads: the per-face and per-cell loops may run over rows in parallel
+ * (OpenMP, when built with it).  Every value is still computed by one thread
+ * from the same operands in the same order, so the results do not depend on
+ * the number of threads; sums (masses, diagnostics) stay serial.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define IX(i, j) ((size_t)(j) * (size_t)nx + (size_t)(i))
 
@@ -58,6 +66,19 @@ static int clampi(int k, int n)
     if (k < 0) return 0;
     if (k >= n) return n - 1;
     return k;
+}
+
+/* Number of threads the parallel loops may use (n < 1: leave it); returns the
+ * number in effect (1 without OpenMP). */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */
@@ -128,15 +149,23 @@ static double tx_at(int nx, int ny, const double *W, int i, int j, double hx)
     return (W[IX(clampi(i + 1, nx), j)] - W[IX(clampi(i - 1, nx), j)]) * hx;
 }
 
-/* D2(W; A) of eq. (3), Table 2.  out[j*nx+i] = divergence of A grad W. */
-void orc_div_w(int nx, int ny, double lx, double ly, const double *W,
-               const double *a, const double *b, const double *c, double *out)
+/* D2(W; A) of eq. (3), Table 2.  out[j*nx+i] = divergence of A grad W.
+ * FX[j*(nx+1) + f]: face f between cells f-1 and f; f = 0 and f = nx are the
+ * domain boundary and carry zero flux.  FY[g*nx + i] likewise in y.  FX and FY
+ * are work arrays of (nx+1)*ny and nx*(ny+1) values. */
+static void div_w_work(int nx, int ny, double lx, double ly, const double *W, const double *a,
+                       const double *b, const double *c, double *out, double *FX, double *FY)
 {
     double idx = nx / lx, idy = ny / ly, hx = 0.5 * idx, hy = 0.5 * idy;
-    /* FX[j*(nx+1) + f]: face f between cells f-1 and f; f = 0 and f = nx are the
-     * domain boundary and carry zero flux.  FY[g*nx + i] likewise in y. */
-    double *FX = calloc((size_t)(nx + 1) * ny, sizeof(double));
-    double *FY = calloc((size_t)nx * (ny + 1), sizeof(double));
+    for (int j = 0; j < ny; ++j) {
+        FX[(size_t)j * (nx + 1)] = 0.0;
+        FX[(size_t)j * (nx + 1) + nx] = 0.0;
+    }
+    for (int i = 0; i < nx; ++i) {
+        FY[i] = 0.0;
+        FY[(size_t)ny * nx + i] = 0.0;
+    }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i + 1 < nx; ++i) {
             size_t l = IX(i, j), r = IX(i + 1, j);
@@ -145,7 +174,8 @@ void orc_div_w(int nx, int ny, double lx, double ly, const double *W,
             FX[(size_t)j * (nx + 1) + i + 1] =
                 0.5 * (a[l] + a[r]) * ((W[r] - W[l]) * idx) + 0.5 * (b[l] * tyl + b[r] * tyr);
         }
-    for (int j = 0; j + 1 < ny; ++j)
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny - 1; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t l = IX(i, j), r = IX(i, j + 1);
             double txl = tx_at(nx, ny, W, i, j, hx);
@@ -153,40 +183,66 @@ void orc_div_w(int nx, int ny, double lx, double ly, const double *W,
             FY[(size_t)(j + 1) * nx + i] =
                 0.5 * (c[l] + c[r]) * ((W[r] - W[l]) * idy) + 0.5 * (b[l] * txl + b[r] * txr);
         }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double fe = FX[(size_t)j * (nx + 1) + i + 1], fw = FX[(size_t)j * (nx + 1) + i];
             double fn = FY[(size_t)(j + 1) * nx + i], fs = FY[(size_t)j * nx + i];
             out[IX(i, j)] = (fe - fw) * idx + (fn - fs) * idy;
         }
+}
+
+void orc_div_w(int nx, int ny, double lx, double ly, const double *W,
+               const double *a, const double *b, const double *c, double *out)
+{
+    double *FX = malloc((size_t)(nx + 1) * ny * sizeof(double));
+    double *FY = malloc((size_t)nx * (ny + 1) * sizeof(double));
+    div_w_work(nx, ny, lx, ly, W, a, b, c, out, FX, FY);
     free(FX);
     free(FY);
 }
 
 /* D1(V; U) of eq. (3), Table 1: divergence of (1-U) grad V with face mobility
- * 1 - (U_l + U_r)/2. */
-void orc_div_v(int nx, int ny, double lx, double ly, const double *U, const double *V,
-               double *out)
+ * 1 - (U_l + U_r)/2.  GX, GY: work arrays laid out as FX, FY of div_w_work. */
+static void div_v_work(int nx, int ny, double lx, double ly, const double *U, const double *V,
+                       double *out, double *GX, double *GY)
 {
     double idx = nx / lx, idy = ny / ly;
-    double *GX = calloc((size_t)(nx + 1) * ny, sizeof(double));
-    double *GY = calloc((size_t)nx * (ny + 1), sizeof(double));
+    for (int j = 0; j < ny; ++j) {
+        GX[(size_t)j * (nx + 1)] = 0.0;
+        GX[(size_t)j * (nx + 1) + nx] = 0.0;
+    }
+    for (int i = 0; i < nx; ++i) {
+        GY[i] = 0.0;
+        GY[(size_t)ny * nx + i] = 0.0;
+    }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i + 1 < nx; ++i) {
             size_t l = IX(i, j), r = IX(i + 1, j);
             GX[(size_t)j * (nx + 1) + i + 1] = (1.0 - 0.5 * (U[l] + U[r])) * ((V[r] - V[l]) * idx);
         }
-    for (int j = 0; j + 1 < ny; ++j)
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny - 1; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t l = IX(i, j), r = IX(i, j + 1);
             GY[(size_t)(j + 1) * nx + i] = (1.0 - 0.5 * (U[l] + U[r])) * ((V[r] - V[l]) * idy);
         }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double ge = GX[(size_t)j * (nx + 1) + i + 1], gw = GX[(size_t)j * (nx + 1) + i];
             double gn = GY[(size_t)(j + 1) * nx + i], gs = GY[(size_t)j * nx + i];
             out[IX(i, j)] = (ge - gw) * idx + (gn - gs) * idy;
         }
+}
+
+void orc_div_v(int nx, int ny, double lx, double ly, const double *U, const double *V,
+               double *out)
+{
+    double *GX = malloc((size_t)(nx + 1) * ny * sizeof(double));
+    double *GY = malloc((size_t)nx * (ny + 1) * sizeof(double));
+    div_v_work(nx, ny, lx, ly, U, V, out, GX, GY);
     free(GX);
     free(GY);
 }
@@ -197,17 +253,45 @@ void orc_div_v(int nx, int ny, double lx, double ly, const double *U, const doub
 /* source arrays su, sv, sw (NULL for none) add dt*S after the scheme's own   */
 /* update; they exist only for manufactured-solution tests.                   */
 
-void orc_step(int nx, int ny, double lx, double ly, const double *prm, double dt,
-              const double *u, const double *v, const double *w, const double *a,
-              const double *b, const double *c, double *un, double *vn, double *wn,
-              const double *su, const double *sv, const double *sw)
+/* Work arrays of one step: divergences dW, dV (n values each) and the face
+ * fluxes of both operators. */
+typedef struct {
+    double *dW, *dV, *FX, *FY, *GX, *GY;
+} step_work;
+
+static int work_alloc(step_work *ws, int nx, int ny)
+{
+    size_t n = (size_t)nx * ny, fx = (size_t)(nx + 1) * ny, fy = (size_t)nx * (ny + 1);
+    ws->dW = malloc(n * sizeof(double));
+    ws->dV = malloc(n * sizeof(double));
+    ws->FX = malloc(fx * sizeof(double));
+    ws->FY = malloc(fy * sizeof(double));
+    ws->GX = malloc(fx * sizeof(double));
+    ws->GY = malloc(fy * sizeof(double));
+    return ws->dW && ws->dV && ws->FX && ws->FY && ws->GX && ws->GY;
+}
+
+static void work_free(step_work *ws)
+{
+    free(ws->dW);
+    free(ws->dV);
+    free(ws->FX);
+    free(ws->FY);
+    free(ws->GX);
+    free(ws->GY);
+}
+
+static void step_work_run(int nx, int ny, double lx, double ly, const double *prm, double dt,
+                          const double *u, const double *v, const double *w, const double *a,
+                          const double *b, const double *c, double *un, double *vn, double *wn,
+                          const double *su, const double *sv, const double *sw, step_work *ws)
 {
     size_t n = (size_t)nx * ny;
     double d1 = prm[0], r2 = prm[1], D2 = prm[2], r3 = prm[3], d3 = prm[4];
-    double *dW = malloc(n * sizeof(double));
-    double *dV = malloc(n * sizeof(double));
-    orc_div_w(nx, ny, lx, ly, w, a, b, c, dW);
-    orc_div_v(nx, ny, lx, ly, u, v, dV);
+    double *dW = ws->dW, *dV = ws->dV;
+    div_w_work(nx, ny, lx, ly, w, a, b, c, dW, ws->FX, ws->FY);
+    div_v_work(nx, ny, lx, ly, u, v, dV, ws->GX, ws->GY);
+#pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; ++k) {
         double U = u[k], V = v[k], W = w[k];
         double Un = U + dt * (U * (1.0 - U) - (d1 * U) * W);
@@ -220,8 +304,17 @@ void orc_step(int nx, int ny, double lx, double ly, const double *prm, double dt
         vn[k] = Vn;
         wn[k] = Wn;
     }
-    free(dW);
-    free(dV);
+}
+
+void orc_step(int nx, int ny, double lx, double ly, const double *prm, double dt,
+              const double *u, const double *v, const double *w, const double *a,
+              const double *b, const double *c, double *un, double *vn, double *wn,
+              const double *su, const double *sv, const double *sw)
+{
+    step_work ws = {0};
+    if (work_alloc(&ws, nx, ny))
+        step_work_run(nx, ny, lx, ly, prm, dt, u, v, w, a, b, c, un, vn, wn, su, sv, sw, &ws);
+    work_free(&ws);
 }
 
 /* max over cells of the per-cell Gershgorin bound of the explicit update's
@@ -410,25 +503,30 @@ void orc_run(int nx, int ny, double lx, double ly, const double *prm, double dt,
              const double *b, const double *c, long mass_every, double *mass_log)
 {
     size_t n = (size_t)nx * ny;
-    double *un = malloc(n * sizeof(double));
-    double *vn = malloc(n * sizeof(double));
-    double *wn = malloc(n * sizeof(double));
+    /* two levels: the caller's arrays and one more; the levels alternate and
+     * the last one is copied back into the caller's arrays */
+    double *lev[2][3] = {{u, v, w}, {malloc(n * sizeof(double)), malloc(n * sizeof(double)),
+                                     malloc(n * sizeof(double))}};
+    step_work ws = {0};
     double dg[11];
     long logged = 0;
-    for (long s = 0; s < nsteps; ++s) {
-        orc_step(nx, ny, lx, ly, prm, dt, u, v, w, a, b, c, un, vn, wn, NULL, NULL, NULL);
-        memcpy(u, un, n * sizeof(double));
-        memcpy(v, vn, n * sizeof(double));
-        memcpy(w, wn, n * sizeof(double));
+    int cur = 0;
+    int ok = lev[1][0] && lev[1][1] && lev[1][2] && work_alloc(&ws, nx, ny);
+    for (long s = 0; ok && s < nsteps; ++s) {
+        double **x = lev[cur], **y = lev[1 - cur];
+        step_work_run(nx, ny, lx, ly, prm, dt, x[0], x[1], x[2], a, b, c, y[0], y[1], y[2], NULL, NULL, NULL,
+                      &ws);
+        cur = 1 - cur;
         if (mass_every > 0 && mass_log && (s + 1) % mass_every == 0) {
-            orc_diag(nx, ny, lx, ly, u, v, w, a, b, c, prm[2], dt, dg);
+            orc_diag(nx, ny, lx, ly, y[0], y[1], y[2], a, b, c, prm[2], dt, dg);
             mass_log[3 * logged + 0] = dg[0];
             mass_log[3 * logged + 1] = dg[1];
             mass_log[3 * logged + 2] = dg[2];
             ++logged;
         }
     }
-    free(un);
-    free(vn);
-    free(wn);
+    work_free(&ws);
+    if (cur == 1)
+        for (int q = 0; q < 3; ++q) memcpy(lev[0][q], lev[1][q], n * sizeof(double));
+    for (int q = 0; q < 3; ++q) free(lev[1][q]);
 }

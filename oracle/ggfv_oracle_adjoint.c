@@ -175,3 +175,61 @@ void orc_adjoint_run(int nx, int ny, double lx, double ly, const double *prm, do
     free(t);
     free(X);
 }
+
+/* The same reverse sweep with the states stored only every `every` steps
+ * (checkpoints x^0, x^every, x^2every, ...): each segment is recomputed from
+ * its checkpoint before its adjoint steps run.  The forward step is
+ * deterministic, so the recomputed states, and hence every result, are those
+ * of orc_adjoint_run; memory is about nsteps/every + every states. */
+void orc_run(int nx, int ny, double lx, double ly, const double *prm, double dt,
+             long nsteps, double *u, double *v, double *w, const double *a,
+             const double *b, const double *c, long mass_every, double *mass_log);
+
+void orc_adjoint_run_ckpt(int nx, int ny, double lx, double ly, const double *prm, double dt,
+                          long nsteps, long every, const double *u0, const double *v0,
+                          const double *w0, const double *a, const double *b, const double *c,
+                          double *lamu, double *lamv, double *lamw, double *ga, double *gb,
+                          double *gc, double *gp)
+{
+    size_t n = (size_t)nx * ny;
+    long nck = (nsteps + every - 1) / every;
+    double *C = malloc((size_t)nck * 3 * n * sizeof(double));
+    double *S = malloc((size_t)every * 3 * n * sizeof(double));
+    double *t = malloc(3 * n * sizeof(double));
+    if (!C || !S || !t) {
+        free(C);
+        free(S);
+        free(t);
+        return;
+    }
+    /* forward: checkpoint k holds x^(k*every) */
+    memcpy(C, u0, n * sizeof(double));
+    memcpy(C + n, v0, n * sizeof(double));
+    memcpy(C + 2 * n, w0, n * sizeof(double));
+    for (long k = 1; k < nck; ++k) {
+        double *x = C + (size_t)k * 3 * n;
+        memcpy(x, x - 3 * n, 3 * n * sizeof(double));
+        orc_run(nx, ny, lx, ly, prm, dt, every, x, x + n, x + 2 * n, a, b, c, 0, NULL);
+    }
+    for (long k = nck - 1; k >= 0; --k) {
+        long s0 = k * every, len = nsteps - s0 < every ? nsteps - s0 : every;
+        /* S holds x^(s0), ..., x^(s0+len-1) */
+        memcpy(S, C + (size_t)k * 3 * n, 3 * n * sizeof(double));
+        for (long q = 1; q < len; ++q) {
+            double *x = S + (size_t)(q - 1) * 3 * n, *y = S + (size_t)q * 3 * n;
+            orc_step(nx, ny, lx, ly, prm, dt, x, x + n, x + 2 * n, a, b, c, y, y + n, y + 2 * n,
+                     NULL, NULL, NULL);
+        }
+        for (long q = len - 1; q >= 0; --q) {
+            double *x = S + (size_t)q * 3 * n;
+            orc_adjoint_step(nx, ny, lx, ly, prm, dt, x, x + n, x + 2 * n, a, b, c, lamu, lamv,
+                             lamw, t, t + n, t + 2 * n, ga, gb, gc, gp);
+            memcpy(lamu, t, n * sizeof(double));
+            memcpy(lamv, t + n, n * sizeof(double));
+            memcpy(lamw, t + 2 * n, n * sizeof(double));
+        }
+    }
+    free(t);
+    free(S);
+    free(C);
+}

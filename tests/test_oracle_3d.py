@@ -165,3 +165,23 @@ def test_3d_step_bound_covers_the_largest_eigenvalue(orc=oracle):
     lmax = float(np.max(np.linalg.eigvalsh(M)))
     dt = orc.stable_dt3(A, 0.01, 1.0, lx, ly, lz)
     assert dt <= 1.0 / (2.0 * lmax * q)
+
+
+def test_3d_mass_closed_forms(orc=oracle):
+    """Masses on a box that is neither a cube nor unit-sized, with a different
+    number of cells along each axis, against the integrals they approximate.
+    A constant c has mass c * lx * ly * lz; the midpoint rule is exact for
+    linear fields, so x, y and z at the cell centres have masses
+    lx^2/2 * ly * lz, ly^2/2 * lx * lz and lz^2/2 * lx * ly.  A cell volume
+    that dropped a factor or took the wrong axis's cell count fails one of
+    them."""
+    nx, ny, nz, lx, ly, lz = 11, 6, 9, 1.7, 0.6, 2.3
+    shape = (nz, ny, nx)
+    one = np.ones(shape)
+    m = orc.mass3(0.8 * one, 1.5 * one, 0.25 * one, lx, ly, lz)
+    vol = lx * ly * lz
+    assert np.allclose(m, [0.8 * vol, 1.5 * vol, 0.25 * vol], rtol=1e-13, atol=0.0)
+    z, y, x = np.meshgrid(centres(nz, lz), centres(ny, ly), centres(nx, lx), indexing="ij")
+    m = orc.mass3(x, y, z, lx, ly, lz)
+    want = [lx * lx / 2 * ly * lz, ly * ly / 2 * lx * lz, lz * lz / 2 * lx * ly]
+    assert np.allclose(m, want, rtol=1e-13, atol=0.0)

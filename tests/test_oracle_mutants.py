@@ -98,6 +98,10 @@ MUTANTS_3D = [
     ("3D idz on the z divergence dropped", "+ (FZ[c] - fb) * idz;", "+ (FZ[c] - fb);", 1),
     ("3D bound without the off-diagonals", "double r0 = fabs(axx[c]) + fabs(axy[c]) + fabs(axz[c]);",
      "double r0 = fabs(axx[c]);", 1),
+    ("3D mass without the z cell height", "double vol = (lx / nx) * (ly / ny) * (lz / nz);",
+     "double vol = (lx / nx) * (ly / ny);", 1),
+    ("3D mass with the x cell count on z", "double vol = (lx / nx) * (ly / ny) * (lz / nz);",
+     "double vol = (lx / nx) * (ly / ny) * (lz / nx);", 1),
 ]
 
 PINS_3D = [
@@ -109,6 +113,7 @@ PINS_3D = [
     lambda o: o3.test_3d_operator_symmetry_and_null_space(o),
     lambda o: o3.test_3d_relabelled_axes(o),
     lambda o: o3.test_3d_step_bound_covers_the_largest_eigenvalue(o),
+    lambda o: o3.test_3d_mass_closed_forms(o),
 ]
 
 ADJ_PINS = [
