@@ -37,6 +37,8 @@ BYTES_PER_CELL = {"f64": 72, "f32c": 60, "f32": 36}
 # launch, lane-shift kernels: 1, or 2 for wide lanes).  Rows 0 is the library's
 # height, the tallest strips whose waves fill the resident slots once.
 HEADLINE_SHAPE = {"f64": (0, 64, 4, 2), "f32c": (0, 64, 4, 1), "f32": (0, 64, 4, 2)}
+# The single-step kernel (one step per launch, the library's width and height).
+SINGLE_SHAPE = (0, 0, 1, 0)
 METRIC = "Gcell-updates/s + % HBM peak, 4096² aniso FV step FP32/FP64; adjoint/fwd ratio"
 # Algorithmic floating-point operations per cell-update (each face flux counted
 # once, shared by its two cells): x/y faces of W 2 x 10, tangential differences
@@ -62,9 +64,6 @@ def kernel_name(variant, tuning):
         return f"fused_dpp_kernel<{T}, {comp}, {2 * cpl}, {K}>", f"wide{K}"
     if tuning.get("lane_shift"):
         return f"fused_dpp_kernel<{T}, {comp}, {cpl}, {K}>", f"lanes{K}"
-    if K > 1:
-        nt = 64 if (tuning.get("threads") == 64 or K == 4) else 128
-        return f"fused_kernel<{T}, {comp}, {cpl}, {nt}, {K}>", f"fused{K}"
     nt = tuning.get("threads") or 256
     return f"step_kernel<{T}, {comp}, {cpl}, {nt}>", "single"
 
@@ -138,21 +137,13 @@ def measured_traffic3(dtype, shape):
     return t["read"] + t["write"]
 
 
-# The resource that bounds each precision's fused kernel at K = 4, from the
-# launch time at K = 2, 3, 4 (4096^2, one box): FP64 266 / 259 / 268 us and
-# compensated FP32 249 / 248 / 241 us, flat while the arithmetic doubles, so
-# HBM per launch; plain FP32 143 / 143 / 158 us, flat until K = 4, where its
-# vector issue (95% of the rate) takes over.
-FUSED_BOUND = {"f64": "hbm", "f32c": "hbm", "f32": "alu"}
-
-
 def roofline_of(variant, r):
-    """Roofline of the kernel that dominates a timed run.  A single-step launch
-    moves BYTES_PER_CELL bytes per cell and is bound by HBM.  A fused launch
-    moves the same bytes once for its K steps; it is placed against HBM
-    (algorithmic bytes over the launch time) or against the non-FMA vector rate
-    (FLOPS_PER_CELL per cell-update), as FUSED_BOUND says, with the other
-    figures beside it."""
+    """Roofline of the kernel that dominates a timed run, against HBM: the
+    algorithmic bytes of one launch (BYTES_PER_CELL per cell; a fused launch
+    moves them once for its K steps) over the average launch time.  A fused
+    launch also carries its vector figures: FLOPS_PER_CELL per cell-update
+    against the non-FMA vector rate, and the measured VALU issue utilisation
+    (counter summary) where it is known."""
     kname, _ = kernel_name(variant, r["tuning"])
     traffic = measured_traffic(variant, r["tuning"], r["rows"])
     hbm = {"achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -162,16 +153,36 @@ def roofline_of(variant, r):
     if r["fused_steps"] > 1 or r["tuning"].get("lane_shift"):
         out.update({"steps_per_launch": r["fused_steps"],
                     "hbm_algorithmic_bytes_per_launch": BYTES_PER_CELL[variant] * r["cells"],
-                    "hbm_algorithmic_GBs": r["achieved_GBs"], "hbm_frac": hbm["frac"],
                     "hbm_effective_GBs": r["effective_GBs"],
                     "hbm_frac_effective": r["effective_GBs"] / PEAK_HBM_GBS,
                     "flops_per_cell_update": FLOPS_PER_CELL,
                     "valu_TFLOPs": r["achieved_TFLOPs"], "valu_peak_TFLOPs": PEAK_VALU_TFLOPS,
                     "valu_frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS})
-        if FUSED_BOUND[variant] == "alu":
-            out.update({"bound": "alu", "achieved": r["achieved_TFLOPs"], "peak": PEAK_VALU_TFLOPS,
-                        "unit": "TFLOP/s", "frac": r["achieved_TFLOPs"] / PEAK_VALU_TFLOPS})
+        issue = measured_valu(variant, r["tuning"], r["rows"])
+        if issue is not None:
+            out["valu_issue_frac"] = issue / (VALU_ISSUE_PER_S * r["kernel_avg_us"] * 1e-6)
     return with_measured(out, r["kernel_avg_us"])
+
+
+def measured_valu(variant, tuning, rows):
+    """VALU wave instructions per launch from the committed counter summary, or
+    None (no summary for this kernel and strip height, or a kernel source
+    changed since the counters were taken)."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "step_kernel_valu.json")) as f:
+            data = json.load(f)
+        if data["kernel_sources"] != traffic_sources(here):
+            return None
+        if sources_digest(here, data["kernel_sources"]) != data.get("kernel_sources_sha256"):
+            return None
+    except (OSError, KeyError, ValueError):
+        return None
+    _, key = kernel_name(variant, tuning)
+    t = data["valu_per_launch"].get(f"{variant}/{key}")
+    if t is None or t.get("rows") != rows:
+        return None
+    return t["valu"]
 
 
 def with_measured(roof, kernel_us):
@@ -188,20 +199,23 @@ def log(msg):
 
 
 def time_variant(pk, torch, w, dtype, steps, warmup, tune, force=None):
-    """Time `steps` steps (after `warmup`) of the workload with the default
-    single-step shape, or with the shape the autotuner picks (tune=True: the
-    search runs before the timed region, on the same data, and restores it)."""
+    """Time `steps` steps (after `warmup`) of the workload in the launch shape
+    `force`, on the single-step kernel (tune=False, no shape given), or with the
+    shape the autotuner picks (tune=True: the search runs before the timed
+    region, on the same data, and restores it)."""
     stream = torch.cuda.current_stream()
     ctx = pk.Context(w.nx, w.ny, w.lx, w.ly, dtype=dtype, stream=stream.cuda_stream)
     ctx.set_params(w.params)
     ctx.set_tensor_eig(*w.eig)
     ctx.set_state(w.u0, w.v0, w.w0)
     dt = ctx.stable_dt(w.safety)
+    if force is None and not tune:
+        force = SINGLE_SHAPE
     if force is not None:
         ctx.set_tuning(*force)
         tuning = ctx.get_tuning()
     else:
-        tuning = ctx.autotune(dt, trial_steps=12) if tune else ctx.get_tuning()
+        tuning = ctx.autotune(dt, trial_steps=12)
     rows = tuning["rows_per_strip"]          # 0: the library's default strip height
     K = max(1, tuning["fused_steps"])
     ctx.step(dt, warmup)
@@ -285,7 +299,9 @@ def time_host_inclusive(pk, torch, w, dtype, steps, tuning, dt):
 def time_adjoint(pk, torch, steps=5000):
     """Gradient workload: 512^2 smooth anisotropic tensor, `steps` steps, loss of
     the final v and w; forward with square-root checkpoints, then the native
-    reverse sweep (recompute + adjoint).  Returns times and their ratio."""
+    reverse sweep (recompute + adjoint).  The forward runs twice, in the
+    library's default shape (four steps per launch) and on the single-step
+    kernel; the backward is the same either way.  Returns times and ratios."""
     from paper_2006_01748_amd import autograd as ag
     from paper_2006_01748_amd import workloads as wl
     w = wl.cfg4(steps=steps)
@@ -294,6 +310,7 @@ def time_adjoint(pk, torch, steps=5000):
     ctx.set_params(w.params)
     ctx.set_tensor_eig(*w.eig)
     dt = ctx.stable_dt(w.safety)
+    default_shape = ctx.get_tuning()
     every = ag.default_every(w.steps)
     sb = ctx.state_bytes()
     ckpt = torch.empty(-(-w.steps // every) * sb, dtype=torch.uint8, device="cuda")
@@ -301,20 +318,25 @@ def time_adjoint(pk, torch, steps=5000):
     lam = [torch.zeros((w.ny, w.nx), dtype=torch.float64, device="cuda") for _ in range(3)]
     g = [torch.empty((w.ny, w.nx), dtype=torch.float64, device="cuda") for _ in range(3)]
     res = {}
-    for rep in range(2):                    # first pass warms up
-        ctx.set_state(w.u0, w.v0, w.w0)
-        torch.cuda.synchronize()
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        e0.record(stream)
-        ctx.step_checkpointed(dt, w.steps, every, ckpt)
-        e1.record(stream)
-        for x in lam:
-            x.fill_(1e-6)
-        ctx.adjoint_run(dt, w.steps, every, ckpt, work, lam, g)
-        e2.record(stream)
-        torch.cuda.synchronize()
-        res = {"forward_ms": e0.elapsed_time(e1), "backward_ms": e1.elapsed_time(e2)}
-    # per-launch kernel times: plain steps vs adjoint steps
+    for label, shape in (("fused", None), ("single_step", SINGLE_SHAPE)):
+        if shape is None:
+            ctx.set_tuning(*(default_shape[k] for k in ("rows_per_strip", "threads", "fused_steps", "lane_shift")))
+        else:
+            ctx.set_tuning(*shape)
+        for rep in range(2):                    # first pass warms up
+            ctx.set_state(w.u0, w.v0, w.w0)
+            torch.cuda.synchronize()
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            ctx.step_checkpointed(dt, w.steps, every, ckpt)
+            e1.record(stream)
+            for x in lam:
+                x.fill_(1e-6)
+            ctx.adjoint_run(dt, w.steps, every, ckpt, work, lam, g)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            res[label] = {"forward_ms": e0.elapsed_time(e1), "backward_ms": e1.elapsed_time(e2)}
+    # per-launch time of the single-step kernel (the backward's recomputation)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ctx.set_state(w.u0, w.v0, w.w0)
     torch.cuda.synchronize()
@@ -324,13 +346,16 @@ def time_adjoint(pk, torch, steps=5000):
     torch.cuda.synchronize()
     fwd_us = 1e3 * e0.elapsed_time(e1) / 1000
     ctx.close()
-    ratio = res["backward_ms"] / res["forward_ms"]
+    bwd = res["fused"]["backward_ms"]
     return {"workload": f"{w.nx}x{w.ny} smooth anisotropic tensor, {w.steps} steps, checkpoint every "
                         f"{every} steps (forward stores {-(-w.steps // every)} states, backward recomputes "
                         f"each segment and runs the adjoint through it)",
-            "dtype": "f64", "forward_ms": res["forward_ms"], "backward_ms": res["backward_ms"],
-            "backward_over_forward": ratio, "step_us": fwd_us,
-            "adjoint_step_us_est": 1e3 * res["backward_ms"] / w.steps - fwd_us}
+            "dtype": "f64", "forward_shape": default_shape,
+            "forward_ms": res["fused"]["forward_ms"], "backward_ms": bwd,
+            "backward_over_forward": bwd / res["fused"]["forward_ms"],
+            "forward_single_step_ms": res["single_step"]["forward_ms"],
+            "backward_over_forward_single_step": res["single_step"]["backward_ms"] / res["single_step"]["forward_ms"],
+            "step_us": fwd_us, "adjoint_step_us_est": 1e3 * bwd / w.steps - fwd_us}
 
 
 def time_adaptive(pk, torch, w, steps=200):
@@ -466,10 +491,13 @@ def time_3d(pk, torch, n=256, steps=100, warmup=10, dtypes=("f64", "f32"), trial
     return out
 
 
-def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50, force=None):
+def time_ensemble(pk, torch, count=256, steps=500, loop_steps=48, force=None):
     """Ensemble workload: `count` instances (sides 64..512, own parameters, tensor
-    and dt), compensated FP32.  Batched graph-replayed run versus a loop of
-    single-instance launches of the same instances on the same GPU."""
+    and dt), compensated FP32.  A batched graph-replayed run versus loops of
+    single-instance launches of the same instances on the same GPU: one in the
+    batch's own launch shape (same kernel family, steps per launch and strip
+    height: the gain from batching alone) and one in each context's default
+    shape."""
     from paper_2006_01748_amd import workloads as wl
     ws = wl.cfg3(count, steps)
     # graph capture needs a stream other than the null stream: time on our own
@@ -488,8 +516,8 @@ def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50, force=None):
         tuned = b.autotune(trial_steps=12)
     else:
         tuned = {"threads": force[0], "rows_per_strip": force[1], "fused_steps": force[2] if len(force) > 2 else 1}
-    b.set_tuning(threads=tuned["threads"], rows_per_strip=tuned["rows_per_strip"], graph_steps=48,
-                 fused_steps=tuned["fused_steps"])
+    K = tuned["fused_steps"]
+    b.set_tuning(threads=tuned["threads"], rows_per_strip=tuned["rows_per_strip"], graph_steps=48, fused_steps=K)
     b.run(48)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -499,32 +527,52 @@ def time_ensemble(pk, torch, count=256, steps=500, loop_steps=50, force=None):
     torch.cuda.synchronize()
     batch_ms = e0.elapsed_time(e1)
     b.close()
-    ctxs = []
-    for i, w in enumerate(ws):
-        c = pk.Context(w.nx, w.ny, dtype="f32c", stream=stream.cuda_stream)
-        c.set_params(w.params)
-        c.set_tensor_eig(*w.eig)
-        c.set_state(w.u0, w.v0, w.w0)
-        ctxs.append(c)
-    for c, dt in zip(ctxs, dts):
-        c.step(dt, 5)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for c, dt in zip(ctxs, dts):
-        c.step(dt, loop_steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    loop_ms = e0.elapsed_time(e1)
-    for c in ctxs:
-        c.close()
+    launches = steps // K + steps % K
+
+    def loop(shape):
+        ctxs = []
+        for w in ws:
+            c = pk.Context(w.nx, w.ny, dtype="f32c", stream=stream.cuda_stream)
+            c.set_params(w.params)
+            c.set_tensor_eig(*w.eig)
+            c.set_state(w.u0, w.v0, w.w0)
+            if shape is not None:
+                c.set_tuning(*shape)
+            ctxs.append(c)
+        for c, dt in zip(ctxs, dts):
+            c.step(dt, 2 * K)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for c, dt in zip(ctxs, dts):
+            c.step(dt, loop_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        for c in ctxs:
+            c.close()
+        return cells * loop_steps / (ms * 1e-3) / 1e9, ms / loop_steps
+
+    same = (tuned["rows_per_strip"], 0, K, 1) if K > 1 else (tuned["rows_per_strip"], tuned["threads"], 1, 0)
+    loop_rate, loop_ms = loop(same)
+    default_rate, default_ms = loop(None)
     batch_rate = cells * steps / (batch_ms * 1e-3) / 1e9
-    loop_rate = cells * loop_steps / (loop_ms * 1e-3) / 1e9
+    launch_us = 1e3 * batch_ms / launches
+    alg = BYTES_PER_CELL["f32c"] * cells
+    kname = (f"fused_dpp_batch_kernel<float, true, 2, {K}>" if K > 1
+             else f"step_batch_kernel<float, true, 2, {tuned['threads']}>")
     return {"workload": f"{count} instances, sides 64..512 (total {cells} cells), own parameters, tensor and dt, "
                         f"compensated FP32", "dtype": "f32c", "tuning": tuned,
             "batched_Gcell_s": batch_rate, "batched_ms_per_step": batch_ms / steps,
-            "loop_of_single_launches_Gcell_s": loop_rate, "loop_ms_per_step": loop_ms / loop_steps,
-            "speedup": batch_rate / loop_rate,
-            "batched_GBs": 60 * cells * steps / (batch_ms * 1e-3) / 1e9}
+            "loop_same_shape_Gcell_s": loop_rate, "loop_same_shape_ms_per_step": loop_ms,
+            "loop_same_shape": dict(zip(("rows_per_strip", "threads", "fused_steps", "lane_shift"), same)),
+            "loop_default_shape_Gcell_s": default_rate, "loop_default_shape_ms_per_step": default_ms,
+            "speedup": batch_rate / loop_rate, "speedup_vs_default_shape_loop": batch_rate / default_rate,
+            "roofline": {"bound": "hbm", "kernel": kname, "achieved": alg / (launch_us * 1e-6) / 1e9,
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": alg / (launch_us * 1e-6) / 1e9 / PEAK_HBM_GBS, "traffic": None,
+                         "launch_avg_us": launch_us, "steps_per_launch": K,
+                         "note": "algorithmic bytes of one launch (60 B per cell of all instances) over the "
+                                 "graph-replayed run's time per launch, gaps between launches included"}}
 
 
 def copy_ceiling(torch, nbytes=1 << 30, reps=20):
@@ -545,17 +593,51 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(w, steps):
+def host_identity():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(w, steps, single_steps):
+    """The FP64 oracle on the host cores: all threads it is allowed (OpenMP over
+    rows, the same bits as one thread) on `steps` steps, and one thread on
+    `single_steps` steps, of the same grid."""
     import oracle
     a, b, c = oracle.tensor_from_eig(*w.eig)
     dt = oracle.stable_dt(a, b, c, w.params[2], w.safety)
-    t0 = time.perf_counter()
-    oracle.run(w.u0, w.v0, w.w0, a, b, c, w.params, dt, steps)
-    sec = time.perf_counter() - t0
-    return {"value": w.nx * w.ny * steps / sec / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+    threads = oracle.set_threads()
+
+    def timed(n):
+        t0 = time.perf_counter()
+        oracle.run(w.u0, w.v0, w.w0, a, b, c, w.params, dt, n)
+        return time.perf_counter() - t0
+
+    sec = timed(steps)
+    oracle.set_threads(1)
+    sec1 = timed(single_steps)
+    oracle.set_threads(threads)
+    cells = w.nx * w.ny
+    return {"value": cells * steps / sec / 1e9, "unit": "Gcell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} FP64 steps of the same {w.nx}x{w.ny} layered-tissue grid, one thread "
-                      f"({sec:.1f} s)"}
+            "sample": f"{steps} FP64 steps of the same {w.nx}x{w.ny} layered-tissue grid on {threads} host "
+                      f"threads ({sec:.1f} s)",
+            "single_thread": {"value": cells * single_steps / sec1 / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+                              "sample": f"{single_steps} FP64 steps, one thread ({sec1:.1f} s)"},
+            "host": host_identity()}
 
 
 # The rocprofv3 runs behind the committed summaries under profiles/.  Run from
@@ -899,7 +981,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=52)
     ap.add_argument("--n", type=int, default=4096, help="grid side (4096 for the standard workload)")
     ap.add_argument("--variants", default="f64,f32c,f32")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=200, help="oracle steps on all host threads")
+    ap.add_argument("--cpu-steps-single", type=int, default=40, help="oracle steps on one host thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--no-host-inclusive", action="store_true",
@@ -979,7 +1062,8 @@ def main():
     if not args.no_adjoint:
         log("timing the gradient workload (forward with checkpoints, reverse sweep)")
         adj = time_adjoint(pk, torch)
-        log(f"  backward/forward = {adj['backward_over_forward']:.2f}")
+        log(f"  backward/forward = {adj['backward_over_forward']:.2f} (fused forward), "
+            f"{adj['backward_over_forward_single_step']:.2f} (single-step forward)")
     adaptive = None
     if not args.no_adaptive and "f64" in variants:
         log("timing adaptive stepping (device-side step size, FP64)")
@@ -1005,13 +1089,16 @@ def main():
         log("timing the ensemble (batched graph vs loop of single launches)")
         ens = time_ensemble(pk, torch, force=tuple(int(x) for x in args.ensemble_tuning.split(","))
                             if args.ensemble_tuning else None)
-        log(f"  batched {ens['batched_Gcell_s']:.1f} Gcell/s vs loop {ens['loop_of_single_launches_Gcell_s']:.1f} "
-            f"Gcell/s (x{ens['speedup']:.2f})")
+        log(f"  batched {ens['batched_Gcell_s']:.1f} Gcell/s vs loop {ens['loop_same_shape_Gcell_s']:.1f} "
+            f"Gcell/s in the same shape (x{ens['speedup']:.2f}), {ens['loop_default_shape_Gcell_s']:.1f} in the "
+            f"default shape")
     ceiling = None if args.no_copy_ceiling else copy_ceiling(torch)
     base = None
     if not args.no_cpu_baseline:
-        log(f"timing the oracle on {args.cpu_steps} steps")
-        base = cpu_baseline(w, args.cpu_steps)
+        log(f"timing the oracle: {args.cpu_steps} steps on all host threads, {args.cpu_steps_single} on one")
+        base = cpu_baseline(w, args.cpu_steps, args.cpu_steps_single)
+        log(f"  {base['value']:.3f} Gcell/s on {base['cores']} threads, "
+            f"{base['single_thread']['value']:.4f} on one ({base['host']['cpu_model']})")
 
     head = variants[0]
     r = res[head]

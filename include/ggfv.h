@@ -268,20 +268,23 @@ int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const v
 /* Launch shape of the step.  rows_per_strip is the number of grid rows one
  * workgroup sweeps (0 = chosen from the grid size; for the lane-shift kernels,
  * the tallest strips whose workgroups fill the device's resident slots once,
- * from the kernel's occupancy and the number of compute units).  threads is the workgroup
- * width, 64, 128 or 256 (0 = chosen from the grid size); fused launches use 64
- * or 128 (256 acts as 128, and depth 4 always uses 64).  fused_steps (1..4, 0 =
- * 1) is the number of time steps computed per launch: the old state is read
- * from HBM once, the intermediate levels stay on chip, and only the last level
- * is written, so HBM traffic per step falls by that factor; a run of n steps
- * uses n / fused_steps fused launches and single steps for the remainder.
+ * from the kernel's occupancy and the number of compute units).
+ * lane_shift = 0 selects the single-step kernel (one step per launch, threads
+ * = its workgroup width, 64, 128 or 256, 0 = chosen from the grid size).
  * lane_shift = 1 selects the one-wave kernels that keep the rows of every time
  * level in registers and exchange x-neighbours by lane shifts (threads is then
- * ignored; fused_steps 1..4 applies); lane_shift = 2 the same kernels with
- * wide lanes, 16 bytes of columns per lane (two FP64 or four FP32 columns:
- * half the lane shifts and halo columns per cell, twice the registers; not for
- * GGFV_F32C).  Every shape gives the same results bit for bit.  EINVAL for
- * values outside these sets. */
+ * ignored); lane_shift = 2 the same kernels with wide lanes, 16 bytes of
+ * columns per lane (two FP64 or four FP32 columns: half the lane shifts and
+ * halo columns per cell, twice the registers; not for GGFV_F32C).
+ * fused_steps (1..4, 0 = 1; above 1 only with lane_shift 1 or 2) is the number
+ * of time steps computed per launch: the old state is read from HBM once, the
+ * intermediate levels stay on chip, and only the last level is written, so HBM
+ * traffic per step falls by that factor; a run of n steps uses n / fused_steps
+ * fused launches and single steps for the remainder.
+ * A new context starts with the fastest shape measured on MI355X for large
+ * grids: rows_per_strip 0, fused_steps 4, lane_shift 2 (1 for GGFV_F32C).
+ * Every shape gives the same results bit for bit.  EINVAL for values outside
+ * these sets. */
 typedef struct {
     int rows_per_strip;
     int threads;
@@ -292,10 +295,11 @@ typedef struct {
 int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tuning);
 int ggfv_get_tuning(const ggfv_ctx *ctx, ggfv_tuning *tuning);
 
-/* Time `trial_steps` steps for each candidate shape (fused depths 1..4, widths
- * 64, 128, 256 and the lane-shift kernels, strip heights 2, 4, 8, 16, 24, 32,
- * 48, 64, 128, the default, and for the lane-shift kernels the heights that
- * fill the resident slots half a round, 1.5 and 2 rounds over) on the
+/* Time `trial_steps` steps for each candidate shape (the single-step kernel at
+ * widths 64, 128, 256; the lane-shift kernels, narrow and wide, at fused depths
+ * 1..4; strip heights 2, 4, 8, 16, 24, 32, 48, 64, 128, the default, and for
+ * the lane-shift kernels the heights that fill the resident slots half a
+ * round, 1.5 and 2 rounds over) on the
  * context's own data, keep the fastest per step as the context's tuning and
  * return it (with the height it ran).  The state, simulated time and step count are restored
  * afterwards.  Needs state, tensor and parameters.  Synchronizes. */
@@ -316,7 +320,9 @@ typedef struct ggfv_batch ggfv_batch;
 
 /* n instances, instance i an nx[i]-by-ny[i] grid on [0,lx] x [0,ly].  With
  * hip_stream NULL the batch creates its own (default-priority) stream, because
- * graph capture needs a stream other than the null stream.  EINVAL on bad sizes
+ * graph capture needs a stream other than the null stream; that stream is a
+ * blocking one, so its work is ordered with work on the null stream both ways
+ * (device arrays written or read there need no extra synchronization).  EINVAL on bad sizes
  * or dtype; ENOMEM / EHIP as ggfv_create.  On failure *out is NULL and
  * ggfv_batch_last_error(NULL) reports why. */
 int ggfv_batch_create(ggfv_batch **out, int n, const int *nx, const int *ny, double lx, double ly,

@@ -211,6 +211,10 @@ int ggfv_create(ggfv_ctx **out, int nx, int ny, double lx, double ly, int dtype,
     ctx->plane = (size_t)ctx->pitch * ny;
     ctx->elem = (dtype == GGFV_F64) ? 8 : 4;
     ctx->nfields = (dtype == GGFV_F32C) ? 6 : 3;
+    // default launch shape: the lane-shift kernels with four steps per launch,
+    // wide lanes except for the compensated state, one-round strip heights
+    ctx->fused_steps = 4;
+    ctx->lane_shift = (dtype == GGFV_F32C) ? 1 : 2;
 
     DeviceGuard g(device);
     if (g.status != hipSuccess) {
@@ -626,6 +630,8 @@ int ggfv_set_tuning(ggfv_ctx *ctx, const ggfv_tuning *tn)
         return fail(ctx, GGFV_EINVAL, "lane_shift must be 0, 1 or 2 (got %d)", tn->lane_shift);
     if (tn->lane_shift == 2 && ctx->dtype == GGFV_F32C)
         return fail(ctx, GGFV_EINVAL, "wide lanes (lane_shift 2) are for FP64 and plain FP32 contexts");
+    if (tn->fused_steps > 1 && tn->lane_shift == 0)
+        return fail(ctx, GGFV_EINVAL, "fused_steps > 1 needs the lane-shift kernels (lane_shift 1 or 2)");
     ctx->rows_per_strip = tn->rows_per_strip;
     ctx->threads = tn->threads;
     ctx->fused_steps = tn->fused_steps < 1 ? 1 : tn->fused_steps;
@@ -683,8 +689,7 @@ int ggfv_autotune(ggfv_ctx *ctx, double dt, int trial_steps, ggfv_tuning *best)
             for (int h : heights) {
                 const bool lanes = wdt <= 0;
                 if (wdt < 0 && ctx->dtype == GGFV_F32C) continue;
-                if (!lanes && K > 1 && wdt == 256) continue;   // fused LDS widths are 64 and 128
-                if (!lanes && K == 4 && wdt != 64) continue;
+                if (!lanes && K > 1) continue;                  // several steps per launch: lane-shift kernels
                 if (h < 0) {
                     if (!lanes) continue;
                     ctx->lane_shift = wdt < 0 ? 2 : 1;           // the fit depends on the kernel

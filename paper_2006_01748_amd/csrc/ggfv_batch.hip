@@ -230,7 +230,10 @@ int ggfv_batch_create(ggfv_batch **out, int n, const int *nx, const int *ny, dou
     if (hip_stream) {
         b->stream = static_cast<hipStream_t>(hip_stream);
     } else {
-        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+        // a blocking stream: its work is ordered with the null stream's (the
+        // default stream of most callers) both ways, so device arrays that the
+        // caller wrote or will read there need no extra synchronization
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamDefault) != hipSuccess) {
             delete b;
             if (prev >= 0) (void)hipSetDevice(prev);
             return bfail(nullptr, GGFV_EHIP, "cannot create the batch stream");

@@ -67,9 +67,10 @@ struct ggfv_ctx {
     double last_dt = 0.0;
     int cus = 0;             // compute units of the device
     int rows_per_strip = 0;  // 0: chosen per launch
-    int threads = 0;         // workgroup width of the step kernel: 64, 128, 256, or 0 (by grid size)
-    int fused_steps = 1;     // time steps per launch (1..4)
-    int lane_shift = 0;      // 1: one-wave register/lane-shift kernels (ggfv_fused_dpp.hip); 2: wide lanes
+    int threads = 0;         // workgroup width of the single-step kernel: 64, 128, 256, or 0 (by grid size)
+    int fused_steps = 4;     // time steps per launch (1..4; above 1 only with the lane-shift kernels)
+    int lane_shift = 2;      // 0: single-step kernel; 1: one-wave register/lane-shift kernels
+                             // (ggfv_fused_dpp.hpp); 2: the same with wide lanes (set per dtype at create)
     ggfv::AdaptCtl *adapt = nullptr;   // adaptive-step control block (lazily allocated)
     double *front = nullptr;           // front diagnostics: 4 * ny per-row values + 16 results (lazily)
 
@@ -94,8 +95,6 @@ struct StatePlanes {
 hipError_t launch_step(ggfv_ctx *ctx, double dt);
 // One step from the stored state at `in` (nfields planes) to `out`.
 hipError_t launch_step_planes(ggfv_ctx *ctx, const void *in, void *out, double dt);
-// K (2..4) steps fused into one launch, from `in` to `out` (ggfv_fused.hip).
-hipError_t launch_step_fused(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);
 // K (1..4) steps per launch with rows in registers and lane shifts (ggfv_fused_dpp.hpp;
 // FP32 in ggfv_fused_dpp.hip, FP64 in ggfv_fused_dpp_f64.hip).
 hipError_t launch_step_fused_dpp(ggfv_ctx *ctx, const void *in, void *out, double dt, int K);

@@ -481,12 +481,6 @@ hipError_t advance_steps(ggfv_ctx *ctx, double dt, long long n)
         }
         return e;
     }
-    if (K > 1) {
-        for (; n >= K && e == hipSuccess; n -= K) {
-            e = launch_step_fused(ctx, ctx->state[ctx->cur], ctx->state[1 - ctx->cur], dt, K);
-            ctx->cur ^= 1;
-        }
-    }
     for (; n > 0 && e == hipSuccess; --n) {
         e = launch_step(ctx, dt);
         ctx->cur ^= 1;

@@ -110,30 +110,62 @@ def test_fused_batch_graph_replays_and_split_runs():
     b2.close()
 
 
-@pytest.mark.parametrize("fused", [1, 4])
-def test_full_ensemble_against_oracle_sampled(fused):
-    """256 instances (sides 64..512), compensated FP32, 5000 steps in one batched
-    run (one or four steps per launch); the 8 smallest instances are recomputed
-    by the FP64 oracle on the FP32-rounded inputs."""
+def _oracle_sample(ws):
+    """Sixteen instances of the ensemble for the oracle: the first instance of
+    every side 64, 96, ..., 512 and the second 512^2 one."""
+    first = {}
+    for i, w in enumerate(ws):
+        first.setdefault(w.nx, []).append(i)
+    pick = [first[s][0] for s in sorted(first)]
+    pick.append(first[max(first)][1])
+    return pick
+
+
+@pytest.fixture(scope="module")
+def ensemble_oracle():
+    """The 256-instance ensemble (sides 64..512, 5000 steps) with FP32-rounded
+    inputs and steps from the oracle's own tensor map and step bound, and the
+    FP64 oracle's final states of 16 instances covering every side."""
     ws = wl.cfg3(256, 5000)
-    b, dts = _setup_batch(ws, "f32c")
-    b.set_tuning(threads=64, rows_per_strip=16, graph_steps=48, fused_steps=fused)
-    b.run(5000)
-    order = sorted(range(len(ws)), key=lambda i: ws[i].cells)[:8]
     f32 = lambda x: np.float64(np.float32(x))
-    worst = 0.0
-    for i in order:
-        w = ws[i]
-        eig = tuple(f32(x) for x in w.eig)
-        a, b_, c = (f32(x) for x in oracle.tensor_from_eig(*eig))
+    inputs = []
+    for w in ws:
+        abc = tuple(f32(x) for x in oracle.tensor_from_eig(*(f32(x) for x in w.eig)))
         prm = tuple(float(np.float32(p)) for p in w.params)
         st = tuple(f32(x) for x in (w.u0, w.v0, w.w0))
-        ref = oracle.run(*st, a, b_, c, prm, float(np.float32(dts[i])), w.steps)[:3]
+        dt = float(np.float32(oracle.stable_dt(*abc, prm[2], w.safety)))
+        inputs.append((abc, prm, st, dt))
+    pick = _oracle_sample(ws)
+    assert len(pick) == 16 and len({ws[i].nx for i in pick}) == 15
+    refs = {}
+    for i in pick:
+        abc, prm, st, dt = inputs[i]
+        refs[i] = oracle.run(*st, *abc, prm, dt, ws[i].steps)[:3]
+    return ws, inputs, refs
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("fused", [1, 4])
+def test_full_ensemble_against_oracle_sampled(ensemble_oracle, fused):
+    """256 instances (sides 64..512), compensated FP32, 5000 steps in one batched
+    run (one or four steps per launch, graph replays); 16 instances, one of
+    every side and two of 512^2, against the FP64 oracle on the same FP32
+    inputs (1e-5 relative max-norm per field)."""
+    ws, inputs, refs = ensemble_oracle
+    f32 = lambda x: np.asarray(x, np.float32)
+    b = pk.Batch([(w.nx, w.ny) for w in ws], dtype="f32c")
+    for i, (abc, prm, st, dt) in enumerate(inputs):
+        b.set(i, prm, dt, tuple(f32(x) for x in abc), tuple(f32(x) for x in st))
+    b.set_tuning(threads=64, rows_per_strip=16, graph_steps=48, fused_steps=fused)
+    b.run(5000)
+    worst = 0.0
+    for i, ref in refs.items():
         got = b[i].get_state()
         err = max(float(np.max(np.abs(x - y)) / np.max(np.abs(y))) for x, y in zip(got, ref))
         worst = max(worst, err)
-        assert err <= 1e-5, (i, w.nx, err)
-    print(f"ensemble: worst per-instance max-norm error vs FP64 oracle over 8 instances: {worst:.3e}")
+        assert err <= 1e-5, (i, ws[i].nx, err)
+    print(f"ensemble: worst per-instance max-norm error vs FP64 oracle over {len(refs)} instances "
+          f"(sides {sorted({ws[i].nx for i in refs})}): {worst:.3e}")
     for i in range(len(ws)):
         d = b[i].diagnostics()
         assert d["nonfinite"] == 0 and d["steps"] == 5000
@@ -249,4 +281,37 @@ def test_batch_set_and_get_state_calls(dtype):
     assert e.value.status == pk.GGFV_EINVAL
     with pytest.raises(pk.GGFVError):
         b.get_state(-1)
+    b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32c"])
+def test_batch_device_tensor_io_orders_with_torch(dtype):
+    """Instance state written by torch kernels on torch's stream just before
+    set_state, and read by a torch kernel just after get_state, with no
+    synchronization in between: the batch's own stream is ordered with
+    torch's, so the device-pointer path gives the bits of the host path."""
+    torch = pytest.importorskip("torch")
+    ws = _instances(4, 24, sides=[64, 200, 96, 512])
+    host, _ = _setup_batch(ws, dtype)
+    host.set_tuning(threads=64, graph_steps=8, fused_steps=4)
+    host.run(24)
+    ref = [host[i].get_state() for i in range(len(ws))]
+    host.close()
+    b, _ = _setup_batch(ws, dtype)
+    b.set_tuning(threads=64, graph_steps=8, fused_steps=4)
+    big = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+    for i, w in enumerate(ws):
+        # state produced on the device behind a long torch kernel
+        st = [torch.from_numpy(x).cuda() for x in (w.u0, w.v0, w.w0)]
+        for _ in range(4):
+            big.mul_(1.0)
+        dev = [x * (big[0] * 1.0) for x in st]
+        b[i].set_state(*dev)
+    b.run(24)
+    for i, w in enumerate(ws):
+        out = [torch.full((w.ny, w.nx), float("nan"), dtype=torch.float64, device="cuda") for _ in range(3)]
+        b[i].get_state(out=out)
+        copies = [x.clone() for x in out]          # a torch kernel right behind the library's
+        for x, r in zip(copies, ref[i]):
+            assert np.array_equal(x.cpu().numpy(), r), (i, w.nx)
     b.close()

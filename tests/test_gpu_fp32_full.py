@@ -1,0 +1,56 @@
+"""FP32 storage and arithmetic on the 1024^2 smooth anisotropic workload, 10^4
+steps, in the launch shapes the benchmark times, against the FP64 oracle.
+
+Both sides take the same FP32-rounded inputs: the tensor (the oracle's map of
+the FP32 eigen-fields, rounded to FP32), the initial state, the parameters and
+the step (0.9 of the explicit bound of that tensor, rounded to FP32).  The
+error of a field is ||f_gpu - f_ref||_inf / ||f_ref||_inf.  Bars: the
+compensated state (hi + lo words, error-free sums) 1e-5; plain FP32 5e-4, the
+tolerance stated for it (its per-step logistic increment falls below half an
+ulp of u near 1, so plain storage cannot meet 1e-5).  The oracle run (10^10
+cell-updates) uses every host thread; its results do not depend on them."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_01748_amd as pk
+from paper_2006_01748_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+N, STEPS = 1024, 10000
+SHAPES = {"f32": (0, 0, 4, 2), "f32c": (0, 0, 4, 1)}     # the benchmark's FP32 launch shapes
+
+
+@pytest.fixture(scope="module")
+def case():
+    w = wl.cfg1(n=N, steps=STEPS)
+    r32 = lambda x: np.float64(np.float32(x))
+    abc = tuple(r32(x) for x in oracle.tensor_from_eig(*(r32(x) for x in w.eig)))
+    prm = tuple(float(np.float32(p)) for p in w.params)
+    st = tuple(r32(x) for x in (w.u0, w.v0, w.w0))
+    dt = float(np.float32(oracle.stable_dt(*abc, prm[2], 0.9)))
+    print(f"oracle: {N}x{N}, {STEPS} FP64 steps on {oracle.set_threads()} host threads", flush=True)
+    ref = oracle.run(*st, *abc, prm, dt, STEPS)[:3]
+    return abc, prm, st, dt, ref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype,tol", [("f32c", 1e-5), ("f32", 5e-4)])
+def test_fp32_1024_10000_steps_headline_shape(case, dtype, tol):
+    abc, prm, st, dt, ref = case
+    f32 = lambda x: np.asarray(x, np.float32)
+    ctx = pk.Context(N, N, dtype=dtype)
+    ctx.set_params(prm)
+    ctx.set_tensor(*(f32(x) for x in abc))
+    ctx.set_state(*(f32(x) for x in st))
+    ctx.set_tuning(*SHAPES[dtype])
+    ctx.step(dt, STEPS)
+    got = ctx.get_state()
+    d = ctx.diagnostics()
+    ctx.close()
+    assert d["steps"] == STEPS and d["nonfinite"] == 0
+    errs = [float(np.max(np.abs(x - r)) / np.max(np.abs(r))) for x, r in zip(got, ref)]
+    print(f"{dtype}: relative max-norm error per field after {STEPS} steps: "
+          + ", ".join(f"{n} {e:.3e}" for n, e in zip("uvw", errs)))
+    assert max(errs) <= tol, errs

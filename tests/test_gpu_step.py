@@ -29,7 +29,13 @@ def rel_err(got, ref):
                for g, r in zip(got, ref))
 
 
+# launch shape of the single-step kernel (one step per launch, default width)
+SINGLE = (0, 0, 1, 0)
+
+
 def gpu_ctx(nx, ny, dtype, params, state, abc=None, eig=None, lx=1.0, ly=1.0, rows=0):
+    """A context in the library's default launch shape, or (rows > 0) on the
+    single-step kernel with that strip height."""
     ctx = pk.Context(nx, ny, lx, ly, dtype=dtype)
     ctx.set_params(params)
     if abc is not None:
@@ -40,6 +46,19 @@ def gpu_ctx(nx, ny, dtype, params, state, abc=None, eig=None, lx=1.0, ly=1.0, ro
     if rows:
         ctx.set_tuning(rows)
     return ctx
+
+
+def test_default_launch_shape_is_the_fused_lane_shift_kernel():
+    """A new context steps four levels per launch on the lane-shift kernels (wide
+    lanes except for the compensated state); several steps per launch need
+    those kernels."""
+    for dtype, lanes in (("f64", 2), ("f32", 2), ("f32c", 1)):
+        ctx = pk.Context(64, 48, dtype=dtype)
+        assert ctx.get_tuning() == {"rows_per_strip": 0, "threads": 0, "fused_steps": 4, "lane_shift": lanes}
+        with pytest.raises(pk.GGFVError) as e:
+            ctx.set_tuning(0, 64, 2, lane_shift=0)
+        assert e.value.status == pk.GGFV_EINVAL
+        ctx.close()
 
 
 # ---------------------------------------------------------------------------
@@ -71,13 +90,18 @@ def test_f64_ragged_shapes_bitwise(nx, ny, rows):
     prm = (12.5, 1.0, 0.05, 70.0, 55.0)
     lx, ly = 1.0, 0.8
     dt = oracle.stable_dt(a, b, c, prm[2], 0.9, lx, ly)
-    ctx = gpu_ctx(nx, ny, "f64", prm, (u, v, w), abc=(a, b, c), lx=lx, ly=ly, rows=rows)
-    assert ctx.stable_dt(0.9) == dt
-    ctx.step(dt, 25)
-    got = ctx.get_state()
     ref = oracle.run(u, v, w, a, b, c, prm, dt, 25, lx, ly)[:3]
-    assert rel_err(got, ref) <= 1e-12
-    assert all(np.array_equal(x, y) for x, y in zip(got, ref))
+    # the single-step kernel at this strip height, then the default shape
+    for single in (True, False):
+        ctx = gpu_ctx(nx, ny, "f64", prm, (u, v, w), abc=(a, b, c), lx=lx, ly=ly)
+        if single:
+            ctx.set_tuning(rows)
+        assert ctx.stable_dt(0.9) == dt
+        ctx.step(dt, 25)
+        got = ctx.get_state()
+        ctx.close()
+        assert rel_err(got, ref) <= 1e-12
+        assert all(np.array_equal(x, y) for x, y in zip(got, ref)), single
 
 
 def test_f64_smooth_anisotropic_eig_tensor():
@@ -255,21 +279,26 @@ def test_full_size_fp32_headline_shapes(dtype, shape, tol):
     own FP32 tensor, state and step."""
     import dataclasses
     w = wl.cfg2(steps=40)
-    ctx = gpu_ctx(w.nx, w.ny, dtype, w.params, (w.u0, w.v0, w.w0), eig=w.eig)
-    dt = float(np.float32(ctx.stable_dt(0.9)))
+    r32 = lambda x: np.float64(np.float32(x))
+    # FP32-rounded inputs for both sides: tensor from the oracle's map of the
+    # FP32 eigen-fields, state, parameters and step
+    a, b, c = (r32(x) for x in oracle.tensor_from_eig(*(r32(x) for x in w.eig)))
+    w32 = dataclasses.replace(w, u0=r32(w.u0), v0=r32(w.v0), w0=r32(w.w0),
+                              params=tuple(float(np.float32(p)) for p in w.params))
+    dt = float(np.float32(oracle.stable_dt(a, b, c, w32.params[2], 0.9)))
+    f32 = lambda x: np.asarray(x, np.float32)
+    st32 = tuple(f32(x) for x in (w32.u0, w32.v0, w32.w0))
+    ctx = gpu_ctx(w.nx, w.ny, dtype, w32.params, st32, abc=tuple(f32(x) for x in (a, b, c)))
+    ctx.set_tuning(*SINGLE)
     ctx.step(dt, w.steps)
     single = ctx.get_state()
-    ctx.set_state(w.u0, w.v0, w.w0)
+    ctx.set_state(*st32)
     ctx.set_tuning(*shape)
     ctx.step(dt, w.steps)
     got = ctx.get_state()
     for name, x, y in zip("uvw", got, single):
         assert np.array_equal(x, y), f"{name}: headline shape differs from single steps"
-    a, b, c = ctx.get_tensor()
     ctx.close()
-    r32 = lambda x: np.float64(np.float32(x))
-    w32 = dataclasses.replace(w, u0=r32(w.u0), v0=r32(w.v0), w0=r32(w.w0),
-                              params=tuple(float(np.float32(p)) for p in w.params))
     n = w.nx
     for (j0, j1, i0, i1) in [(0, 30, 0, 30), (n - 30, n, 2000, 2030), (2030, 2060, 2030, 2060)]:
         ref = _patch_reference(w32, a, b, c, dt, w.steps, j0, j1, i0, i1)
@@ -485,28 +514,6 @@ def test_error_paths():
 # ---------------------------------------------------------------------------
 # several steps fused per launch: identical bits to single steps
 
-@pytest.mark.parametrize("dtype", ["f64", "f32c", "f32"])
-@pytest.mark.parametrize("K,threads", [(2, 64), (2, 128), (3, 64), (3, 128), (4, 64)])
-def test_fused_steps_bitwise(dtype, K, threads):
-    shapes = [(300, 77), (1, 50), (50, 1), (513, 130), (3, 700), (129, 129)]
-    for (nx, ny) in shapes:
-        g = rng(nx * 13 + ny + K)
-        a, b, c = wl.random_abc(g, nx, ny)
-        u, v, w = wl.random_state(g, nx, ny)
-        ctx = gpu_ctx(nx, ny, dtype, PRM, (u, v, w), abc=(a, b, c))
-        dt = ctx.stable_dt(0.9)
-        n = 4 * K + 1                              # fused launches plus a single-step remainder
-        ctx.step(dt, n)
-        ref = ctx.get_state()
-        for rows in (0, 5 * K, 37):
-            ctx.set_tuning(rows, threads, K)
-            ctx.set_state(u, v, w)
-            ctx.step(dt, n)
-            got = ctx.get_state()
-            assert all(np.array_equal(x, y) for x, y in zip(got, ref)), (nx, ny, rows)
-        ctx.close()
-
-
 @pytest.mark.parametrize("dtype,lanes", [("f64", 1), ("f32c", 1), ("f32", 1), ("f64", 2), ("f32", 2)])
 @pytest.mark.parametrize("K", [1, 2, 3, 4])
 def test_lane_shift_steps_bitwise(dtype, lanes, K):
@@ -520,6 +527,7 @@ def test_lane_shift_steps_bitwise(dtype, lanes, K):
         a, b, c = wl.random_abc(g, nx, ny)
         u, v, w = wl.random_state(g, nx, ny)
         ctx = gpu_ctx(nx, ny, dtype, PRM, (u, v, w), abc=(a, b, c))
+        ctx.set_tuning(*SINGLE)
         dt = ctx.stable_dt(0.9)
         n = 3 * K + 2 if K > 1 else 5             # fused launches plus single-step remainder
         ctx.step(dt, n)
@@ -568,14 +576,14 @@ def test_lane_shift_full_size_against_oracle_patches(lanes):
 
 
 def test_fused_full_size_patches_and_checkpoints():
-    """4096^2 layered tissue with three steps per launch, 60 steps, sampled
+    """4096^2 layered tissue with three steps per launch (narrow lanes), 60 steps, sampled
     windows against the oracle; checkpointed stepping with fusion keeps the
     same states."""
     torch = pytest.importorskip("torch")
     w = wl.cfg2(steps=60)
     a, b, c = oracle.tensor_from_eig(*w.eig)
     ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), eig=w.eig)
-    ctx.set_tuning(0, 128, 3)
+    ctx.set_tuning(0, 0, 3, lane_shift=1)
     dt = ctx.stable_dt(0.9)
     ctx.step(dt, w.steps)
     got = ctx.get_state()
