@@ -206,6 +206,36 @@ double ggfv_front_speed(double mass0, double mass1, double t0, double t1, double
  * filled) if nonfinite > 0 or cfl > 1. */
 int ggfv_diagnostics(ggfv_ctx *ctx, ggfv_diag *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * diagnostics of ggfv_diagnostics for a state and tensor held in caller device
+ * arrays, with no context, no allocation, no host copy and no
+ * synchronization.  u, v, w, a, b, c: dense row-major device arrays of nx*ny
+ * io_dtype values (GGFV_F64 or GGFV_F32) on `device`; for a compensated state
+ * pass hi + lo as FP64.  Delta2 is the tumour-cell diffusion of eq. (1), dt
+ * the step the cfl refers to.  out: 11 doubles of device memory, written by
+ * work enqueued on hip_stream (NULL: the null stream):
+ *   out[0..2] masses of u, v, w (dx*dy times the sum of the finite values),
+ *   out[3..5] minima, out[6..8] maxima (over finite values),
+ *   out[9]    cfl = dt * max over cells of max(2(a idx^2 + c idy^2) + |b| idx idy,
+ *             2 Delta2 |1-u| (idx^2 + idy^2)),
+ *   out[10]   the number of non-finite values among u, v, w,
+ * the same values, bit for bit, as ggfv_diagnostics on a context holding this
+ * state, tensor and Delta2 after steps of size dt.  The reduction's per-block
+ * partials live in a static device array of the library: at most 1024 blocks
+ * x 12 doubles (96 KiB per device, held until the process ends), enough for
+ * every grid the library accepts; every block rewrites its own partials, so
+ * nothing needs clearing between calls.  Calls on one device share that array:
+ * calls that overlap on one device (different streams or threads) race and
+ * give wrong results.  EINVAL (before any device work) for nx or ny < 1, more
+ * than 2^34 cells, non-finite or non-positive lx, ly, a bad io_dtype, a NULL
+ * pointer, a negative or non-finite Delta2 or dt, or a device out of range;
+ * EHIP if the array's device address cannot be obtained or the launch fails.
+ * ggfv_last_error(NULL) reports why on the calling thread. */
+int ggfv_diagnostics_noalloc(int nx, int ny, double lx, double ly, int io_dtype, const void *u, const void *v,
+                             const void *w, const void *a, const void *b, const void *c, double Delta2,
+                             double dt, double *out, int device, void *hip_stream);
+
 /* ---- gradients ------------------------------------------------------------
  *
  * The adjoint of the explicit step: for a loss L of the state after N steps,
@@ -369,7 +399,8 @@ int ggfv_batch_autotune(ggfv_batch *b, int trial_steps, int *best_threads, int *
 const char *ggfv_batch_last_error(const ggfv_batch *b);
 
 /* Message describing the last failure of this context ("" if none).  With
- * ctx == NULL: the message of the last failed ggfv_create on the calling thread. */
+ * ctx == NULL: the message of the last failed ggfv_create or
+ * ggfv_diagnostics_noalloc on the calling thread. */
 const char *ggfv_last_error(const ggfv_ctx *ctx);
 
 /* Static name of a status code. */

@@ -8,7 +8,7 @@ not load the library: the first ``Context`` does, and it raises if the library
 was not built (``python -m paper_2006_01748_amd.build``).
 """
 from ._binding import (  # noqa: F401
-    Context, Context3, Batch, GGFVError, Params, Diag, lib, exported_names, front_speed,
+    Context, Context3, Batch, GGFVError, Params, Diag, lib, exported_names, front_speed, diagnostics_noalloc,
     GGFV_OK, GGFV_EINVAL, GGFV_ENOMEM, GGFV_EHIP, GGFV_ESTATE, GGFV_EUNSTABLE,
     GGFV_F32, GGFV_F64, GGFV_F32C, GGFV_HOST, GGFV_DEVICE,
 )

@@ -38,6 +38,8 @@ _SIGNATURES = [
     ("ggfv_stable_dt", _c.c_int, [_VP, _c.c_double, _c.POINTER(_c.c_double)]),
     ("ggfv_step", _c.c_int, [_VP, _c.c_double, _c.c_longlong]),
     ("ggfv_diagnostics", _c.c_int, [_VP, _VP]),
+    ("ggfv_diagnostics_noalloc", _c.c_int, [_c.c_int, _c.c_int, _c.c_double, _c.c_double, _c.c_int] + [_VP] * 6
+     + [_c.c_double, _c.c_double, _VP, _c.c_int, _VP]),
     ("ggfv_state_bytes", _c.c_longlong, [_VP]),
     ("ggfv_step_checkpointed", _c.c_int, [_VP, _c.c_double, _c.c_longlong, _c.c_longlong, _VP, _c.c_longlong]),
     ("ggfv_adjoint_step", _c.c_int, [_VP, _c.c_double] + [_VP] * 12 + [_c.POINTER(_c.c_double), _c.c_int, _c.c_int]),
@@ -141,6 +143,30 @@ def front_speed(mass0, mass1, t0, t1, ly=1.0, behind=1.0, ahead=0.0):
     """LeVeque-Yee space-averaged front speed from two masses (ggfv_front_speed)."""
     return float(lib().ggfv_front_speed(float(mass0), float(mass1), float(t0), float(t1), float(ly),
                                         float(behind), float(ahead)))
+
+
+def diagnostics_noalloc(u, v, w, a, b, c, Delta2, dt, out, lx=1.0, ly=1.0, device=0, stream=None):
+    """ggfv_diagnostics_noalloc: diagnostics of a state and tensor in torch device
+    tensors (all (ny, nx), float64 or float32) into `out`, a float64 device
+    tensor of 11 values, enqueued on torch's current stream (or `stream`);
+    allocates nothing.  Returns `out`."""
+    arrays = (u, v, w, a, b, c)
+    if not all(_is_device_tensor(x) and x.is_contiguous() for x in arrays):
+        raise TypeError("diagnostics_noalloc takes contiguous device tensors")
+    io = _io_of(u)
+    if any(_io_of(x) != io or tuple(x.shape) != tuple(u.shape) for x in arrays):
+        raise TypeError("all arrays must share one shape and dtype")
+    if not (_is_device_tensor(out) and out.is_contiguous() and out.numel() >= 11 and out.dtype == _torch().float64):
+        raise TypeError("out must be a contiguous float64 device tensor of at least 11 values")
+    ny, nx = (int(u.shape[0]), int(u.shape[1])) if u.dim() == 2 else (1, int(u.numel()))
+    if stream is None:
+        stream = _current_stream()
+    rc = lib().ggfv_diagnostics_noalloc(nx, ny, float(lx), float(ly), io,
+                                        *[ctypes.c_void_p(x.data_ptr()) for x in arrays], float(Delta2),
+                                        float(dt), ctypes.c_void_p(out.data_ptr()), int(device), stream)
+    if rc != GGFV_OK:
+        raise GGFVError(rc, lib().ggfv_last_error(None).decode())
+    return out
 
 
 def exported_names():

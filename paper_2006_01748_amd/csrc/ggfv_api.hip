@@ -774,4 +774,36 @@ int ggfv_diagnostics(ggfv_ctx *ctx, ggfv_diag *out)
     return GGFV_OK;
 }
 
+int ggfv_diagnostics_noalloc(int nx, int ny, double lx, double ly, int io_dtype, const void *u, const void *v,
+                             const void *w, const void *a, const void *b, const void *c, double Delta2,
+                             double dt, double *out, int device, void *hip_stream)
+{
+    if (nx < 1 || ny < 1) return fail(nullptr, GGFV_EINVAL, "grid must be at least 1x1 (got %dx%d)", nx, ny);
+    if ((long long)nx * ny > (1LL << 34))
+        return fail(nullptr, GGFV_EINVAL, "grid too large (%dx%d; at most 2^34 cells)", nx, ny);
+    if (!(lx > 0.0) || !(ly > 0.0) || !std::isfinite(lx) || !std::isfinite(ly))
+        return fail(nullptr, GGFV_EINVAL, "domain sides must be finite and > 0");
+    if (!valid_io(io_dtype))
+        return fail(nullptr, GGFV_EINVAL, "io_dtype must be GGFV_F32 or GGFV_F64 (got %d)", io_dtype);
+    if (!u || !v || !w || !a || !b || !c || !out) return fail(nullptr, GGFV_EINVAL, "null array pointer");
+    if (!(Delta2 >= 0.0) || !std::isfinite(Delta2) || !(dt >= 0.0) || !std::isfinite(dt))
+        return fail(nullptr, GGFV_EINVAL, "Delta2 and dt must be finite and >= 0");
+    int ndev = 0;
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess) return fail(nullptr, GGFV_EHIP, "hipGetDeviceCount failed: %s", hipGetErrorString(he));
+    if (device < 0 || device >= ndev)
+        return fail(nullptr, GGFV_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    DeviceGuard g(device);
+    if (g.status != hipSuccess)
+        return fail(nullptr, GGFV_EHIP, "hipSetDevice(%d) failed: %s", device, hipGetErrorString(g.status));
+    double *parts = nullptr;
+    he = noalloc_scratch(device, &parts);
+    if (he != hipSuccess)
+        return fail(nullptr, GGFV_EHIP, "no scratch address on device %d: %s", device, hipGetErrorString(he));
+    he = launch_diagnostics_dense(nx, ny, lx, ly, io_dtype == GGFV_F64, u, v, w, a, b, c, Delta2, dt, parts, out,
+                                  static_cast<hipStream_t>(hip_stream));
+    if (he != hipSuccess) return fail(nullptr, GGFV_EHIP, "diagnostics launch failed: %s", hipGetErrorString(he));
+    return GGFV_OK;
+}
+
 }  // extern "C"

@@ -14,6 +14,7 @@
 // partials in index order.  All accumulation is FP64.
 
 #include <cmath>
+#include <mutex>
 
 #include "ggfv_internal.hpp"
 
@@ -185,12 +186,22 @@ __global__ __launch_bounds__(kReduceThreads) void spd_kernel(const T *__restrict
     }
 }
 
-// Diagnostics partial: slots 0-2 sums, 3-5 minima, 6-8 maxima, 9 cfl max,
-// 10 non-finite count, 11 unused (kept zero).
+// Fields of the diagnostics: u, v, w (and their low words for the compensated
+// state, else null) and the tensor a, b, c, each a row-major plane with rows
+// `pitch` values apart.
 template <typename T>
-__global__ __launch_bounds__(kReduceThreads) void diag_kernel(const T *__restrict__ st, size_t plane,
-                                                              bool has_lo,
-                                                              const T *__restrict__ abc, int nx,
+struct DiagFields {
+    const T *f[3];
+    const T *lo[3];
+    const T *a, *b, *c;
+};
+
+// Diagnostics partial: slots 0-2 sums, 3-5 minima, 6-8 maxima, 9 cfl max,
+// 10 non-finite count, 11 unused (kept zero).  Cell k of the grid goes to
+// thread k mod (blocks * threads) whatever the row pitch, so dense and padded
+// planes of the same values give the same partials.
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void diag_kernel(DiagFields<T> F, bool has_lo, int nx,
                                                               int ny, int pitch, double idx2,
                                                               double idy2, double idxy, double D2,
                                                               double *__restrict__ parts)
@@ -209,8 +220,8 @@ __global__ __launch_bounds__(kReduceThreads) void diag_kernel(const T *__restric
         double f[3];
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            f[p] = double(st[p * plane + o]);
-            if (has_lo) f[p] = f[p] + double(st[(3 + p) * plane + o]);
+            f[p] = double(F.f[p][o]);
+            if (has_lo) f[p] = f[p] + double(F.lo[p][o]);
             if (!isfinite(f[p])) {
                 x[10] += 1.0;
             } else {
@@ -219,7 +230,7 @@ __global__ __launch_bounds__(kReduceThreads) void diag_kernel(const T *__restric
                 x[6 + p] = fmax(x[6 + p], f[p]);
             }
         }
-        const double a = abc[o], b = abc[plane + o], c = abc[2 * plane + o];
+        const double a = F.a[o], b = F.b[o], c = F.c[o];
         const double cw = 2.0 * (a * idx2 + c * idy2) + fabs(b) * idxy;
         const double cv = 2.0 * D2 * fabs(1.0 - f[0]) * (idx2 + idy2);
         x[9] = fmax(x[9], fmax(cw, cv));
@@ -385,9 +396,12 @@ __global__ __launch_bounds__(kReduceThreads) void front_final_kernel(const doubl
     }
 }
 
-// Diagnostics final pass (fixed operators per slot).
+// Diagnostics final pass (fixed operators per slot) into the first nout slots
+// of out; the sums of slots 0-2 are multiplied by `area` and the maximum of
+// slot 9 by `dt` (1 and 1 leave them as they are).
 __global__ __launch_bounds__(kReduceThreads) void diag_final_kernel(const double *__restrict__ parts,
-                                                                    int nparts, double *__restrict__ out)
+                                                                    int nparts, double area, double dt,
+                                                                    int nout, double *__restrict__ out)
 {
     const Op ops[kDiagSlots] = {Op::Sum, Op::Sum, Op::Sum, Op::Min, Op::Min, Op::Min,
                                 Op::Max, Op::Max, Op::Max, Op::Max, Op::Sum, Op::Sum};
@@ -401,18 +415,25 @@ __global__ __launch_bounds__(kReduceThreads) void diag_final_kernel(const double
     block_reduce<kDiagSlots>(x, ops);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int s = 0; s < kDiagSlots; ++s) out[s] = x[s];
+        for (int s = 0; s < 3; ++s) x[s] = area * x[s];
+        x[9] = dt * x[9];
+#pragma unroll
+        for (int s = 0; s < kDiagSlots; ++s)
+            if (s < nout) out[s] = x[s];
     }
 }
 
-int reduce_blocks(const ggfv_ctx *ctx)
+// Partial blocks of the reductions over an nx*ny grid: about four cells per
+// thread, at most kMaxPartialBlocks.
+int reduce_blocks_of(long n)
 {
-    const long n = (long)ctx->nx * ctx->ny;
     long b = (n + 4L * kReduceThreads - 1) / (4L * kReduceThreads);
     if (b < 1) b = 1;
     if (b > kMaxPartialBlocks) b = kMaxPartialBlocks;
     return (int)b;
 }
+
+int reduce_blocks(const ggfv_ctx *ctx) { return reduce_blocks_of((long)ctx->nx * ctx->ny); }
 
 double *parts_of(ggfv_ctx *ctx) { return static_cast<double *>(ctx->scratch); }
 double *result_of(ggfv_ctx *ctx)
@@ -546,6 +567,24 @@ hipError_t launch_front_diagnostics(ggfv_ctx *ctx, double theta_u, double theta_
     return hipGetLastError();
 }
 
+template <typename T>
+DiagFields<T> ctx_fields(ggfv_ctx *ctx)
+{
+    const T *st = static_cast<const T *>(ctx->state[ctx->cur]);
+    const T *ab = static_cast<const T *>(ctx->tensor);
+    const size_t P = ctx->plane;
+    const bool lo = (ctx->dtype == GGFV_F32C);
+    DiagFields<T> F;
+    for (int p = 0; p < 3; ++p) {
+        F.f[p] = st + p * P;
+        F.lo[p] = lo ? st + (3 + p) * P : nullptr;
+    }
+    F.a = ab;
+    F.b = ab + P;
+    F.c = ab + 2 * P;
+    return F;
+}
+
 hipError_t launch_diagnostics(ggfv_ctx *ctx, double dt)
 {
     (void)dt;
@@ -554,18 +593,78 @@ hipError_t launch_diagnostics(ggfv_ctx *ctx, double dt)
     const bool lo = (ctx->dtype == GGFV_F32C);
     if (ctx->dtype == GGFV_F64)
         hipLaunchKernelGGL((diag_kernel<double>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
-                           (const double *)ctx->state[ctx->cur], ctx->plane, false,
-                           (const double *)ctx->tensor, ctx->nx, ctx->ny, ctx->pitch, idx * idx,
+                           ctx_fields<double>(ctx), false, ctx->nx, ctx->ny, ctx->pitch, idx * idx,
                            idy * idy, idx * idy, ctx->prm.Delta2, parts_of(ctx));
     else
         hipLaunchKernelGGL((diag_kernel<float>), dim3(nb), dim3(kReduceThreads), 0, ctx->stream,
-                           (const float *)ctx->state[ctx->cur], ctx->plane, lo,
-                           (const float *)ctx->tensor, ctx->nx, ctx->ny, ctx->pitch, idx * idx,
+                           ctx_fields<float>(ctx), lo, ctx->nx, ctx->ny, ctx->pitch, idx * idx,
                            idy * idy, idx * idy, ctx->prm.Delta2, parts_of(ctx));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kReduceThreads), 0, ctx->stream,
-                       parts_of(ctx), nb, result_of(ctx));
+                       parts_of(ctx), nb, 1.0, 1.0, kDiagSlots, result_of(ctx));
+    return hipGetLastError();
+}
+
+// ---- diagnostics without allocation ------------------------------------------
+//
+// ggfv_diagnostics_noalloc keeps its per-block partials in this array instead
+// of memory the library allocates: kMaxPartialBlocks x kDiagSlots doubles (96
+// KiB), which covers every grid (the reduction uses at most kMaxPartialBlocks
+// blocks, whatever the grid size).  Each device the library runs on holds its
+// own copy until the process ends.  Host code never uses the array's name as an
+// address: its device address, per device, comes from hipGetSymbolAddress.
+__device__ __align__(256) double scratch[kMaxPartialBlocks * kDiagSlots];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double **out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_diagnostics_dense(int nx, int ny, double lx, double ly, bool f64, const void *u,
+                                    const void *v, const void *w, const void *a, const void *b,
+                                    const void *c, double Delta2, double dt, double *parts, double *out,
+                                    hipStream_t stream)
+{
+    const int nb = reduce_blocks_of((long)nx * ny);
+    const double idx = nx / lx, idy = ny / ly;
+    if (f64) {
+        DiagFields<double> F{{static_cast<const double *>(u), static_cast<const double *>(v),
+                              static_cast<const double *>(w)},
+                             {nullptr, nullptr, nullptr}, static_cast<const double *>(a),
+                             static_cast<const double *>(b), static_cast<const double *>(c)};
+        hipLaunchKernelGGL((diag_kernel<double>), dim3(nb), dim3(kReduceThreads), 0, stream, F, false, nx, ny,
+                           nx, idx * idx, idy * idy, idx * idy, Delta2, parts);
+    } else {
+        DiagFields<float> F{{static_cast<const float *>(u), static_cast<const float *>(v),
+                             static_cast<const float *>(w)},
+                            {nullptr, nullptr, nullptr}, static_cast<const float *>(a),
+                            static_cast<const float *>(b), static_cast<const float *>(c)};
+        hipLaunchKernelGGL((diag_kernel<float>), dim3(nb), dim3(kReduceThreads), 0, stream, F, false, nx, ny,
+                           nx, idx * idx, idy * idy, idx * idy, Delta2, parts);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double dx = lx / nx, dy = ly / ny;
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kReduceThreads), 0, stream, parts, nb, dx * dy, dt,
+                       kDiagSlots - 1, out);
     return hipGetLastError();
 }
 

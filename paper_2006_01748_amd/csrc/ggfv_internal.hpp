@@ -183,5 +183,15 @@ hipError_t launch_spd_count(ggfv_ctx *ctx);
 hipError_t launch_lambda_max(ggfv_ctx *ctx);
 // Diagnostics partials and final reduction -> kDiagSlots doubles at scratch.
 hipError_t launch_diagnostics(ggfv_ctx *ctx, double dt);
+// Diagnostics of dense nx*ny arrays (FP64 or FP32), no context: partials into
+// `parts` (kMaxPartialBlocks * kDiagSlots doubles), the 11 results into `out`
+// (device), masses times dx*dy and the cfl maximum times dt.
+hipError_t launch_diagnostics_dense(int nx, int ny, double lx, double ly, bool f64, const void *u,
+                                    const void *v, const void *w, const void *a, const void *b,
+                                    const void *c, double Delta2, double dt, double *parts, double *out,
+                                    hipStream_t stream);
+// Device address of the library's static diagnostics scratch on `device`
+// (which must be current); looked up once per device.
+hipError_t noalloc_scratch(int device, double **out);
 
 }  // namespace ggfv
