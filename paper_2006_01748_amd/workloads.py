@@ -241,10 +241,11 @@ def front_instance(delta1: float, kappa: float, nx: int = 512, ny: int = 256, lx
                    ly: float = 0.5, steps: int = 0, seed: int = BASE_SEED + 5) -> Workload:
     """Propagating-front workload (Section 2's invasion experiment): healthy
     tissue u = 1 everywhere, the tumour v = 1 behind a front at x0(y) = 0.2 +
-    0.02 sin(4 pi y / ly + phase) (seeded phase), no acid.  The acid diffuses
-    with lambda1 along x and kappa * lambda1 across (lower vertical diffusivity
-    for kappa < 1), lambda1 a smooth seeded field in [0.75, 1.25]
-    (heterogeneous).  Parameters (delta1, 1, 0.01, 70, 70)."""
+    0.02 sin(4 pi y / ly + phase) (seeded phase), no acid.  The fronts advance
+    along +x.  The acid diffuses with kappa * lam along x, the direction of
+    propagation (lower diffusivity there for kappa < 1), and lam across it, lam a
+    smooth seeded field in [0.75, 1.25] (heterogeneous); as (lambda1, lambda2,
+    theta) = (kappa lam, lam, 0).  Parameters (delta1, 1, 0.01, 70, 70)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     X, Y = cell_centres(nx, ny, lx, ly)
     phase = rng.uniform(0.0, 2.0 * math.pi)
@@ -252,18 +253,17 @@ def front_instance(delta1: float, kappa: float, nx: int = 512, ny: int = 256, lx
     v = (X < x0).astype(np.float64)
     u = np.ones((ny, nx))
     w = np.zeros((ny, nx))
-    lam1 = 0.75 + 0.5 * smooth_field(rng, nx, ny)
-    lam2 = kappa * lam1
+    lam = 0.75 + 0.5 * smooth_field(rng, nx, ny)
     theta = np.zeros((ny, nx))
     return Workload(f"front d={delta1} kappa={kappa}", nx, ny, lx, ly, (delta1, 1.0, 0.01, 70.0, 70.0),
-                    u, v, w, eig=(lam1, lam2, theta), safety=0.9, steps=steps, seed=seed)
+                    u, v, w, eig=(kappa * lam, lam, theta), safety=0.9, steps=steps, seed=seed)
 
 
 def front_sweep(deltas=(0.5, 0.8, 1.5, 3.0, 6.0, 12.5), kappas=(1.0, 0.2), nx: int = 512, ny: int = 256,
                 steps: int = 0):
-    """The delta1 sweep across 1 for each vertical-diffusivity ratio kappa: one
-    front_instance per (delta1, kappa), all with the same seeded front and
-    heterogeneity."""
+    """The delta1 sweep across 1 for each ratio kappa of the acid diffusivity
+    along the propagation direction to the one across it: one front_instance
+    per (delta1, kappa), all with the same seeded front and heterogeneity."""
     return [front_instance(d, k, nx, ny, steps=steps) for k in kappas for d in deltas]
 
 

@@ -76,13 +76,21 @@ def test_invasion_run_bitwise_and_fronts():
 
 
 def test_invasion_sweep_batch():
-    """delta1 sweep across 1 (lower vertical acid diffusivity as a second set),
-    256 x 128 fronts, batched lane-shift kernel, t = 0.5: the gap opens for large
-    delta1 only and the tumour front travels faster with delta1; the front diagnostics of
-    every instance equal the oracle's on the GPU state; the LeVeque-Yee speed of
-    the tumour grows with delta1 as well."""
-    ws = wl.front_sweep(deltas=(0.5, 0.8, 1.5, 3.0, 12.5), kappas=(1.0, 0.2), nx=256, ny=128)
-    b = pk.Batch([(w.nx, w.ny) for w in ws], lx=ws[0].lx, ly=ws[0].ly, dtype="f32c")
+    """The delta1 sweep across 1, for acid diffusing equally in both directions
+    (kappa = 1) and five times more slowly along the direction of propagation
+    (kappa = 0.2): 256 x 128 fronts, FP64, batched lane-shift kernel, t = 2.
+    The two invasion types of Section 2: for delta1 < 1 normal and tumour
+    cells coexist behind the front (u stays above its coexistence level
+    1 - delta1) and no gap opens; for large delta1 the normal cells are
+    degraded behind the front (u -> 0) and a gap opens ahead of it, wider for
+    larger delta1.  Lower acid diffusivity along the propagation direction
+    narrows the gap, and a larger delta1 compensates for it.  The front
+    diagnostics of every instance equal the oracle's on the GPU state; fronts
+    and LeVeque-Yee tumour speeds grow with delta1."""
+    deltas = (0.5, 0.8, 1.5, 3.0, 6.0, 12.5)
+    kappas = (1.0, 0.2)
+    ws = wl.front_sweep(deltas=deltas, kappas=kappas, nx=256, ny=128)
+    b = pk.Batch([(w.nx, w.ny) for w in ws], lx=ws[0].lx, ly=ws[0].ly, dtype="f64")
     dts = []
     for i, w in enumerate(ws):
         c = b[i]
@@ -96,32 +104,40 @@ def test_invasion_sweep_batch():
     b.set_tuning(threads=64, rows_per_strip=16, graph_steps=48, fused_steps=4)
     f0 = [b[i].front_diagnostics(0.25, 0.5) for i in range(len(ws))]
     m0 = [b[i].diagnostics()["mass"][1] for i in range(len(ws))]
-    n = int(0.5 / dt)
+    n = int(2.0 / dt)
     b.run(n)
-    t = [b[i].diagnostics()["t"] for i in range(len(ws))]
+    h = ws[0].lx / ws[0].nx
     res = {}
-    keys = [(k, d) for k in (1.0, 0.2) for d in (0.5, 0.8, 1.5, 3.0, 12.5)]   # front_sweep's order
+    keys = [(k, d) for k in kappas for d in deltas]   # front_sweep's order
     for i, w in enumerate(ws):
+        assert w.params[0] == keys[i][1]
+        d = b[i].diagnostics()
         f = b[i].front_diagnostics(0.25, 0.5)
         U, V, _ = b[i].get_state()
         same_front(f, oracle.front_diag(U, V, 0.25, 0.5, w.lx))
-        m1 = b[i].diagnostics()["mass"][1]
-        speed = pk.front_speed(m0[i], m1, 0.0, t[i], w.ly, 1.0, 0.0)
-        disp = (f["tumour"][0] - f0[i]["tumour"][0]) / t[i]
-        assert w.params[0] == keys[i][1]
-        res[keys[i]] = (f, speed, disp)
-    for kappa in (1.0, 0.2):
-        gaps = [res[(kappa, d)][0]["gap"][0] if res[(kappa, d)][0]["rows_gap"] else 0.0
-                for d in (0.5, 0.8, 1.5, 3.0, 12.5)]
-        fronts = [res[(kappa, d)][0]["tumour"][0] for d in (0.5, 0.8, 1.5, 3.0, 12.5)]
-        print(f"kappa {kappa}: fronts {np.round(fronts, 4)}, gaps {np.round(gaps, 4)}, speeds "
-              f"{[round(res[(kappa, d)][1], 4) for d in (0.5, 0.8, 1.5, 3.0, 12.5)]}")
-        # the gap belongs to the homogeneous (large delta1) invasion only
-        assert gaps[0] < 0.02 and gaps[-1] > 0.05 and gaps[-1] > gaps[0], gaps
-        assert all(f1 < f2 for f1, f2 in zip(fronts, fronts[1:])), fronts
-        # the space-averaged (LeVeque-Yee) speed of the tumour orders the invasions
-        # the same way (the fronts are still settling from their initial step at
-        # this horizon, so it is not compared with the threshold's displacement)
-        speeds = [res[(kappa, d)][1] for d in (0.5, 0.8, 1.5, 3.0, 12.5)]
-        assert speeds[0] > 0 and all(s1 < s2 for s1, s2 in zip(speeds, speeds[1:])), speeds
+        speed = pk.front_speed(m0[i], d["mass"][1], 0.0, d["t"], w.ly, 1.0, 0.0)
+        behind = V >= 0.9                 # the tumour bulk behind the front
+        res[keys[i]] = {"front": f["tumour"][0], "gap": f["gap"][0] if f["rows_gap"] else 0.0,
+                        "rows_gap": f["rows_gap"], "u_behind": float(U[behind].min()), "speed": speed,
+                        "advance": f["tumour"][0] - f0[i]["tumour"][0]}
+    for kappa in kappas:
+        r = [res[(kappa, d)] for d in deltas]
+        print(f"kappa {kappa}: fronts {[round(x['front'], 4) for x in r]}, gaps {[round(x['gap'], 4) for x in r]}, "
+              f"u behind {[round(x['u_behind'], 4) for x in r]}, speeds {[round(x['speed'], 4) for x in r]}")
+        for d, x in zip(deltas, r):
+            if d < 1.0:       # heterogeneous invasion: coexistence, no gap
+                assert x["u_behind"] > (1.0 - d) - 0.02 and x["gap"] < 2 * h, (kappa, d, x)
+        for d in (6.0, 12.5):  # homogeneous invasion: degradation and a gap
+            x = res[(kappa, d)]
+            assert x["u_behind"] < 1e-2 and x["gap"] > 3 * h and x["rows_gap"] == ws[0].ny, (kappa, d, x)
+        assert res[(kappa, 12.5)]["gap"] > res[(kappa, 6.0)]["gap"]
+        assert all(a["u_behind"] > c["u_behind"] or a["u_behind"] < 1e-6 for a, c in zip(r, r[1:])), \
+            "degradation grows with delta1"
+        assert all(a["front"] < c["front"] for a, c in zip(r, r[1:])), "fronts order with delta1"
+        assert r[0]["speed"] > 0 and all(a["speed"] < c["speed"] for a, c in zip(r, r[1:])), "speeds"
+    # lower acid diffusivity along the propagation direction narrows the gap,
+    # and a larger delta1 compensates for it
+    for d in (6.0, 12.5):
+        assert res[(0.2, d)]["gap"] < 0.75 * res[(1.0, d)]["gap"], d
+    assert res[(0.2, 12.5)]["gap"] > res[(1.0, 6.0)]["gap"]
     b.close()
