@@ -346,6 +346,7 @@ def time_adjoint(pk, torch, steps=5000):
     torch.cuda.synchronize()
     fwd_us = 1e3 * e0.elapsed_time(e1) / 1000
     ctx.close()
+    big = time_adjoint_kernel(pk, torch)
     bwd = res["fused"]["backward_ms"]
     return {"workload": f"{w.nx}x{w.ny} smooth anisotropic tensor, {w.steps} steps, checkpoint every "
                         f"{every} steps (forward stores {-(-w.steps // every)} states, backward recomputes "
@@ -355,7 +356,72 @@ def time_adjoint(pk, torch, steps=5000):
             "backward_over_forward": bwd / res["fused"]["forward_ms"],
             "forward_single_step_ms": res["single_step"]["forward_ms"],
             "backward_over_forward_single_step": res["single_step"]["backward_ms"] / res["single_step"]["forward_ms"],
-            "step_us": fwd_us, "adjoint_step_us_est": 1e3 * bwd / w.steps - fwd_us}
+            "step_us": fwd_us, "adjoint_step_us_est": 1e3 * bwd / w.steps - fwd_us,
+            "adjoint_kernel_4096": big, "roofline": big["roofline"]}
+
+
+# Algorithmic HBM bytes of one adjoint step per cell (FP64): read x^k (3),
+# lam^{k+1} (3), a, b, c and the tensor gradient (3 + 3); write lam^k (3) and the
+# tensor gradient (3).
+ADJOINT_BYTES_PER_CELL = 18 * 8
+
+
+def time_adjoint_kernel(pk, torch, n=4096, short=4, long=12):
+    """The adjoint step at an HBM-resident size: the 4096^2 layered tissue, a
+    reverse sweep with a checkpoint at every step (so it recomputes nothing and
+    runs only adjoint steps), timed for `short` and `long` steps with HIP events
+    on the context's stream; the difference over the extra steps is the time of
+    one adjoint step, free of the sweep's fixed costs."""
+    from paper_2006_01748_amd import workloads as wl
+    w = wl.cfg2(n=n)
+    stream = torch.cuda.current_stream()
+    ctx = pk.Context(w.nx, w.ny, w.lx, w.ly, dtype="f64", stream=stream.cuda_stream)
+    ctx.set_params(w.params)
+    ctx.set_tensor_eig(*w.eig)
+    dt = ctx.stable_dt(w.safety)
+    sb = ctx.state_bytes()
+    ckpt = torch.empty(long * sb, dtype=torch.uint8, device="cuda")
+    work = torch.empty(sb, dtype=torch.uint8, device="cuda")
+    lam = [torch.zeros((w.ny, w.nx), dtype=torch.float64, device="cuda") for _ in range(3)]
+    g = [torch.empty((w.ny, w.nx), dtype=torch.float64, device="cuda") for _ in range(3)]
+    ctx.set_state(w.u0, w.v0, w.w0)
+    ctx.step_checkpointed(dt, long, 1, ckpt)
+    ms = {}
+    for k in (short, long, short, long):            # the first pair warms up
+        for x in lam:
+            x.fill_(1e-6)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.adjoint_run(dt, k, 1, ckpt, work, lam, g)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms[k] = e0.elapsed_time(e1)
+    ctx.close()
+    del ckpt, work
+    us = 1e3 * (ms[long] - ms[short]) / (long - short)
+    cells = w.nx * w.ny
+    gbs = ADJOINT_BYTES_PER_CELL * cells / (us * 1e-6) / 1e9
+    return {"workload": f"{w.nx}x{w.ny} layered tissue, FP64, reverse sweeps of {short} and {long} steps with a "
+                        "checkpoint at every step", "adjoint_step_us": us,
+            "roofline": {"bound": "hbm", "kernel": "adjoint_kernel<double>", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": measured_adjoint_traffic(),
+                         "bytes_per_cell_update": ADJOINT_BYTES_PER_CELL, "kernel_avg_us": us}}
+
+
+def measured_adjoint_traffic():
+    """HBM bytes per adjoint step at 4096^2 from the committed counter summary,
+    or None (none taken, or the adjoint source changed since)."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "adjoint_kernel_traffic.json")) as f:
+            data = json.load(f)
+        if sources_digest(here, data["kernel_sources"]) != data.get("kernel_sources_sha256"):
+            return None
+        t = data["bytes_per_launch"]["adjoint_kernel<double>"]
+    except (OSError, KeyError, ValueError):
+        return None
+    return t["read"] + t["write"]
 
 
 def time_adaptive(pk, torch, w, steps=200):
@@ -385,13 +451,14 @@ def time_adaptive(pk, torch, w, steps=200):
             "ms_per_step": ms / steps, "dt_first": float(dts[0]), "dt_last": float(dts[-1])}
 
 
-def time_front_sweep(pk, torch, t_end=0.5):
+def time_front_sweep(pk, torch, t_end=2.0):
     """Invasion sweep (Section 2's propagating fronts and interstitial gap):
-    delta1 in {0.5, 0.8, 1.5, 3, 6, 12.5} x vertical/horizontal acid
-    diffusivity ratio in {1, 0.2}, 512 x 256 fronts on [0,1] x [0,0.5], FP64,
-    one batch on the lane-shift kernel (4 steps per launch) with a common dt, run
-    to t_end; then the fronts, the gap and the LeVeque-Yee tumour speed of every
-    instance."""
+    delta1 in {0.5, 0.8, 1.5, 3, 6, 12.5} x ratio of the acid diffusivity along
+    the propagation direction to the one across it in {1, 0.2}, 512 x 256 fronts
+    on [0,1] x [0,0.5], FP64, one batch on the lane-shift kernel (4 steps per
+    launch) with a common dt, run to t_end; then the fronts, the gap, the least
+    u in the tumour bulk behind the front (v >= 0.9) and the LeVeque-Yee tumour
+    speed of every instance."""
     from paper_2006_01748_amd import workloads as wl
     ws = wl.front_sweep()
     stream = torch.cuda.Stream()
@@ -422,7 +489,9 @@ def time_front_sweep(pk, torch, t_end=0.5):
     for i, w in enumerate(ws):
         d = b[i].diagnostics()
         f = b[i].front_diagnostics(0.25, 0.5)
-        out.append({"delta1": w.params[0], "kappa": round(float(w.eig[1][0, 0] / w.eig[0][0, 0]), 6),
+        U, V, _ = b[i].get_state()
+        out.append({"delta1": w.params[0], "kappa": round(float(w.eig[0][0, 0] / w.eig[1][0, 0]), 6),
+                    "u_behind_min": float(U[V >= 0.9].min()) if (V >= 0.9).any() else None,
                     "tumour_front": float(f["tumour"][0]), "tumour_front_advance": float(f["tumour"][0] - f0[i]),
                     "gap_mean": float(f["gap"][0]) if f["rows_gap"] else None,
                     "gap_max": float(f["gap"][2]) if f["rows_gap"] else None,
@@ -661,6 +730,21 @@ PROFILE_COMMANDS = {
               "-- python3 $R/bench.py --only-3d",
     "write3": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/write3 -o write3 "
               "-- python3 $R/bench.py --only-3d",
+    # the ensemble alone: batched kernel trace (with the gaps between graph-replayed
+    # launches) and its HBM traffic
+    "etrace": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/etrace -o etrace "
+              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,16,4 > $P/etrace_bench.json",
+    "efetch": "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $P/efetch -o efetch "
+              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,16,4",
+    "ewrite": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/ewrite -o ewrite "
+              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,16,4",
+    # the adjoint alone (512^2 gradient workload, 4096^2 adjoint steps)
+    "atrace": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/atrace -o atrace "
+              "-- python3 $R/bench.py --only-adjoint > $P/atrace_bench.json",
+    "afetch": "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $P/afetch -o afetch "
+              "-- python3 $R/bench.py --only-adjoint",
+    "awrite": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/awrite -o awrite "
+              "-- python3 $R/bench.py --only-adjoint",
     # instruction counts of the 2D kernels (six SQ counters, one pass)
     "valu": "timeout -s KILL 300 rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD "
             "SQ_INSTS_VMEM_WR SQ_WAVES --output-format csv -d $P/valu -o valu "
@@ -760,10 +844,24 @@ def _counter_means(pdir, kind):
     agg = collections.defaultdict(list)
     for d, v in vals.items():
         agg[meta[d]].append(v)
-    return {k: sum(v) / len(v) for k, v in agg.items()}
+    out = {k: sum(v) / len(v) for k, v in agg.items()}
+    out["__per_dispatch__"] = [(meta[d], v) for d, v in sorted(vals.items())]
+    return out
 
 
 def _copy_calibration(fetch, write, copy_bytes=1 << 30):
+    """Scale factors of FETCH_SIZE and WRITE_SIZE from the 1 GiB device copies of
+    the copy-ceiling probe.  Copies of other sizes (checkpoints, state saves) run
+    the same copy kernel with the same launch shape, so the calibration uses the
+    largest copy dispatches of each run, identified per dispatch."""
+    if isinstance(fetch, dict) and "__per_dispatch__" in fetch:
+        fd, wd = fetch["__per_dispatch__"], write["__per_dispatch__"]
+        fc = [v for (name, _, _), v in fd if name == "__amd_rocclr_copyBuffer"]
+        wc = [v for (name, _, _), v in wd if name == "__amd_rocclr_copyBuffer"]
+        fbig = [v for v in fc if v >= 0.9 * max(fc)]
+        wbig = [v for v in wc if v >= 0.9 * max(wc)]
+        f_mean, w_mean = sum(fbig) / len(fbig), sum(wbig) / len(wbig)
+        return ("__amd_rocclr_copyBuffer", f_mean, w_mean), copy_bytes / (f_mean * 1024), copy_bytes / (w_mean * 1024)
     cal = [k for k in fetch if k[0] == "__amd_rocclr_copyBuffer"]
     ck = max(cal, key=lambda k: k[1])
     return ck, copy_bytes / (fetch[ck] * 1024), copy_bytes / (write[ck] * 1024)
@@ -828,8 +926,8 @@ def summarize_3d(pdir, tdir, fdir, wdir, bench_json):
                 "traced run (a short sweep of rows per wave x planes per strip x waves per workgroup "
                 "precedes the timed steps).  Algorithmic bytes per cell-update: u, v, w and the six tensor "
                 "entries read once, u, v, w written once (96 B in FP64, 48 B in FP32).  Counter calibration: "
-                f"the 1 GiB `__amd_rocclr_copyBuffer` reads FETCH_SIZE = {fetch[ck]:.0f} KiB and WRITE_SIZE = "
-                f"{write[ck]:.0f} KiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.\n\n"
+                f"the 1 GiB `__amd_rocclr_copyBuffer` reads FETCH_SIZE = {ck[1]:.0f} KiB and WRITE_SIZE = "
+                f"{ck[2]:.0f} KiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.\n\n"
                 "| dtype | kernel | rows per wave | planes per strip | waves per workgroup | workgroups | "
                 "dispatches (trace) | average (us, trace) | average (us, live HIP events) | algorithmic GB/s "
                 "(trace) | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | scaled read (MB) | scaled write (MB) | "
@@ -840,6 +938,152 @@ def summarize_3d(pdir, tdir, fdir, wdir, bench_json):
     return traffic3
 
 
+def _trace_rows(pdir, kind):
+    """(short name, grid size, workgroup size, start ns, end ns) of every dispatch
+    in a --kernel-trace run."""
+    import csv
+    out = []
+    with open(os.path.join(pdir, kind, f"{kind}_kernel_trace.csv")) as f:
+        for row in csv.DictReader(f):
+            out.append((_short(row["Kernel_Name"]), int(row["Grid_Size_X"]), int(row["Workgroup_Size_X"]),
+                        int(row["Start_Timestamp"]), int(row["End_Timestamp"])))
+    return out
+
+
+def _stats_table(rows, pred):
+    import collections
+    agg = collections.defaultdict(list)
+    for name, grid, wg, t0, t1 in rows:
+        if pred(name):
+            agg[(name, grid)].append((t1 - t0) / 1e3)
+    lines = []
+    for (name, grid), d in sorted(agg.items(), key=lambda x: -sum(x[1])):
+        lines.append(f"| {name} | {grid} | {len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |")
+    return ("| kernel | grid (threads) | calls | average (us) | min (us) | max (us) |\n|---|---|---|---|---|---|\n"
+            + "\n".join(lines)), agg
+
+
+def summarize_ensemble(pdir):
+    """profiles/ensemble_kernels_256.md and profiles/ensemble_kernel_traffic.json
+    from the etrace/, efetch/ and ewrite/ runs: the batched lane-shift kernel's
+    launch time, the gap between its graph-replayed launches, and its traffic."""
+    import statistics
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(pdir, "etrace_bench.json")) as f:
+        ens = json.loads(f.read().strip().splitlines()[-1])["ensemble"]
+    rows = _trace_rows(pdir, "etrace")
+    table, agg = _stats_table(rows, lambda k: k.startswith(("fused_dpp_batch_kernel", "step_batch_kernel",
+                                                             "fused_dpp_kernel", "step_kernel")))
+    kname = ens["roofline"]["kernel"]
+    batch = sorted((t0, t1) for name, grid, wg, t0, t1 in rows if name == kname)
+    # gaps between consecutive batched launches (end to next start; the
+    # timestamps of back-to-back launches may overlap by a few ns, read as 0);
+    # those under 100 us belong to one run of graph replays
+    gaps = [max(0.0, (b0 - a1) / 1e3) for (a0, a1), (b0, b1) in zip(batch, batch[1:])]
+    run = sorted(g for g in gaps if g < 100.0)
+    dur = [(t1 - t0) / 1e3 for t0, t1 in batch]
+    gap_p90 = run[int(0.9 * (len(run) - 1))] if run else float("nan")
+    gap_max = run[-1] if run else float("nan")
+    gap_mean = sum(run) / len(run) if run else float("nan")
+    fetch, write = _counter_means(pdir, "efetch"), _counter_means(pdir, "ewrite")
+    ck, f_scale, w_scale = _copy_calibration(fetch, write)
+    keys = [k for k in fetch if k[0] == kname]
+    traffic = None
+    if keys:
+        k = max(keys, key=lambda x: x[1])
+        traffic = {"kernel": kname, "read": fetch[k] * 1024 * f_scale, "write": write.get(k, 0.0) * 1024 * w_scale,
+                   "fetch_kib": fetch[k], "write_kib": write.get(k, 0.0)}
+    cells = int(ens["workload"].split("total ")[1].split(" cells")[0])
+    alg = BYTES_PER_CELL["f32c"] * cells
+    srcs = traffic_sources(here)
+    gap_med = statistics.median(run) if run else float("nan")
+    dur_med = statistics.median(dur) if dur else float("nan")
+    with open(os.path.join(here, "profiles", "ensemble_kernel_traffic.json"), "w") as f:
+        json.dump({"note": "HBM bytes per launch of the batched lane-shift kernel on the 256-instance ensemble "
+                           "(sides 64..512, compensated FP32), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
+                           f"(separate runs) scaled by the 1 GiB copyBuffer (FETCH x{f_scale:.3f}, WRITE "
+                           f"x{w_scale:.3f}); launch gaps from the kernel trace.",
+                   "kernel_sources": srcs, "kernel_sources_sha256": sources_digest(here, srcs),
+                   "bytes_per_launch": {kname: traffic} if traffic else {},
+                   "launch_gap_us_median": gap_med, "launch_gap_us_mean": gap_mean, "launch_gap_us_max": gap_max,
+                   "launch_us_median": dur_med}, f, indent=1)
+    cmds = "\n".join(PROFILE_COMMANDS[k] for k in ("etrace", "efetch", "ewrite"))
+    tr = (f"{(traffic['read'] + traffic['write']) / 1e6:.1f} MB per launch (read {traffic['read'] / 1e6:.1f}, "
+          f"write {traffic['write'] / 1e6:.1f}; FETCH_SIZE {traffic['fetch_kib']:.0f} KiB, WRITE_SIZE "
+          f"{traffic['write_kib']:.0f} KiB), {(traffic['read'] + traffic['write']) / alg:.3f} of the algorithmic "
+          f"{alg / 1e6:.1f} MB" if traffic else "not collected")
+    with open(os.path.join(here, "profiles", "ensemble_kernels_256.md"), "w") as f:
+        f.write("# Ensemble kernels: 256 instances (sides 64..512), compensated FP32 (rocprofv3)\n\n"
+                "Commands (from /tmp with TMPDIR=/tmp; $R = repository root, $P = output folder):\n\n"
+                f"```\n{cmds}\n```\n\nSummary written by `python bench.py --summarize-profiles $P`.\n\n"
+                f"## Kernel trace\n\n{table}\n\n"
+                f"`{kname}` steps every instance 4 steps per launch (graph-replayed, 48 steps per graph); "
+                "`fused_dpp_kernel<float, true, 2, 4>` is the loop of single-instance launches in the same shape "
+                "and `fused_dpp_kernel` / `step_kernel` rows of other shapes belong to the default-shape loop.\n\n"
+                f"## Launches of the batched kernel\n\n"
+                f"- median launch: {dur_med:.1f} us; gaps between consecutive launches (end to next start, "
+                f"gaps under 100 us, {len(run)} gaps): median {gap_med:.2f} us, mean {gap_mean:.2f} us, 90th "
+                f"percentile {gap_p90:.2f} us, largest {gap_max:.2f} us; the mean gap is "
+                f"{100 * gap_mean / (dur_med + gap_mean):.2f}% of the time per launch.\n"
+                f"- HBM traffic: {tr}.\n"
+                f"- bench.py in the same run: batched {ens['batched_Gcell_s']:.1f} Gcell/s, loop in the same shape "
+                f"{ens['loop_same_shape_Gcell_s']:.1f}, loop in the default shape "
+                f"{ens['loop_default_shape_Gcell_s']:.1f} Gcell/s.\n")
+    return {"launch_gap_us_median": gap_med, "launch_gap_us_mean": gap_mean, "launch_gap_us_max": gap_max,
+            "launch_us_median": dur_med, "traffic": traffic}
+
+
+def summarize_adjoint(pdir):
+    """profiles/adjoint_kernels.md and profiles/adjoint_kernel_traffic.json from
+    the atrace/, afetch/ and awrite/ runs: the adjoint kernel on the 512^2
+    gradient workload and at 4096^2, and its HBM traffic at 4096^2."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(pdir, "atrace_bench.json")) as f:
+        adj = json.loads(f.read().strip().splitlines()[-1])["adjoint"]
+    rows = _trace_rows(pdir, "atrace")
+    table, agg = _stats_table(rows, lambda k: k.startswith(("adjoint_kernel", "slots_reduce", "step_kernel<double",
+                                                             "fused_dpp_kernel<double", "eig_backward")))
+    fetch, write = _counter_means(pdir, "afetch"), _counter_means(pdir, "awrite")
+    ck, f_scale, w_scale = _copy_calibration(fetch, write)
+    keys = [k for k in fetch if k[0].startswith("adjoint_kernel<double")]
+    k = max(keys, key=lambda x: x[1])                 # the 4096^2 dispatches
+    rd, wr = fetch[k] * 1024 * f_scale, write.get(k, 0.0) * 1024 * w_scale
+    n = 4096
+    alg = ADJOINT_BYTES_PER_CELL * n * n
+    big = [d for (name, grid), d in agg.items() if name == k[0] and grid == k[1]]
+    avg = sum(big[0]) / len(big[0]) if big else float("nan")
+    srcs = [os.path.join("paper_2006_01748_amd", "build.py")] + sorted(
+        os.path.join("paper_2006_01748_amd", "csrc", x) for x in ("ggfv_adjoint.hip", "ggfv_dpp.hpp",
+                                                                  "ggfv_step_common.hpp", "ggfv_internal.hpp"))
+    traffic = {"kernel": k[0], "read": rd, "write": wr, "fetch_kib": fetch[k], "write_kib": write.get(k, 0.0)}
+    with open(os.path.join(here, "profiles", "adjoint_kernel_traffic.json"), "w") as f:
+        json.dump({"note": "HBM bytes per adjoint step on the 4096^2 layered-tissue grid (FP64), from rocprofv3 "
+                           "--pmc FETCH_SIZE and WRITE_SIZE (separate runs) scaled by the 1 GiB copyBuffer "
+                           f"(FETCH x{f_scale:.3f}, WRITE x{w_scale:.3f}).",
+                   "kernel_sources": srcs, "kernel_sources_sha256": sources_digest(here, srcs),
+                   "bytes_per_launch": {"adjoint_kernel<double>": traffic}}, f, indent=1)
+    cmds = "\n".join(PROFILE_COMMANDS[x] for x in ("atrace", "afetch", "awrite"))
+    with open(os.path.join(here, "profiles", "adjoint_kernels.md"), "w") as f:
+        f.write("# Adjoint kernels: 512^2 gradient workload and 4096^2 adjoint steps, FP64 (rocprofv3)\n\n"
+                "Commands (from /tmp with TMPDIR=/tmp; $R = repository root, $P = output folder):\n\n"
+                f"```\n{cmds}\n```\n\nSummary written by `python bench.py --summarize-profiles $P`.\n\n"
+                f"## Kernel trace\n\n{table}\n\n"
+                "The smaller `adjoint_kernel` grid is the 512^2 gradient workload (5000 adjoint steps), the larger "
+                "one the 4096^2 reverse sweeps of 4 and 12 steps.  `step_kernel<double, false, 1, 64>` recomputes "
+                "each 512^2 segment; the forward runs in the default shape.\n\n"
+                "## 4096^2 adjoint step\n\n"
+                f"- trace average {avg:.1f} us; live HIP events in the same run "
+                f"{adj['adjoint_kernel_4096']['adjoint_step_us']:.1f} us per step.\n"
+                f"- algorithmic bytes {alg / 1e6:.1f} MB (144 B per cell: read x, lam', a, b, c and g; write lam and "
+                f"g), {alg / (avg * 1e-6) / 1e9:.0f} GB/s over the trace average.\n"
+                f"- counters: FETCH_SIZE {fetch[k]:.0f} KiB, WRITE_SIZE {write.get(k, 0.0):.0f} KiB per dispatch; "
+                f"scaled read {rd / 1e6:.1f} MB, write {wr / 1e6:.1f} MB: {(rd + wr) / alg:.3f} of the algorithmic "
+                f"bytes (calibration: FETCH x{f_scale:.3f}, WRITE x{w_scale:.3f} from the 1 GiB copyBuffer).\n"
+                f"- bench.py in the same run: backward / forward = {adj['backward_over_forward']:.2f} (forward in "
+                f"the default shape), {adj['backward_over_forward_single_step']:.2f} (single-step forward).\n")
+    return {"adjoint_4096_us": avg, "traffic": traffic}
+
+
 def summarize_profiles(pdir):
     """Write profiles/*.md and profiles/step_kernel_traffic.json from the CSV
     output of PROFILE_COMMANDS (trace/, fetch/, write/ and trace_bench.json
@@ -848,6 +1092,10 @@ def summarize_profiles(pdir):
     alone)."""
     if os.path.isdir(os.path.join(pdir, "valu")):
         print(json.dumps({"valu": summarize_valu(pdir)}, indent=1))
+    if os.path.isdir(os.path.join(pdir, "etrace")):
+        print(json.dumps({"ensemble": summarize_ensemble(pdir)}, indent=1))
+    if os.path.isdir(os.path.join(pdir, "atrace")):
+        print(json.dumps({"adjoint": summarize_adjoint(pdir)}, indent=1))
     if not os.path.isdir(os.path.join(pdir, "trace")):
         if os.path.isdir(os.path.join(pdir, "trace3")):
             print(json.dumps({"three_d": summarize_3d(pdir, "trace3", "fetch3", "write3", "trace3_bench.json")},
@@ -919,34 +1167,13 @@ def summarize_profiles(pdir):
                 "(headline shapes): " + ", ".join(f"{v} {us:.1f} us" for v, us in live.items()) + ".\n\n"
                 "## HBM traffic per dispatch (--pmc, one counter per run)\n\n"
                 f"Calibration: the 1 GiB `__amd_rocclr_copyBuffer` of the copy-ceiling probe reads "
-                f"FETCH_SIZE = {fetch[ck]:.0f} KiB and WRITE_SIZE = {write[ck]:.0f} KiB per dispatch, so "
+                f"FETCH_SIZE = {ck[1]:.0f} KiB and WRITE_SIZE = {ck[2]:.0f} KiB per dispatch, so "
                 f"FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.  Algorithmic bytes: "
                 "each launch reads u, v, w, a, b, c and writes u, v, w once (the compensated state reads "
                 "and writes the low words too), whatever the number of steps it fuses.\n\n"
                 "| variant | kernel | rows | calls (trace) | average (us) | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | "
                 "scaled read (MB) | scaled write (MB) | algorithmic read / write (MB) | traffic / algorithmic |\n"
                 "|---|---|---|---|---|---|---|---|---|---|---|\n" + "\n".join(rows_md) + "\n")
-    ens = bench.get("ensemble") or {}
-    with open(os.path.join(here, "profiles", "batch_step_kernel_ensemble_256.md"), "w") as f:
-        f.write("# Batched ensemble kernels, 256 instances (sides 64..512), compensated FP32 (rocprofv3)\n\n"
-                f"Command (from /tmp with TMPDIR=/tmp):\n\n```\n{PROFILE_COMMANDS['trace']}\n```\n\n"
-                "## Kernel trace (--stats)\n\n" + head +
-                stat_rows(lambda k: k.startswith("step_batch_kernel") or k.startswith("step_kernel<float, true, 2, 64>"))
-                + "\n\n`step_batch_kernel` runs every instance of the ensemble in one launch (graph-replayed); "
-                "`step_kernel<float, true, 2, 64>` is the loop of single-instance launches it is compared "
-                "with.  bench.py in the same run: "
-                f"batched {ens.get('batched_Gcell_s', float('nan')):.1f} Gcell/s, loop "
-                f"{ens.get('loop_of_single_launches_Gcell_s', float('nan')):.1f} Gcell/s.\n")
-    adj = bench.get("adjoint") or {}
-    with open(os.path.join(here, "profiles", "adjoint_kernels_512_smooth.md"), "w") as f:
-        f.write("# Adjoint workload, 512x512 smooth anisotropic tensor, 5000 steps, FP64 (rocprofv3)\n\n"
-                f"Command (from /tmp with TMPDIR=/tmp):\n\n```\n{PROFILE_COMMANDS['trace']}\n```\n\n"
-                "## Kernel trace (--stats)\n\n" + head +
-                stat_rows(lambda k: k.startswith(("adjoint_kernel", "slots_reduce", "eig_backward", "zero_kernel"))
-                          or k.startswith("step_kernel<double, false, 1, 64>"))
-                + "\n\n`step_kernel<double, false, 1, 64>` is the 512^2 forward step (checkpointed forward and "
-                "the recomputation of each segment in the reverse sweep).  bench.py in the same run: "
-                f"backward / forward = {adj.get('backward_over_forward', float('nan')):.2f}.\n")
     fdir = os.path.join(pdir, "fronts")
     if os.path.isdir(fdir):
         fstats = {}
@@ -994,7 +1221,11 @@ def main():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--only-3d", action="store_true",
                     help="time the three-dimensional step and the copy ceiling only (for its profiles)")
-    ap.add_argument("--fronts-t", type=float, default=0.5, help="simulated time of the invasion sweep")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="time the gradient workload, the 4096^2 adjoint step and the copy ceiling only")
+    ap.add_argument("--only-ensemble", action="store_true",
+                    help="time the ensemble (in the benchmark's batched launch shape) and the copy ceiling only")
+    ap.add_argument("--fronts-t", type=float, default=2.0, help="simulated time of the invasion sweep")
     ap.add_argument("--no-tune", action="store_true", help="time the default single-step shape only")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner for the headline shape instead of the fixed shapes")
@@ -1026,6 +1257,15 @@ def main():
     if args.only_3d:
         three = time_3d(pk, torch)
         print(json.dumps({"three_d": three, "copy_ceiling_GBs": copy_ceiling(torch)}), flush=True)
+        return
+    if args.only_ensemble:
+        ens = time_ensemble(pk, torch, force=tuple(int(x) for x in args.ensemble_tuning.split(","))
+                            if args.ensemble_tuning else None)
+        print(json.dumps({"ensemble": ens, "copy_ceiling_GBs": copy_ceiling(torch)}), flush=True)
+        return
+    if args.only_adjoint:
+        adj = time_adjoint(pk, torch)
+        print(json.dumps({"adjoint": adj, "copy_ceiling_GBs": copy_ceiling(torch)}), flush=True)
         return
     log(f"generating {args.n}x{args.n} layered-tissue workload")
     w = wl.cfg2(n=args.n)
@@ -1063,7 +1303,9 @@ def main():
         log("timing the gradient workload (forward with checkpoints, reverse sweep)")
         adj = time_adjoint(pk, torch)
         log(f"  backward/forward = {adj['backward_over_forward']:.2f} (fused forward), "
-            f"{adj['backward_over_forward_single_step']:.2f} (single-step forward)")
+            f"{adj['backward_over_forward_single_step']:.2f} (single-step forward); adjoint step at 4096^2 "
+            f"{adj['adjoint_kernel_4096']['adjoint_step_us']:.1f} us, "
+            f"{adj['roofline']['achieved']:.0f} GB/s algorithmic")
     adaptive = None
     if not args.no_adaptive and "f64" in variants:
         log("timing adaptive stepping (device-side step size, FP64)")

@@ -7,8 +7,8 @@
 //   lam(m)   = ((dF/dx)^T lam')(m)
 //   g_A(m)  += ((dF/d(a,b,c))^T lam')(m)
 //   g_p     += (dF/dp)^T lam'    (p = delta1, rho2, Delta2, rho3, delta3)
-// in gather form: each thread owns one cell and collects the contributions of
-// every face flux that reads a value of that cell.  Writing s_f for the loss
+// in gather form: each lane owns a cell of the row being swept and collects the
+// contributions of every face flux that reads a value of that cell.  Writing s_f for the loss
 // sensitivity of a face flux,
 //   x-face (l, l+1): s = dt*idx*(lamW_l - lamW_r),  sv = dt*Delta2*idx*(lamV_l - lamV_r)
 //   y-face (l, l+1): the same with idy,
@@ -29,19 +29,20 @@
 // twice).
 //
 // Memory: reads x^k (3), lam' (3), a, b, c (3), g (3) and writes lam (3), g (3):
-// 18 values per cell-update.  Neighbour reuse goes through L1/L2.  The five
-// scalar partial sums are folded per block in a fixed order and added into that
-// block's own slot (no atomics), so repeated sweeps give identical bits.
+// 18 values per cell-update, each read once per strip (plus a halo row above
+// and below the strip and a halo column on each side).  The five scalar partial
+// sums are folded per workgroup in a fixed order and added into that
+// workgroup's own slot (no atomics), so repeated sweeps give identical bits.
 
 #include <cmath>
 
-#include "ggfv_internal.hpp"
+#include "ggfv_dpp.hpp"
+#include "ggfv_step_common.hpp"
 
 namespace ggfv {
 namespace {
 
-constexpr int kAdjBX = 64;
-constexpr int kAdjBY = 4;
+constexpr int kAdjCols = 62;      // output columns of a one-wave strip (64 lanes, one halo lane each side)
 
 template <typename T>
 struct AdjArgs {
@@ -56,133 +57,189 @@ struct AdjArgs {
     T d1, r2, D2, r3, d3;
 };
 
-template <typename T>
-__global__ __launch_bounds__(kAdjBX *kAdjBY) void adjoint_kernel(AdjArgs<T> A)
+// Streaming sweep: one wave per workgroup owns a strip of 62 columns (lane l
+// holds column x0 - 1 + l; lanes 0 and 63 only supply neighbour values) and
+// `rows` rows, and marches up it.  At the row-j iteration the lanes hold rows
+// j and j+1 of the fields read at y-neighbours (lam_w', lam_v', w, u, v, c, b)
+// and row j of the rest (a, lam_u', g); x-neighbours come through DPP lane
+// shifts.  Every face quantity is evaluated once, by the cell west of the
+// x-face (and handed east by a shift) or south of the y-face (and carried in
+// registers to the next row): the face sensitivities of lam_w' and lam_v', the
+// face coefficients, the mobility, the differences of w and v, and b times the
+// face-sensitivity sums of a row.  The expressions and their operands are those
+// of the per-cell formulas above, so lam and g do not depend on the strips.
+// OFF32: every plane spans less than 4 GiB, so a cell's byte offset from its
+// plane's base fits 32 bits and one offset register serves every field (the
+// bases stay scalar).
+template <typename T, bool OFF32>
+__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs<T> A, int rows, int nsy)
 {
-    const int i = blockIdx.x * kAdjBX + threadIdx.x;
-    const int j = blockIdx.y * kAdjBY + threadIdx.y;
+    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    const int sx = lid / nsy, sy = lid - sx * nsy;
+    const int lane = threadIdx.x;
     const int nx = A.nx, ny = A.ny;
-    const bool inside = (i < nx) && (j < ny);
+    const int i = sx * kAdjCols - 1 + lane;
+    const int ic = min(max(i, 0), nx - 1);
+    const bool out_lane = lane >= 1 && lane <= kAdjCols && i < nx;
+    const bool hw = i > 0, he = i + 1 < nx;
+    const int j0 = sy * rows, j1 = min(j0 + rows, ny);
+    const size_t P = A.pitch;
+    const T zero = T(0), half = T(0.5), one = T(1), two = T(2);
+    const T dtx = A.dt * A.idx, dty = A.dt * A.idy;
+    const T dvx = A.dt * A.D2 * A.idx, dvy = A.dt * A.D2 * A.idy;
+    auto at = [&](const T *p, int r) -> const T * {
+        if constexpr (OFF32)
+            return reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) +
+                                               ((unsigned)r * (unsigned)P + (unsigned)ic) * (unsigned)sizeof(T));
+        else
+            return p + ((size_t)r * P + ic);
+    };
+    auto ld = [&](const T *p, int r) { return *at(p, r); };
+    auto mut = [&](T *p, int r) { return const_cast<T *>(at(p, r)); };
+
+    // east-face sensitivity of lam_w' in a row and the row's sum over both x-faces
+    auto xfaces = [&](T L, T &sxw, T &sxe) {
+        const T Le = from_right(L);
+        const T F = dtx * (L - Le);
+        const T Fw = from_left(F);
+        sxw = hw ? Fw : zero;
+        sxe = he ? F : zero;
+    };
+
+    // rows j0-1 (clamped; its faces are masked off at j0 = 0) and j0
+    const int jm = max(j0 - 1, 0);
+    const T Lm = ld(A.lw1, jm), LVm = ld(A.lv1, jm), Wm0 = ld(A.w, jm), Um = ld(A.u, jm), Vm = ld(A.v, jm);
+    const T Cm = ld(A.c, jm), Bm = ld(A.b, jm);
+    T L0 = ld(A.lw1, j0), LV0 = ld(A.lv1, j0), W0 = ld(A.w, j0), U0 = ld(A.u, j0), V0 = ld(A.v, j0);
+    T C0 = ld(A.c, j0), B0 = ld(A.b, j0);
+    T Wm = Wm0;
+    T sxw_m, sxe_m, sxw0, sxe0;
+    xfaces(Lm, sxw_m, sxe_m);
+    xfaces(L0, sxw0, sxe0);
+    T Qm = Bm * (sxw_m + sxe_m);
+    T Q0 = B0 * (sxw0 + sxe0);
+    // the face between the previous row and the current one
+    T Fy_s = dty * (Lm - L0);
+    T HC_s = half * (Cm + C0) * A.idy;
+    T GWy_s = half * (W0 - Wm0) * A.idy;
+    T SVy_s = dvy * (LVm - LV0);
+    T MN_s = one - half * (Um + U0);
+    T DVy_s = V0 - Vm;
     double part[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
-    if (inside) {
-        const int im = max(i - 1, 0), ip = min(i + 1, nx - 1);
-        const int jm = max(j - 1, 0), jp = min(j + 1, ny - 1);
-        const bool hw = i > 0, he = i + 1 < nx, hs = j > 0, hn = j + 1 < ny;
-        const size_t P = A.pitch;
-        auto at = [&](const T *p, int ii, int jj) { return p[(size_t)jj * P + ii]; };
-        const T zero = T(0), half = T(0.5), one = T(1), two = T(2);
+    for (int j = j0; j < j1; ++j) {
+        const int jp = min(j + 1, ny - 1);
+        const bool hs = j > 0, hn = j + 1 < ny;
+        const T Ln = ld(A.lw1, jp), LVn = ld(A.lv1, jp), Wn = ld(A.w, jp), Un = ld(A.u, jp), Vn = ld(A.v, jp);
+        const T Cn = ld(A.c, jp), Bn = ld(A.b, jp);
+        const T a0 = ld(A.a, j), LU = ld(A.lu1, j);
 
-        // adjoint values on the 3x3 neighbourhood (clamped; absent faces are zeroed below)
-        const T L00 = at(A.lw1, i, j);
-        const T Lw0 = at(A.lw1, im, j), Le0 = at(A.lw1, ip, j);
-        const T L0s = at(A.lw1, i, jm), L0n = at(A.lw1, i, jp);
-        const T Lws = at(A.lw1, im, jm), Les = at(A.lw1, ip, jm);
-        const T Lwn = at(A.lw1, im, jp), Len = at(A.lw1, ip, jp);
+        // row j: x-neighbours
+        const T ae = from_right(a0);
+        const T HA = half * (a0 + ae) * A.idx;              // (a_i + a_i+1)/2 idx, east face
+        const T HAw = from_left(HA);
+        const T We = from_right(W0), Ww = from_left(W0);
+        const T GW = half * (We - W0) * A.idx;
+        const T GWw = from_left(GW);
+        const T Ue = from_right(U0);
+        const T me = one - half * (U0 + Ue);
+        const T mw = from_left(me);
+        const T Ve = from_right(V0);
+        const T DV = Ve - V0;
+        const T DVw = from_left(DV);
+        const T LVe = from_right(LV0);
+        const T SV = dvx * (LV0 - LVe);
+        const T SVw = from_left(SV);
+        const T svw = hw ? SVw : zero;
+        const T sve = he ? SV : zero;
+        const T GX = me * (DV * A.idx);
+        const T GXl = from_left(GX);
 
-        // sums of the loss sensitivities of a cell's two x-faces (row r) and two y-faces (col q)
-        auto SXrow = [&](T Lm, T L0, T Lp) {
-            return (hw ? A.dt * A.idx * (Lm - L0) : zero) + (he ? A.dt * A.idx * (L0 - Lp) : zero);
-        };
-        auto SYcol = [&](T Ls, T L0, T Ln) {
-            return (hs ? A.dt * A.idy * (Ls - L0) : zero) + (hn ? A.dt * A.idy * (L0 - Ln) : zero);
-        };
-        const T sx_w = hw ? A.dt * A.idx * (Lw0 - L00) : zero;   // face (i-1, i)
-        const T sx_e = he ? A.dt * A.idx * (L00 - Le0) : zero;   // face (i, i+1)
-        const T sy_s = hs ? A.dt * A.idy * (L0s - L00) : zero;   // face (j-1, j)
-        const T sy_n = hn ? A.dt * A.idy * (L00 - L0n) : zero;   // face (j, j+1)
-        const T SX0 = sx_w + sx_e;
-        const T SXs = SXrow(Lws, L0s, Les);                       // row j-1 (used only if j > 0)
-        const T SXn = SXrow(Lwn, L0n, Len);                       // row j+1 (used only if j+1 < ny)
+        // row j+1: its x-faces; the face between rows j and j+1
+        T sxw_n, sxe_n;
+        xfaces(Ln, sxw_n, sxe_n);
+        const T Qn = Bn * (sxw_n + sxe_n);
+        const T Fy_n = dty * (L0 - Ln);
+        const T HC_n = half * (C0 + Cn) * A.idy;
+        const T GWy_n = half * (Wn - W0) * A.idy;
+        const T SVy_n = dvy * (LV0 - LVn);
+        const T MN_n = one - half * (U0 + Un);
+        const T DVy_n = Vn - V0;
+
+        const T sy_s = hs ? Fy_s : zero, sy_n = hn ? Fy_n : zero;
+        const T svs = hs ? SVy_s : zero, svn = hn ? SVy_n : zero;
+        const T SX0 = sxw0 + sxe0;
         const T SY0 = sy_s + sy_n;
-        const T SYw = SYcol(Lws, Lw0, Lwn);                       // column i-1 (used only if i > 0)
-        const T SYe = SYcol(Les, Le0, Len);                       // column i+1 (used only if i+1 < nx)
+        const T P0 = B0 * SY0;
+        const T Pw = from_left(P0), Pe = from_right(P0);
 
-        const T W0 = at(A.w, i, j), Ww = at(A.w, im, j), We = at(A.w, ip, j);
-        const T Ws = at(A.w, i, jm), Wn = at(A.w, i, jp);
-        const T a0 = at(A.a, i, j), aw = at(A.a, im, j), ae = at(A.a, ip, j);
-        const T c0 = at(A.c, i, j), cs = at(A.c, i, jm), cn = at(A.c, i, jp);
-        const T b0 = at(A.b, i, j), bw = at(A.b, im, j), be = at(A.b, ip, j);
-        const T bs = at(A.b, i, jm), bn = at(A.b, i, jp);
-        const T U0 = at(A.u, i, j), Uw = at(A.u, im, j), Ue = at(A.u, ip, j);
-        const T Us = at(A.u, i, jm), Un = at(A.u, i, jp);
-        const T V0 = at(A.v, i, j), Vw = at(A.v, im, j), Ve = at(A.v, ip, j);
-        const T Vs = at(A.v, i, jm), Vn = at(A.v, i, jp);
-        const T LU = at(A.lu1, i, j);
-        const T LV0 = at(A.lv1, i, j), LVw = at(A.lv1, im, j), LVe = at(A.lv1, ip, j);
-        const T LVs = at(A.lv1, i, jm), LVn = at(A.lv1, i, jp);
-
-        // acid: diagonal part of the face fluxes
-        T lw = L00 * (one - A.dt * A.d3) - A.dt * A.d1 * U0 * LU;
-        lw += sx_w * (half * (aw + a0) * A.idx) - sx_e * (half * (a0 + ae) * A.idx);
-        lw += sy_s * (half * (cs + c0) * A.idy) - sy_n * (half * (c0 + cn) * A.idy);
-        // acid: cross terms through the tangential differences of neighbouring cells
-        T cy = (hs ? bs * SXs : zero) - (hn ? bn * SXn : zero);
-        if (j == ny - 1) cy += b0 * SX0;
-        if (j == 0) cy -= b0 * SX0;
-        T cx = (hw ? bw * SYw : zero) - (he ? be * SYe : zero);
-        if (i == nx - 1) cx += b0 * SY0;
-        if (i == 0) cx -= b0 * SY0;
+        // acid
+        T lw = L0 * (one - A.dt * A.d3) - A.dt * A.d1 * U0 * LU;
+        lw += sxw0 * HAw - sxe0 * HA;
+        lw += sy_s * HC_s - sy_n * HC_n;
+        T cy = (hs ? Qm : zero) - (hn ? Qn : zero);
+        if (j == ny - 1) cy += Q0;
+        if (j == 0) cy -= Q0;
+        T cx = (hw ? Pw : zero) - (he ? Pe : zero);
+        if (i == nx - 1) cx += P0;
+        if (i == 0) cx -= P0;
         lw += half * A.hy * cy + half * A.hx * cx;
 
         // tensor gradients
-        const T ty0 = (Wn - Ws) * A.hy, tx0 = (We - Ww) * A.hx;
-        const T dga = sx_w * (half * (W0 - Ww) * A.idx) + sx_e * (half * (We - W0) * A.idx);
-        const T dgc = sy_s * (half * (W0 - Ws) * A.idy) + sy_n * (half * (Wn - W0) * A.idy);
+        const T ty0 = (Wn - Wm) * A.hy, tx0 = (We - Ww) * A.hx;
+        const T dga = sxw0 * GWw + sxe0 * GW;
+        const T dgc = sy_s * GWy_s + sy_n * GWy_n;
         const T dgb = half * ty0 * SX0 + half * tx0 * SY0;
 
-        // tumour cells: mobility fluxes
-        const T svw = hw ? A.dt * A.D2 * A.idx * (LVw - LV0) : zero;
-        const T sve = he ? A.dt * A.D2 * A.idx * (LV0 - LVe) : zero;
-        const T svs = hs ? A.dt * A.D2 * A.idy * (LVs - LV0) : zero;
-        const T svn = hn ? A.dt * A.D2 * A.idy * (LV0 - LVn) : zero;
-        const T mw = one - half * (Uw + U0), me = one - half * (U0 + Ue);
-        const T ms = one - half * (Us + U0), mn = one - half * (U0 + Un);
-        T lv = LV0 * (one + A.dt * A.r2 * (one - two * V0)) + A.dt * A.r3 * L00;
-        lv += svw * mw * A.idx - sve * me * A.idx + svs * ms * A.idy - svn * mn * A.idy;
+        // tumour cells
+        T lv = LV0 * (one + A.dt * A.r2 * (one - two * V0)) + A.dt * A.r3 * L0;
+        lv += svw * mw * A.idx - sve * me * A.idx + svs * MN_s * A.idy - svn * MN_n * A.idy;
         T lu = LU * (one + A.dt * (one - two * U0 - A.d1 * W0));
-        lu += svw * (-half * (V0 - Vw) * A.idx) + sve * (-half * (Ve - V0) * A.idx);
-        lu += svs * (-half * (V0 - Vs) * A.idy) + svn * (-half * (Vn - V0) * A.idy);
+        lu += svw * (-half * DVw * A.idx) + sve * (-half * DV * A.idx);
+        lu += svs * (-half * DVy_s * A.idy) + svn * (-half * DVy_n * A.idy);
 
-        const size_t o = (size_t)j * P + i;
-        A.lu[o] = lu;
-        A.lv[o] = lv;
-        A.lw[o] = lw;
-        A.ga[o] = A.ga[o] + dga;
-        A.gb[o] = A.gb[o] + dgb;
-        A.gc[o] = A.gc[o] + dgc;
+        if (out_lane) {
+            *mut(A.lu, j) = lu;
+            *mut(A.lv, j) = lv;
+            *mut(A.lw, j) = lw;
+            *mut(A.ga, j) = *at(A.ga, j) + dga;
+            *mut(A.gb, j) = *at(A.gb, j) + dgb;
+            *mut(A.gc, j) = *at(A.gc, j) + dgc;
+            // scalar gradients (FP64 accumulation); divV at x^k in the forward order
+            const T GXe = he ? GX : zero;
+            const T GXw = hw ? GXl : zero;
+            const T GYn = hn ? MN_n * (DVy_n * A.idy) : zero;
+            const T GYs = hs ? MN_s * (DVy_s * A.idy) : zero;
+            const T divV = (GXe - GXw) * A.idx + (GYn - GYs) * A.idy;
+            const double dt = double(A.dt);
+            part[0] += -dt * double(U0) * double(W0) * double(LU);
+            part[1] += dt * double(V0) * (1.0 - double(V0)) * double(LV0);
+            part[2] += dt * double(divV) * double(LV0);
+            part[3] += dt * double(V0) * double(L0);
+            part[4] += -dt * double(W0) * double(L0);
+        }
 
-        // scalar gradients (FP64 accumulation); divV at x^k in the forward order
-        const T GXe = he ? me * ((Ve - V0) * A.idx) : zero;
-        const T GXw = hw ? mw * ((V0 - Vw) * A.idx) : zero;
-        const T GYn = hn ? mn * ((Vn - V0) * A.idy) : zero;
-        const T GYs = hs ? ms * ((V0 - Vs) * A.idy) : zero;
-        const T divV = (GXe - GXw) * A.idx + (GYn - GYs) * A.idy;
-        const double dt = double(A.dt);
-        part[0] = -dt * double(U0) * double(W0) * double(LU);
-        part[1] = dt * double(V0) * (1.0 - double(V0)) * double(LV0);
-        part[2] = dt * double(divV) * double(LV0);
-        part[3] = dt * double(V0) * double(L00);
-        part[4] = -dt * double(W0) * double(L00);
+        // move up one row
+        Wm = W0;
+        L0 = Ln; LV0 = LVn; W0 = Wn; U0 = Un; V0 = Vn; C0 = Cn; B0 = Bn;
+        sxw0 = sxw_n; sxe0 = sxe_n;
+        Qm = Q0; Q0 = Qn;
+        Fy_s = Fy_n; HC_s = HC_n; GWy_s = GWy_n; SVy_s = SVy_n; MN_s = MN_n; DVy_s = DVy_n;
     }
 
-    // block reduction of the five partial sums in a fixed order
-    __shared__ double sm[kAdjBX * kAdjBY / 64][5];
-    const int tid = threadIdx.y * kAdjBX + threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
+    // wave reduction of the five partial sums in a fixed order, into the
+    // workgroup's own slot
 #pragma unroll
     for (int s = 0; s < 5; ++s)
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) part[s] += __shfl_xor(part[s], off, 64);
-    if (lane == 0)
+    if (lane < 5) {
+        double r = part[0];
 #pragma unroll
-        for (int s = 0; s < 5; ++s) sm[wv][s] = part[s];
-    __syncthreads();
-    if (tid < 5) {
-        double r = 0.0;
-        for (int k = 0; k < kAdjBX * kAdjBY / 64; ++k) r += sm[k][tid];
-        double *slot = A.slots + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 5;
-        slot[tid] = slot[tid] + r;
+        for (int s = 1; s < 5; ++s)
+            if (lane == s) r = part[s];
+        double *slot = A.slots + (size_t)lid * 5;
+        slot[lane] = slot[lane] + r;
     }
 }
 
@@ -232,6 +289,10 @@ __global__ void eig_backward_kernel(const S *__restrict__ l1, const S *__restric
     }
 }
 
+}  // namespace
+int adjoint_rows(const ggfv_ctx *ctx);
+namespace {
+
 template <typename T>
 hipError_t launch_adjoint_typed(ggfv_ctx *ctx, const void *x, const void *lam_in, void *lam_out,
                                 void *g, double *slots, double dt)
@@ -273,16 +334,34 @@ hipError_t launch_adjoint_typed(ggfv_ctx *ctx, const void *x, const void *lam_in
     A.D2 = T(ctx->prm.Delta2);
     A.r3 = T(ctx->prm.rho3);
     A.d3 = T(ctx->prm.delta3);
-    dim3 blk(kAdjBX, kAdjBY), grd((ctx->nx + kAdjBX - 1) / kAdjBX, (ctx->ny + kAdjBY - 1) / kAdjBY);
-    hipLaunchKernelGGL(adjoint_kernel<T>, grd, blk, 0, ctx->stream, A);
+    const int rows = adjoint_rows(ctx);
+    const int nsx = (ctx->nx + kAdjCols - 1) / kAdjCols, nsy = (ctx->ny + rows - 1) / rows;
+    if (ctx->plane * sizeof(T) < (size_t(1) << 32))
+        hipLaunchKernelGGL((adjoint_kernel<T, true>), dim3(nsx * nsy), dim3(64), 0, ctx->stream, A, rows, nsy);
+    else
+        hipLaunchKernelGGL((adjoint_kernel<T, false>), dim3(nsx * nsy), dim3(64), 0, ctx->stream, A, rows, nsy);
     return hipGetLastError();
 }
 
 }  // namespace
 
+// Strip height of the adjoint sweep: the tallest strips that still give about
+// 16 waves per compute unit (taller strips re-read fewer halo rows; fewer
+// waves hide less memory latency).
+int adjoint_rows(const ggfv_ctx *ctx)
+{
+    const long nsx = (ctx->nx + kAdjCols - 1) / kAdjCols;
+    const long want = 16L * (ctx->cus > 0 ? ctx->cus : 256);
+    long nsy = (want + nsx - 1) / nsx;
+    if (nsy < 1) nsy = 1;
+    long rows = (ctx->ny + nsy - 1) / nsy;
+    return (int)(rows < 1 ? 1 : rows);
+}
+
 int adjoint_blocks(const ggfv_ctx *ctx)
 {
-    return ((ctx->nx + kAdjBX - 1) / kAdjBX) * ((ctx->ny + kAdjBY - 1) / kAdjBY);
+    const int rows = adjoint_rows(ctx);
+    return ((ctx->nx + kAdjCols - 1) / kAdjCols) * ((ctx->ny + rows - 1) / rows);
 }
 
 hipError_t launch_adjoint_step(ggfv_ctx *ctx, const void *x, const void *lam_in, void *lam_out,
