@@ -311,8 +311,14 @@ int ggfv_eig_backward(ggfv_ctx *ctx, const void *lam1, const void *lam2, const v
  * intermediate levels stay on chip, and only the last level is written, so HBM
  * traffic per step falls by that factor; a run of n steps uses n / fused_steps
  * fused launches and single steps for the remainder.
- * A new context starts with the fastest shape measured on MI355X for large
- * grids: rows_per_strip 0, fused_steps 4, lane_shift 2 (1 for GGFV_F32C).
+ * A new context starts with the shape measured fastest on MI355X for its grid
+ * size, from h4 = ny * ceil(nx / W) / (8 * compute units) (W = 248 columns for
+ * GGFV_F32, 120 otherwise: the strip height at which the 4-step lane-shift
+ * kernel's one-wave strips fill the device once): h4 >= 8 gives rows_per_strip
+ * 0, fused_steps 4, lane_shift 2 (1 for GGFV_F32C); 3 <= h4 < 8 the same with
+ * fused_steps 2; smaller grids the single-step kernel (fused_steps 1,
+ * lane_shift 0, threads 0).  On MI355X 4096^2 and 2048^2 get four steps per
+ * launch, 1024^2 two, 512^2 one.
  * Every shape gives the same results bit for bit.  EINVAL for values outside
  * these sets. */
 typedef struct {

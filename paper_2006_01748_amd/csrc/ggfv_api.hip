@@ -87,6 +87,35 @@ int ensure_staging(ggfv_ctx *ctx, int narrays = 3)
     return GGFV_OK;
 }
 
+// Default launch shape, from h4 = ny * (column strips of the 4-step lane-shift
+// kernel) / (8 * compute units): the strip height at which those one-wave
+// strips fill the device's wave slots once at two waves per SIMD (wide lanes
+// except for the compensated state).  Every level of a strip repeats a
+// pipeline fill of about 2K+2 rows, so fused launches pay only on strips that
+// are tall enough.  Measured on MI355X (FP64 / compensated FP32,
+// Gcell-updates/s: single step, 2 and 4 steps per launch): 512^2 (h4 = 1.3)
+// 39 / 23 / 15 and 31 / 23 / 15; 1024^2 (h4 = 4.5) 58 / 73 / 54 and 61 / 84 /
+// 58; 1536^2 (h4 = 9.8) 60 / 118 / 115 and 76 / 151 / 123; 2048^2 (h4 = 18)
+// 72 / 141 / 134 and 71 / 170 / 185; 4096^2 (h4 = 70) 71 / 127 / 230 and 80 /
+// 136 / 279.  Hence: h4 >= 8, four steps per launch; 3 <= h4 < 8, two;
+// otherwise the single-step kernel.
+void set_default_shape(ggfv_ctx *ctx)
+{
+    ctx->rows_per_strip = 0;
+    ctx->threads = 0;
+    ctx->fused_steps = 4;
+    ctx->lane_shift = (ctx->dtype == GGFV_F32C) ? 1 : 2;
+    const int outw = (ctx->dtype == GGFV_F32) ? 248 : 120;     // output columns of one wave, K = 4
+    const double h4 = (double)ctx->ny * ((ctx->nx + outw - 1) / outw) / (8.0 * (ctx->cus > 0 ? ctx->cus : 256));
+    if (h4 >= 8.0) return;
+    if (h4 >= 3.0) {
+        ctx->fused_steps = 2;
+        return;
+    }
+    ctx->fused_steps = 1;
+    ctx->lane_shift = 0;
+}
+
 // Copy three dense host arrays into the staging area; returns device pointers.
 int stage_in(ggfv_ctx *ctx, const void *h0, const void *h1, const void *h2, int io,
              const void *(&d)[3])
@@ -211,16 +240,13 @@ int ggfv_create(ggfv_ctx **out, int nx, int ny, double lx, double ly, int dtype,
     ctx->plane = (size_t)ctx->pitch * ny;
     ctx->elem = (dtype == GGFV_F64) ? 8 : 4;
     ctx->nfields = (dtype == GGFV_F32C) ? 6 : 3;
-    // default launch shape: the lane-shift kernels with four steps per launch,
-    // wide lanes except for the compensated state, one-round strip heights
-    ctx->fused_steps = 4;
-    ctx->lane_shift = (dtype == GGFV_F32C) ? 1 : 2;
 
     DeviceGuard g(device);
     if (g.status != hipSuccess) {
         delete ctx;
         return fail(nullptr, GGFV_EHIP, "hipSetDevice(%d) failed: %s", device, hipGetErrorString(g.status));
     }
+    set_default_shape(ctx);
     const size_t sbytes = ctx->nfields * ctx->plane * ctx->elem;
     const size_t tbytes = 3 * ctx->plane * ctx->elem;
     ctx->scratch_bytes = ((size_t)kMaxPartialBlocks * kDiagSlots + 64) * sizeof(double);

@@ -48,37 +48,22 @@ def gpu_ctx(nx, ny, dtype, params, state, abc=None, eig=None, lx=1.0, ly=1.0, ro
     return ctx
 
 
-def test_default_launch_shape_is_the_fused_lane_shift_kernel():
-    """A new context steps four levels per launch on the lane-shift kernels (wide
-    lanes except for the compensated state); several steps per launch need
-    those kernels."""
-    for dtype, lanes in (("f64", 2), ("f32", 2), ("f32c", 1)):
-        ctx = pk.Context(64, 48, dtype=dtype)
-        assert ctx.get_tuning() == {"rows_per_strip": 0, "threads": 0, "fused_steps": 4, "lane_shift": lanes}
-        with pytest.raises(pk.GGFVError) as e:
-            ctx.set_tuning(0, 64, 2, lane_shift=0)
-        assert e.value.status == pk.GGFV_EINVAL
-        ctx.close()
-
-
-# ---------------------------------------------------------------------------
-# FP64
-
-def test_f64_isotropic_disk_full_run():
-    """128^2, A = I, central disk, 2000 steps at dt = 0.2 h^2/(4 max(1, Delta2))."""
-    w = wl.cfg0()
-    ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), abc=w.abc)
-    dt = ctx.stable_dt(0.2)
-    assert dt == w.dt_closed_form
-    ctx.step(dt, w.steps)
-    got = ctx.get_state()
-    ref = oracle.run(w.u0, w.v0, w.w0, *w.abc, w.params, dt, w.steps)[:3]
-    assert rel_err(got, ref) <= 1e-12
-    assert all(np.array_equal(g, r) for g, r in zip(got, ref)), "expected bitwise agreement"
-    d = ctx.diagnostics()
-    od = oracle.diagnostics(*ref, *w.abc, w.params[2], dt)
-    assert np.allclose(d["mass"], od["mass"], rtol=1e-12, atol=0)
-    assert d["steps"] == w.steps and math.isclose(d["t"], w.steps * dt, rel_tol=1e-12)
+def test_default_launch_shape_follows_the_grid_size():
+    """A new context's launch shape: four steps per launch on the lane-shift
+    kernels (wide lanes except for the compensated state) on large grids, two
+    on mid-sized ones, the single-step kernel on small ones; several steps per
+    launch need the lane-shift kernels."""
+    for n, K in ((4096, 4), (1024, 2), (256, 1)):
+        for dtype, lanes in (("f64", 2), ("f32c", 1)):
+            ctx = pk.Context(n, n, dtype=dtype)
+            want = {"rows_per_strip": 0, "threads": 0, "fused_steps": K, "lane_shift": lanes if K > 1 else 0}
+            assert ctx.get_tuning() == want, (n, dtype, ctx.get_tuning())
+            ctx.close()
+    ctx = pk.Context(64, 48, dtype="f64")
+    with pytest.raises(pk.GGFVError) as e:
+        ctx.set_tuning(0, 64, 2, lane_shift=0)
+    assert e.value.status == pk.GGFV_EINVAL
+    ctx.close()
 
 
 @pytest.mark.parametrize("nx,ny,rows", [(300, 77, 0), (1, 50, 7), (50, 1, 0), (257, 3, 2), (64, 64, 5),
