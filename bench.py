@@ -638,10 +638,29 @@ def time_ensemble(pk, torch, count=256, steps=500, loop_steps=48, force=None):
             "speedup": batch_rate / loop_rate, "speedup_vs_default_shape_loop": batch_rate / default_rate,
             "roofline": {"bound": "hbm", "kernel": kname, "achieved": alg / (launch_us * 1e-6) / 1e9,
                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": alg / (launch_us * 1e-6) / 1e9 / PEAK_HBM_GBS, "traffic": None,
+                         "frac": alg / (launch_us * 1e-6) / 1e9 / PEAK_HBM_GBS,
+                         "traffic": measured_ensemble_traffic(kname),
                          "launch_avg_us": launch_us, "steps_per_launch": K,
                          "note": "algorithmic bytes of one launch (60 B per cell of all instances) over the "
                                  "graph-replayed run's time per launch, gaps between launches included"}}
+
+
+def measured_ensemble_traffic(kname):
+    """HBM bytes per launch of the batched kernel on the 256-instance ensemble
+    from the committed counter summary, or None (none for this kernel, or a
+    kernel source changed since)."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "ensemble_kernel_traffic.json")) as f:
+            data = json.load(f)
+        if data["kernel_sources"] != traffic_sources(here):
+            return None
+        if sources_digest(here, data["kernel_sources"]) != data.get("kernel_sources_sha256"):
+            return None
+        t = data["bytes_per_launch"][kname]
+    except (OSError, KeyError, ValueError, TypeError):
+        return None
+    return t["read"] + t["write"]
 
 
 def copy_ceiling(torch, nbytes=1 << 30, reps=20):
@@ -713,16 +732,17 @@ def cpu_baseline(w, steps, single_steps):
 # /tmp with TMPDIR=/tmp; $R is the repository root, $P an output folder.
 PROFILE_COMMANDS = {
     "trace": "timeout -k 10 500 rocprofv3 --kernel-trace --stats --output-format csv -d $P/trace -o trace "
-             "-- python3 $R/bench.py --steps 200 --warmup 12 --no-cpu-baseline --no-fronts > $P/trace_bench.json",
+             "-- python3 $R/bench.py --steps 200 --warmup 12 --no-cpu-baseline --no-fronts --no-adjoint --no-ensemble "
+             "--no-3d > $P/trace_bench.json",
     "fronts": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/fronts -o fronts "
               "-- python3 $R/bench.py --variants f64 --no-tune --steps 4 --warmup 4 --no-cpu-baseline --no-adjoint "
               "--no-ensemble --no-adaptive --no-copy-ceiling --no-3d --fronts-t 0.02 > $P/fronts_bench.json",
     "fetch": "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $P/fetch -o fetch "
              "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble "
-             "--no-adaptive --no-fronts",
+             "--no-adaptive --no-fronts --no-3d --no-host-inclusive",
     "write": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/write -o write "
              "-- python3 $R/bench.py --steps 8 --warmup 4 --no-cpu-baseline --no-adjoint --no-ensemble "
-             "--no-adaptive --no-fronts",
+             "--no-adaptive --no-fronts --no-3d --no-host-inclusive",
     # the three-dimensional kernel alone (with the copy used for calibration)
     "trace3": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/trace3 -o trace3 "
               "-- python3 $R/bench.py --only-3d > $P/trace3_bench.json",
@@ -777,7 +797,7 @@ def summarize_valu(pdir, n=4096):
     for d, c in vals.items():
         agg[meta[d][:3]].append((c, meta[d][3]))
     counters = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR")
-    rows, out = [], {}
+    rows, out, per_launch = [], {}, {}
     for v in ("f64", "f32c", "f32"):
         for label, tuning in (("single step", {"fused_steps": 1, "threads": 0}),
                               ("headline", dict(zip(("rows_per_strip", "threads", "fused_steps", "lane_shift"),
@@ -795,6 +815,9 @@ def summarize_valu(pdir, n=4096):
             util = mean["SQ_INSTS_VALU"] / (VALU_ISSUE_PER_S * us * 1e-6)
             out[f"{v}/{label}"] = {"kernel": kname, "dispatches": len(runs), "duration_us": us,
                                    "valu_per_cell_update": per["SQ_INSTS_VALU"], "valu_issue_util": util}
+            _, key = kernel_name(v, tuning)
+            per_launch[f"{v}/{key}"] = {"kernel": kname, "rows": tuning.get("rows_per_strip", 0),
+                                        "valu": mean["SQ_INSTS_VALU"]}
             rows.append(f"| {v} | {label} | {kname} | {len(runs)} | {us:.1f} | {mean['SQ_INSTS_VALU']:.4g} | "
                         f"{per['SQ_INSTS_VALU']:.1f} | {per['SQ_INSTS_SALU']:.1f} | {per['SQ_INSTS_LDS']:.2f} | "
                         f"{per['SQ_INSTS_VMEM_RD']:.2f} | {per['SQ_INSTS_VMEM_WR']:.2f} | {100 * util:.0f}% |")
@@ -812,6 +835,12 @@ def summarize_valu(pdir, n=4096):
                 "VALU / cell-update | SALU / cell-update | LDS / cell-update | VMEM reads / cell-update | "
                 "VMEM writes / cell-update | VALU issue utilisation |\n"
                 "|---|---|---|---|---|---|---|---|---|---|---|---|\n" + "\n".join(rows) + "\n")
+    srcs = traffic_sources(here)
+    with open(os.path.join(here, "profiles", "step_kernel_valu.json"), "w") as f:
+        json.dump({"note": "VALU wave instructions per dispatch (SQ_INSTS_VALU) of the 4096^2 step kernels; valid "
+                           "for the kernel sources with this digest and the strip heights given (0: library "
+                           "default).", "kernel_sources": srcs, "kernel_sources_sha256": sources_digest(here, srcs),
+                   "valu_per_launch": per_launch}, f, indent=1)
     return out
 
 

@@ -43,6 +43,9 @@ namespace ggfv {
 namespace {
 
 constexpr int kAdjCols = 62;      // output columns of a one-wave strip (64 lanes, one halo lane each side)
+// Bytes of one adjoint step's arrays above which they no longer fit the
+// last-level cache (256 MB on MI355X): streaming stores, taller strips.
+constexpr size_t kAdjCacheBytes = size_t(256) << 20;
 
 template <typename T>
 struct AdjArgs {
@@ -70,8 +73,10 @@ struct AdjArgs {
 // of the per-cell formulas above, so lam and g do not depend on the strips.
 // OFF32: every plane spans less than 4 GiB, so a cell's byte offset from its
 // plane's base fits 32 bits and one offset register serves every field (the
-// bases stay scalar).
-template <typename T, bool OFF32>
+// bases stay scalar).  NT: the step's arrays exceed the last-level cache, so
+// the outputs are written with streaming stores (nothing reads them again in
+// this step); on cache-resident grids cached stores measured faster.
+template <typename T, bool OFF32, bool NT>
 __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs<T> A, int rows, int nsy)
 {
     const int lid = xcd_local_id(blockIdx.x, gridDim.x);
@@ -133,6 +138,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs<T> A, int rows, int
         const T Ln = ld(A.lw1, jp), LVn = ld(A.lv1, jp), Wn = ld(A.w, jp), Un = ld(A.u, jp), Vn = ld(A.v, jp);
         const T Cn = ld(A.c, jp), Bn = ld(A.b, jp);
         const T a0 = ld(A.a, j), LU = ld(A.lu1, j);
+        const T GA0 = ld(A.ga, j), GB0 = ld(A.gb, j), GC0 = ld(A.gc, j);
 
         // row j: x-neighbours
         const T ae = from_right(a0);
@@ -199,12 +205,16 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs<T> A, int rows, int
         lu += svs * (-half * DVy_s * A.idy) + svn * (-half * DVy_n * A.idy);
 
         if (out_lane) {
-            *mut(A.lu, j) = lu;
-            *mut(A.lv, j) = lv;
-            *mut(A.lw, j) = lw;
-            *mut(A.ga, j) = *at(A.ga, j) + dga;
-            *mut(A.gb, j) = *at(A.gb, j) + dgb;
-            *mut(A.gc, j) = *at(A.gc, j) + dgc;
+            auto st = [&](T *p, T x) {
+                if constexpr (NT) __builtin_nontemporal_store(x, mut(p, j));
+                else *mut(p, j) = x;
+            };
+            st(A.lu, lu);
+            st(A.lv, lv);
+            st(A.lw, lw);
+            st(A.ga, GA0 + dga);
+            st(A.gb, GB0 + dgb);
+            st(A.gc, GC0 + dgc);
             // scalar gradients (FP64 accumulation); divV at x^k in the forward order
             const T GXe = he ? GX : zero;
             const T GXw = hw ? GXl : zero;
@@ -289,6 +299,9 @@ __global__ void eig_backward_kernel(const S *__restrict__ l1, const S *__restric
     }
 }
 
+// The step's arrays (18 values per cell) exceed the last-level cache.
+bool adjoint_big(const ggfv_ctx *ctx) { return 18 * ctx->plane * ctx->elem > kAdjCacheBytes; }
+
 }  // namespace
 int adjoint_rows(const ggfv_ctx *ctx);
 namespace {
@@ -336,23 +349,45 @@ hipError_t launch_adjoint_typed(ggfv_ctx *ctx, const void *x, const void *lam_in
     A.d3 = T(ctx->prm.delta3);
     const int rows = adjoint_rows(ctx);
     const int nsx = (ctx->nx + kAdjCols - 1) / kAdjCols, nsy = (ctx->ny + rows - 1) / rows;
-    if (ctx->plane * sizeof(T) < (size_t(1) << 32))
-        hipLaunchKernelGGL((adjoint_kernel<T, true>), dim3(nsx * nsy), dim3(64), 0, ctx->stream, A, rows, nsy);
+    const bool off32 = ctx->plane * sizeof(T) < (size_t(1) << 32), big = adjoint_big(ctx);
+    const dim3 grid(nsx * nsy), block(64);
+    if (off32 && big)
+        hipLaunchKernelGGL((adjoint_kernel<T, true, true>), grid, block, 0, ctx->stream, A, rows, nsy);
+    else if (off32)
+        hipLaunchKernelGGL((adjoint_kernel<T, true, false>), grid, block, 0, ctx->stream, A, rows, nsy);
     else
-        hipLaunchKernelGGL((adjoint_kernel<T, false>), dim3(nsx * nsy), dim3(64), 0, ctx->stream, A, rows, nsy);
+        hipLaunchKernelGGL((adjoint_kernel<T, false, true>), grid, block, 0, ctx->stream, A, rows, nsy);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Strip height of the adjoint sweep: the tallest strips that still give about
-// 16 waves per compute unit (taller strips re-read fewer halo rows; fewer
-// waves hide less memory latency).
+// Strip height of the adjoint sweep: the tallest strips whose one-wave
+// workgroups fill the device's resident wave slots (the kernel's occupancy
+// times the compute units) at most once, or half of them on grids beyond the
+// last-level cache.  Taller strips re-read fewer halo rows; a second, partial
+// round of waves would leave most CUs idle at its end.  Measured at 4096^2
+// (FP64): 531 us per step at half a round, 552 at one, 676 at 1.35 rounds;
+// at 512^2 one round (2-row strips) is the fastest.
 int adjoint_rows(const ggfv_ctx *ctx)
 {
+    const bool off32 = ctx->plane * ctx->elem < (size_t(1) << 32), big = adjoint_big(ctx);
+    const void *k;
+    if (ctx->dtype == GGFV_F64)
+        k = off32 ? (big ? (const void *)adjoint_kernel<double, true, true> : (const void *)adjoint_kernel<double, true, false>)
+                  : (const void *)adjoint_kernel<double, false, true>;
+    else
+        k = off32 ? (big ? (const void *)adjoint_kernel<float, true, true> : (const void *)adjoint_kernel<float, true, false>)
+                  : (const void *)adjoint_kernel<float, false, true>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64, 0) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 8;
+    }
     const long nsx = (ctx->nx + kAdjCols - 1) / kAdjCols;
-    const long want = 16L * (ctx->cus > 0 ? ctx->cus : 256);
-    long nsy = (want + nsx - 1) / nsx;
+    long slots = (long)per_cu * (ctx->cus > 0 ? ctx->cus : 256);
+    if (big) slots /= 2;
+    long nsy = slots / nsx;
     if (nsy < 1) nsy = 1;
     long rows = (ctx->ny + nsy - 1) / nsy;
     return (int)(rows < 1 ? 1 : rows);

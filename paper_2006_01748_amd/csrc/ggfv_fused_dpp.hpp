@@ -75,6 +75,7 @@ struct LaneGeom {
     int nx, ny, own, cbase, lcol, last0;
     int lo[K + 1], re[K + 1], hi[K + 1];   // per level: warm-up row, first real row, end
     bool store_ok;                         // the lane's columns are outputs of this workgroup
+    bool flip;                             // the strip sweeps downward (rows mirrored, see dpp_strip)
 };
 
 template <typename T, int CPL, int RTA, int RTC>
@@ -157,7 +158,7 @@ __device__ __forceinline__ void store_level_k(const StepArgs<T> &A, const LaneGe
 {
     constexpr bool NT = sizeof(T) == 8 || BATCH;
     if (q < g.re[K] || q >= g.hi[K] || !g.store_ok) return;
-    const size_t o = (size_t)q * A.pitch + g.cbase;
+    const size_t o = (size_t)(g.flip ? g.ny - 1 - q : q) * A.pitch + g.cbase;
     store_vec<T, CPL, NT>(A.un + o, R.KO[0]);
     store_vec<T, CPL, NT>(A.vn + o, R.KO[1]);
     store_vec<T, CPL, NT>(A.wn + o, R.KO[2]);
@@ -321,7 +322,8 @@ __device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K
         for (int k = 0; k < CPL; ++k) {
             const T ar = k + 1 < CPL ? R.ta[k + 1 < CPL ? k + 1 : k] : aRs;
             L.hA[ts][k * kWave + g.own] = half * (R.ta[k] + ar);
-            L.B[ts][k * kWave + g.own] = R.tb[k];
+            const T bneg = -R.tb[k];
+            L.B[ts][k * kWave + g.own] = g.flip ? bneg : R.tb[k];
             L.hC[tm][k * kWave + g.own] = half * (R.cprev[k] + R.tc[k]);
             R.cprev[k] = R.tc[k];
         }
@@ -332,7 +334,7 @@ __device__ __forceinline__ void lane_iter(const StepArgs<T> &A, const LaneGeom<K
     // request old-state row r+1 (clamped: rows -1 and ny load their mirrors)
     if (r + 1 <= g.last0) {
         const int row = min(max(r + 1, 0), g.ny - 1);
-        const size_t base = (size_t)row * A.pitch + g.lcol;
+        const size_t base = (size_t)(g.flip ? g.ny - 1 - row : row) * A.pitch + g.lcol;
         constexpr int w1 = pmod(PH + 1, 3), u1 = pmod(PH + 1, 2);
         load_vec<T, CPL>(A.w + base, R.W[0][w1]);
         load_vec<T, CPL>(A.u + base, R.U[0][u1]);
@@ -357,6 +359,23 @@ struct DppShape {
     static constexpr int RTC = K >= 2 ? 2 * K - 2 : 1;     // rows of the (c+c')/2 ring
 };
 
+// Strips of odd index sweep downward: row j of the grid is row ny-1-j of the
+// sweep, and b enters negated.  Mirroring the rows turns every y-face flux and
+// every y-difference into its exact negative (sums commute, differences swap
+// sign, and b*ty keeps its sign), so the update of every cell is the same
+// bits either way.  Vertically neighbouring strips then reach the halo rows
+// they share at the same time (both at the end or both at the start of their
+// sweeps), so the second read finds them in L2.
+__device__ __forceinline__ bool strip_flips(const int sy) { return (sy & 1) != 0; }
+
+// Rows [j0, j1) of strip sy, in the rows of its sweep.
+__device__ __forceinline__ void strip_rows(const int ny, const int rows, const int sy, int &j0, int &j1)
+{
+    const int p0 = sy * rows, p1 = min(ny, p0 + rows);
+    j0 = strip_flips(sy) ? ny - p1 : p0;
+    j1 = strip_flips(sy) ? ny - p0 : p1;
+}
+
 // One workgroup's strip: output columns [sx*OUTW, sx*OUTW + OUTW) of rows
 // [sy*A.rows, sy*A.rows + A.rows), K steps from A's input to A's output planes.
 template <typename T, bool COMP, int CPL, int K, bool EDGE, bool BATCH>
@@ -374,7 +393,9 @@ __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, co
     g.cbase = e0 + (int)threadIdx.x * CPL;
     g.lcol = min(max(g.cbase, 0), A.pitch - CPL);
     g.store_ok = g.cbase >= o0 && g.cbase < o0 + Sh::OUTW && g.cbase < A.pitch;
-    const int j0 = sy * A.rows, j1 = min(g.ny, j0 + A.rows);
+    g.flip = strip_flips(sy);
+    int j0, j1;
+    strip_rows(g.ny, A.rows, sy, j0, j1);
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
         g.lo[s] = max(0, j0 - (K - s) - 1);
@@ -442,7 +463,8 @@ __device__ __forceinline__ bool strip_interior(const StepArgs<T> &A, const int s
 {
     using Sh = DppShape<CPL, K>;
     const int e0 = sx * Sh::OUTW - Sh::H;
-    const int j0 = sy * A.rows, j1 = min(A.ny, j0 + A.rows);
+    int j0, j1;
+    strip_rows(A.ny, A.rows, sy, j0, j1);
     return e0 >= 1 && e0 + Sh::TXW < A.nx && j0 >= K + 2 && j1 + K < A.ny;
 }
 
