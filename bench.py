@@ -583,8 +583,10 @@ def time_ensemble(pk, torch, count=256, steps=500, loop_steps=48, force=None):
         b.set_dt(i, dts[-1])
     if force is None:
         tuned = b.autotune(trial_steps=12)
+        tuned["source"] = "batch autotuner"
     else:
-        tuned = {"threads": force[0], "rows_per_strip": force[1], "fused_steps": force[2] if len(force) > 2 else 1}
+        tuned = {"threads": force[0], "rows_per_strip": force[1], "fused_steps": force[2] if len(force) > 2 else 1,
+                 "source": "fixed (--ensemble-tuning)"}
     K = tuned["fused_steps"]
     b.set_tuning(threads=tuned["threads"], rows_per_strip=tuned["rows_per_strip"], graph_steps=48, fused_steps=K)
     b.run(48)
@@ -639,13 +641,13 @@ def time_ensemble(pk, torch, count=256, steps=500, loop_steps=48, force=None):
             "roofline": {"bound": "hbm", "kernel": kname, "achieved": alg / (launch_us * 1e-6) / 1e9,
                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": alg / (launch_us * 1e-6) / 1e9 / PEAK_HBM_GBS,
-                         "traffic": measured_ensemble_traffic(kname),
+                         "traffic": measured_ensemble_traffic(kname, tuned["rows_per_strip"]),
                          "launch_avg_us": launch_us, "steps_per_launch": K,
                          "note": "algorithmic bytes of one launch (60 B per cell of all instances) over the "
                                  "graph-replayed run's time per launch, gaps between launches included"}}
 
 
-def measured_ensemble_traffic(kname):
+def measured_ensemble_traffic(kname, rows):
     """HBM bytes per launch of the batched kernel on the 256-instance ensemble
     from the committed counter summary, or None (none for this kernel, or a
     kernel source changed since)."""
@@ -658,6 +660,8 @@ def measured_ensemble_traffic(kname):
         if sources_digest(here, data["kernel_sources"]) != data.get("kernel_sources_sha256"):
             return None
         t = data["bytes_per_launch"][kname]
+        if t.get("rows") != rows:
+            return None
     except (OSError, KeyError, ValueError, TypeError):
         return None
     return t["read"] + t["write"]
@@ -753,11 +757,11 @@ PROFILE_COMMANDS = {
     # the ensemble alone: batched kernel trace (with the gaps between graph-replayed
     # launches) and its HBM traffic
     "etrace": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/etrace -o etrace "
-              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,16,4 > $P/etrace_bench.json",
+              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,32,4 > $P/etrace_bench.json",
     "efetch": "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $P/efetch -o efetch "
-              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,16,4",
+              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,32,4",
     "ewrite": "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $P/ewrite -o ewrite "
-              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,16,4",
+              "-- python3 $R/bench.py --only-ensemble --ensemble-tuning 64,32,4",
     # the adjoint alone (512^2 gradient workload, 4096^2 adjoint steps)
     "atrace": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d $P/atrace -o atrace "
               "-- python3 $R/bench.py --only-adjoint > $P/atrace_bench.json",
@@ -1020,8 +1024,8 @@ def summarize_ensemble(pdir):
     traffic = None
     if keys:
         k = max(keys, key=lambda x: x[1])
-        traffic = {"kernel": kname, "read": fetch[k] * 1024 * f_scale, "write": write.get(k, 0.0) * 1024 * w_scale,
-                   "fetch_kib": fetch[k], "write_kib": write.get(k, 0.0)}
+        traffic = {"kernel": kname, "rows": ens["tuning"]["rows_per_strip"], "read": fetch[k] * 1024 * f_scale,
+                   "write": write.get(k, 0.0) * 1024 * w_scale, "fetch_kib": fetch[k], "write_kib": write.get(k, 0.0)}
     cells = int(ens["workload"].split("total ")[1].split(" cells")[0])
     alg = BYTES_PER_CELL["f32c"] * cells
     srcs = traffic_sources(here)
@@ -1046,7 +1050,8 @@ def summarize_ensemble(pdir):
                 "Commands (from /tmp with TMPDIR=/tmp; $R = repository root, $P = output folder):\n\n"
                 f"```\n{cmds}\n```\n\nSummary written by `python bench.py --summarize-profiles $P`.\n\n"
                 f"## Kernel trace\n\n{table}\n\n"
-                f"`{kname}` steps every instance 4 steps per launch (graph-replayed, 48 steps per graph); "
+                f"`{kname}` steps every instance 4 steps per launch (graph-replayed, 48 steps per graph; launch "
+                f"shape {ens['tuning']}); "
                 "`fused_dpp_kernel<float, true, 2, 4>` is the loop of single-instance launches in the same shape "
                 "and `fused_dpp_kernel` / `step_kernel` rows of other shapes belong to the default-shape loop.\n\n"
                 f"## Launches of the batched kernel\n\n"
@@ -1075,7 +1080,7 @@ def summarize_adjoint(pdir):
     fetch, write = _counter_means(pdir, "afetch"), _counter_means(pdir, "awrite")
     ck, f_scale, w_scale = _copy_calibration(fetch, write)
     keys = [k for k in fetch if k[0].startswith("adjoint_kernel<double")]
-    k = max(keys, key=lambda x: x[1])                 # the 4096^2 dispatches
+    k = max(keys, key=lambda x: fetch[x])             # the 4096^2 dispatches read the most
     rd, wr = fetch[k] * 1024 * f_scale, write.get(k, 0.0) * 1024 * w_scale
     n = 4096
     alg = ADJOINT_BYTES_PER_CELL * n * n
@@ -1113,6 +1118,33 @@ def summarize_adjoint(pdir):
     return {"adjoint_4096_us": avg, "traffic": traffic}
 
 
+def summarize_fronts(pdir):
+    """profiles/front_sweep_kernels_512x256.md from the fronts/ trace."""
+    import csv
+    here = os.path.dirname(os.path.abspath(__file__))
+    head = "| kernel | calls | average (us) | min (us) | max (us) |\n|---|---|---|---|---|\n"
+    fdir = os.path.join(pdir, "fronts")
+    if os.path.isdir(fdir):
+        fstats = {}
+        with open(os.path.join(fdir, "fronts_kernel_stats.csv")) as f:
+            for row in csv.DictReader(f):
+                fstats[_short(row["Name"])] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3,
+                                              float(row["MinNs"]) / 1e3, float(row["MaxNs"]) / 1e3)
+        with open(os.path.join(pdir, "fronts_bench.json")) as f:
+            fb = json.loads(f.read().strip().splitlines()[-1])["front_sweep"]
+        rows = [f"| {k} | {n} | {avg:.1f} | {lo:.1f} | {hi:.1f} |"
+                for k, (n, avg, lo, hi) in sorted(fstats.items(), key=lambda x: -x[1][0] * x[1][1])
+                if k.startswith(("fused_dpp_batch_kernel", "step_batch_kernel", "front_"))]
+        with open(os.path.join(here, "profiles", "front_sweep_kernels_512x256.md"), "w") as f:
+            f.write("# Invasion sweep: 12 fronts of 512x256 (delta1 sweep x 2 acid anisotropies), FP64 (rocprofv3)\n\n"
+                    f"Command (from /tmp with TMPDIR=/tmp):\n\n```\n{PROFILE_COMMANDS['fronts']}\n```\n\n"
+                    "## Kernel trace (--stats)\n\n" + head + "\n".join(rows) +
+                    "\n\n`fused_dpp_batch_kernel<double, false, 1, 4>` steps all twelve fronts 4 steps per launch; "
+                    "`front_row_kernel` / `front_final_kernel` are the front and gap diagnostics (one wave per row, "
+                    f"then a fixed-order reduction).  bench.py in the same run: {fb['value']:.1f} Gcell/s over "
+                    f"{fb['workload']}.\n")
+
+
 def summarize_profiles(pdir):
     """Write profiles/*.md and profiles/step_kernel_traffic.json from the CSV
     output of PROFILE_COMMANDS (trace/, fetch/, write/ and trace_bench.json
@@ -1125,6 +1157,8 @@ def summarize_profiles(pdir):
         print(json.dumps({"ensemble": summarize_ensemble(pdir)}, indent=1))
     if os.path.isdir(os.path.join(pdir, "atrace")):
         print(json.dumps({"adjoint": summarize_adjoint(pdir)}, indent=1))
+    if os.path.isdir(os.path.join(pdir, "fronts")):
+        summarize_fronts(pdir)
     if not os.path.isdir(os.path.join(pdir, "trace")):
         if os.path.isdir(os.path.join(pdir, "trace3")):
             print(json.dumps({"three_d": summarize_3d(pdir, "trace3", "fetch3", "write3", "trace3_bench.json")},
@@ -1203,26 +1237,6 @@ def summarize_profiles(pdir):
                 "| variant | kernel | rows | calls (trace) | average (us) | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | "
                 "scaled read (MB) | scaled write (MB) | algorithmic read / write (MB) | traffic / algorithmic |\n"
                 "|---|---|---|---|---|---|---|---|---|---|---|\n" + "\n".join(rows_md) + "\n")
-    fdir = os.path.join(pdir, "fronts")
-    if os.path.isdir(fdir):
-        fstats = {}
-        with open(os.path.join(fdir, "fronts_kernel_stats.csv")) as f:
-            for row in csv.DictReader(f):
-                fstats[_short(row["Name"])] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3,
-                                              float(row["MinNs"]) / 1e3, float(row["MaxNs"]) / 1e3)
-        with open(os.path.join(pdir, "fronts_bench.json")) as f:
-            fb = json.loads(f.read().strip().splitlines()[-1])["front_sweep"]
-        rows = [f"| {k} | {n} | {avg:.1f} | {lo:.1f} | {hi:.1f} |"
-                for k, (n, avg, lo, hi) in sorted(fstats.items(), key=lambda x: -x[1][0] * x[1][1])
-                if k.startswith(("fused_dpp_batch_kernel", "step_batch_kernel", "front_"))]
-        with open(os.path.join(here, "profiles", "front_sweep_kernels_512x256.md"), "w") as f:
-            f.write("# Invasion sweep: 12 fronts of 512x256 (delta1 sweep x 2 acid anisotropies), FP64 (rocprofv3)\n\n"
-                    f"Command (from /tmp with TMPDIR=/tmp):\n\n```\n{PROFILE_COMMANDS['fronts']}\n```\n\n"
-                    "## Kernel trace (--stats)\n\n" + head + "\n".join(rows) +
-                    "\n\n`fused_dpp_batch_kernel<double, false, 1, 4>` steps all twelve fronts 4 steps per launch; "
-                    "`front_row_kernel` / `front_final_kernel` are the front and gap diagnostics (one wave per row, "
-                    f"then a fixed-order reduction).  bench.py in the same run: {fb['value']:.1f} Gcell/s over "
-                    f"{fb['workload']}.\n")
     if os.path.isdir(os.path.join(pdir, "trace3")):
         traffic["three_d"] = summarize_3d(pdir, "trace3", "fetch3", "write3", "trace3_bench.json")
     elif bench.get("three_d"):
@@ -1260,8 +1274,11 @@ def main():
                     help="run the library's autotuner for the headline shape instead of the fixed shapes")
     ap.add_argument("--force-tuning", default="",
                     help="VARIANT=ROWS,THREADS,FUSED,LANE_SHIFT[;...]: headline launch shapes")
-    ap.add_argument("--ensemble-tuning", default="",
-                    help="THREADS,ROWS[,FUSED]: batched launch shape instead of the batch autotuner")
+    ap.add_argument("--ensemble-tuning", default="64,32,4",
+                    help="THREADS,ROWS[,FUSED]: batched launch shape (default: the shape the batch autotuner "
+                         "picks on this workload, which the committed ensemble profile covers)")
+    ap.add_argument("--ensemble-autotune", action="store_true",
+                    help="run the batch autotuner for the ensemble's launch shape instead")
     ap.add_argument("--summarize-profiles", metavar="DIR", default="",
                     help="write the profiles/ summaries from the output of PROFILE_COMMANDS in DIR; no GPU work")
     args = ap.parse_args()
@@ -1288,8 +1305,8 @@ def main():
         print(json.dumps({"three_d": three, "copy_ceiling_GBs": copy_ceiling(torch)}), flush=True)
         return
     if args.only_ensemble:
-        ens = time_ensemble(pk, torch, force=tuple(int(x) for x in args.ensemble_tuning.split(","))
-                            if args.ensemble_tuning else None)
+        ens = time_ensemble(pk, torch, force=None if args.ensemble_autotune or not args.ensemble_tuning
+                            else tuple(int(x) for x in args.ensemble_tuning.split(",")))
         print(json.dumps({"ensemble": ens, "copy_ceiling_GBs": copy_ceiling(torch)}), flush=True)
         return
     if args.only_adjoint:
@@ -1358,8 +1375,8 @@ def main():
     ens = None
     if not args.no_ensemble:
         log("timing the ensemble (batched graph vs loop of single launches)")
-        ens = time_ensemble(pk, torch, force=tuple(int(x) for x in args.ensemble_tuning.split(","))
-                            if args.ensemble_tuning else None)
+        ens = time_ensemble(pk, torch, force=None if args.ensemble_autotune or not args.ensemble_tuning
+                            else tuple(int(x) for x in args.ensemble_tuning.split(",")))
         log(f"  batched {ens['batched_Gcell_s']:.1f} Gcell/s vs loop {ens['loop_same_shape_Gcell_s']:.1f} "
             f"Gcell/s in the same shape (x{ens['speedup']:.2f}), {ens['loop_default_shape_Gcell_s']:.1f} in the "
             f"default shape")
