@@ -84,3 +84,24 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_copy_calibration_uses_the_largest_copies(tmp_path):
+    """Copies of other sizes (checkpoints) run the same copy kernel in the same
+    launch shape as the 1 GiB calibration copies; the calibration must come
+    from the largest copy dispatches, not from the mean over all of them."""
+    for kind, gib, small in (("fetch", 524288.0, 6144.0), ("write", 1048576.0, 12288.0)):
+        d = tmp_path / kind
+        d.mkdir()
+        rows = []
+        vals = [small] * 30 + [gib * 1.001, gib * 0.999, gib]
+        for disp, val in enumerate(vals):
+            rows.append({"Dispatch_Id": disp, "Kernel_Name": "__amd_rocclr_copyBuffer", "Grid_Size": 4096,
+                         "Workgroup_Size": 256, "Counter_Name": kind.upper() + "_SIZE", "Counter_Value": val})
+        with open(d / f"{kind}_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=list(rows[0]))
+            w.writeheader()
+            w.writerows(rows)
+    fetch, write = bench._counter_means(str(tmp_path), "fetch"), bench._counter_means(str(tmp_path), "write")
+    _, f_scale, w_scale = bench._copy_calibration(fetch, write)
+    assert f_scale == pytest.approx(2.0, rel=1e-3) and w_scale == pytest.approx(1.0, rel=1e-3)

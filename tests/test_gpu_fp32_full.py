@@ -1,4 +1,5 @@
-"""FP32 storage and arithmetic on the 1024^2 smooth anisotropic workload, 10^4
+"""FP32 storage and arithmetic on the 1024^2 smooth anisotropic workload and on
+the 4096^2 layered-tissue benchmark workload, 10^4
 steps, in the launch shapes the benchmark times, against the FP64 oracle.
 
 Both sides take the same FP32-rounded inputs: the tensor (the oracle's map of
@@ -53,5 +54,48 @@ def test_fp32_1024_10000_steps_headline_shape(case, dtype, tol):
     assert d["steps"] == STEPS and d["nonfinite"] == 0
     errs = [float(np.max(np.abs(x - r)) / np.max(np.abs(r))) for x, r in zip(got, ref)]
     print(f"{dtype}: relative max-norm error per field after {STEPS} steps: "
+          + ", ".join(f"{n} {e:.3e}" for n, e in zip("uvw", errs)))
+    assert max(errs) <= tol, errs
+
+
+N4, STEPS4 = 4096, 10000
+
+
+@pytest.fixture(scope="module")
+def case4096():
+    """The 4096^2 layered-tissue workload (delta1 = 12.5) on FP32-rounded inputs,
+    10^4 FP64 oracle steps (1.7e11 cell-updates on every host thread)."""
+    w = wl.cfg2(n=N4, steps=STEPS4)
+    r32 = lambda x: np.float64(np.float32(x))
+    abc = tuple(r32(x) for x in oracle.tensor_from_eig(*(r32(x) for x in w.eig)))
+    prm = tuple(float(np.float32(p)) for p in w.params)
+    st = tuple(r32(x) for x in (w.u0, w.v0, w.w0))
+    dt = float(np.float32(oracle.stable_dt(*abc, prm[2], 0.9)))
+    threads = oracle.set_threads()
+    ref = st
+    for done in range(0, STEPS4, 1000):            # the same recurrence, reported as it goes
+        ref = oracle.run(*ref, *abc, prm, dt, 1000)[:3]
+        print(f"oracle: {N4}x{N4}, {done + 1000} of {STEPS4} FP64 steps on {threads} host threads", flush=True)
+    return abc, prm, st, dt, ref
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("dtype,tol", [("f32c", 1e-5), ("f32", 2e-3)])
+def test_fp32_4096_layered_tissue_10000_steps_headline_shape(case4096, dtype, tol):
+    """The benchmark's workload and launch shapes, the full 10^4 steps."""
+    abc, prm, st, dt, ref = case4096
+    f32 = lambda x: np.asarray(x, np.float32)
+    ctx = pk.Context(N4, N4, dtype=dtype)
+    ctx.set_params(prm)
+    ctx.set_tensor(*(f32(x) for x in abc))
+    ctx.set_state(*(f32(x) for x in st))
+    ctx.set_tuning(*SHAPES[dtype])
+    ctx.step(dt, STEPS4)
+    got = ctx.get_state()
+    d = ctx.diagnostics()
+    ctx.close()
+    assert d["steps"] == STEPS4 and d["nonfinite"] == 0
+    errs = [float(np.max(np.abs(x - r)) / np.max(np.abs(r))) for x, r in zip(got, ref)]
+    print(f"{dtype} 4096^2: relative max-norm error per field after {STEPS4} steps: "
           + ", ".join(f"{n} {e:.3e}" for n, e in zip("uvw", errs)))
     assert max(errs) <= tol, errs
