@@ -130,7 +130,7 @@ def test_step3_conserves_tumour_cells_and_acid_without_reactions():
     prm = (0.0, 0.0, 0.5, 0.0, 0.0)
     with ctx_of(nx, ny, nz, state, A, prm=prm) as ctx:
         m0 = ctx.mass()
-        dt = 0.9 * ctx.stable_dt(1.0)
+        dt = 0.9 * oracle.stable_dt3(A, prm[2], 1.0)
         ctx.step(dt, 50)
         m1 = ctx.mass()
         u = ctx.get_state()[0]

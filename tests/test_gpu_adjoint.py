@@ -120,21 +120,19 @@ def _forward_loss(ctx, params, eig, x0, dt, N, target, dxdy):
 @pytest.fixture(scope="module")
 def gradient_case():
     """512^2 smooth anisotropic tensor, 5000 steps: target from the true
-    parameters and theta, loss at parameters perturbed by +/-20% and a perturbed
-    theta field."""
+    parameters and theta (the oracle's run, at the oracle's step bound), loss
+    at parameters perturbed by +/-20% and a perturbed theta field."""
     torch = pytest.importorskip("torch")
     w = wl.cfg4()
     p_pert, dtheta = wl.cfg4_perturbation()
     lam1, lam2, th_true = w.eig
     th_pert = th_true + dtheta
     n = w.nx
+    abc_true = oracle.tensor_from_eig(*w.eig)
+    # frozen: the perturbation changes neither lambda nor the step bound
+    dt = oracle.stable_dt(*abc_true, w.params[2], w.safety)
+    _, v_t, w_t, _ = oracle.run(w.u0, w.v0, w.w0, *abc_true, w.params, dt, w.steps)
     ctx = pk.Context(n, n, dtype="f64")
-    ctx.set_params(w.params)
-    ctx.set_tensor_eig(*w.eig)
-    dt = ctx.stable_dt(w.safety)       # frozen: the perturbation changes neither lambda nor dt's bound
-    ctx.set_state(w.u0, w.v0, w.w0)
-    ctx.step(dt, w.steps)
-    _, v_t, w_t = ctx.get_state()
     return dict(torch=torch, w=w, ctx=ctx, dt=dt, p=p_pert, eig=(lam1, lam2, th_pert),
                 target=(v_t, w_t), dxdy=1.0 / (n * n))
 

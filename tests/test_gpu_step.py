@@ -131,8 +131,8 @@ def test_full_size_layered_tissue_patches(dtype):
     w = wl.cfg2(steps=60)
     a, b, c = oracle.tensor_from_eig(*w.eig)
     ctx = gpu_ctx(w.nx, w.ny, dtype, w.params, (w.u0, w.v0, w.w0), eig=w.eig)
-    dt = ctx.stable_dt(0.9)
-    assert math.isclose(dt, oracle.stable_dt(a, b, c, w.params[2], 0.9), rel_tol=1e-15)
+    dt = oracle.stable_dt(a, b, c, w.params[2], 0.9)
+    assert math.isclose(ctx.stable_dt(0.9), dt, rel_tol=1e-15)
     ctx.step(dt, w.steps)
     got = ctx.get_state()
     n = w.nx
@@ -173,7 +173,7 @@ def test_full_size_500_steps_headline_shape_each_delta1(delta1):
     a, b, c = oracle.tensor_from_eig(*w.eig)
     ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), abc=(a, b, c))
     ctx.set_tuning(0, 64, 4, lane_shift=2)
-    dt = ctx.stable_dt(0.9)
+    dt = oracle.stable_dt(a, b, c, w.params[2], 0.9)
     ctx.step(dt, w.steps)
     got = ctx.get_state()
     ctx.close()
@@ -437,7 +437,7 @@ def test_device_pointer_io_matches_host_io():
     ctx.set_params(PRM)
     ctx.set_tensor(*tdev)
     ctx.set_state(*dev)
-    dt = ctx.stable_dt(0.9)
+    dt = oracle.stable_dt(a, b, c, PRM[2], 0.9)
     ctx.step(dt, 10)
     outs = [torch.empty((ny, nx), dtype=torch.float64, device="cuda") for _ in range(3)]
     ctx.get_state(out=outs)
@@ -549,7 +549,7 @@ def test_lane_shift_full_size_against_oracle_patches(lanes):
     a, b, c = oracle.tensor_from_eig(*w.eig)
     ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), eig=w.eig)
     ctx.set_tuning(0, 0, 4, lane_shift=lanes)
-    dt = ctx.stable_dt(0.9)
+    dt = oracle.stable_dt(a, b, c, w.params[2], 0.9)
     ctx.step(dt, w.steps)
     got = ctx.get_state()
     n = w.nx
@@ -569,7 +569,7 @@ def test_fused_full_size_patches_and_checkpoints():
     a, b, c = oracle.tensor_from_eig(*w.eig)
     ctx = gpu_ctx(w.nx, w.ny, "f64", w.params, (w.u0, w.v0, w.w0), eig=w.eig)
     ctx.set_tuning(0, 0, 3, lane_shift=1)
-    dt = ctx.stable_dt(0.9)
+    dt = oracle.stable_dt(a, b, c, w.params[2], 0.9)
     ctx.step(dt, w.steps)
     got = ctx.get_state()
     n = w.nx
