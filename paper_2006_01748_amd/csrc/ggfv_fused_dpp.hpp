@@ -5,8 +5,7 @@
 // A wave of 64 lanes owns 64*CPL adjacent columns (lane l: columns e0 + l*CPL +
 // k) and sweeps a strip upwards.  Level s = 1..K computes row q = r - 2s + 1 at
 // iteration r from rows q-1, q, q+1 of level s-1 (level 0 is the old state,
-// requested one iteration ahead).  Compared with the LDS-ring variant
-// (ggfv_fused.hip):
+// requested one iteration ahead).
 //   * every lane keeps the rows it needs of each level in registers, so the
 //     state needs no LDS and no barriers;
 //   * the levels of one iteration run from K down to 1, so that level s has
@@ -53,6 +52,9 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kPeriod = 6;    // row-loop unroll: lcm of the ring lengths 3 and 2
+// s_getreg operand for bit 0 of the wave's slot (HW_ID register 4, bits 3:0 hold
+// the slot; size field 0 = one bit, offset 0)
+constexpr int kHwIdWaveSlotBit0 = 4;
 
 constexpr int pmod(int x, int m) { return ((x % m) + m) % m; }
 
@@ -74,7 +76,7 @@ template <int K>
 struct LaneGeom {
     int nx, ny, own, cbase, lcol, last0;
     int lo[K + 1], re[K + 1], hi[K + 1];   // per level: warm-up row, first real row, end
-    bool store_ok;                         // the lane's columns are outputs of this workgroup
+    int o0, span;                          // first output column of the workgroup; output columns of a row
     bool flip;                             // the strip sweeps downward (rows mirrored, see dpp_strip)
 };
 
@@ -150,22 +152,29 @@ __device__ __forceinline__ void x_difference(const T (&X)[CPL], const ColumnMask
 template <typename T, int CPL, int K>
 constexpr bool late_store() { return sizeof(T) == 8 && CPL == 2 && K >= 2; }
 
-// Store level K's output row q (held in R.KO) if it is one of this
-// workgroup's rows and columns.
+// Store level K's output row q (held in R.KO): the lanes whose columns are
+// outputs of this workgroup, if q is one of its rows.  Every lane issues the
+// store in every iteration, as a buffer store whose range is the workgroup's
+// output span of the row (empty for a row outside the strip): the hardware
+// drops the lanes outside the range.  With no branch around the stores, the
+// compiler's memory-counter waits can count them, so the wait for the next
+// row's loads does not also wait for the stores issued before them.
 template <typename T, bool COMP, int CPL, int K, bool BATCH>
 __device__ __forceinline__ void store_level_k(const StepArgs<T> &A, const LaneGeom<K> &g,
                                               const LaneRows<T, COMP, CPL, K> &R, const int q)
 {
     constexpr bool NT = sizeof(T) == 8 || BATCH;
-    if (q < g.re[K] || q >= g.hi[K] || !g.store_ok) return;
-    const size_t o = (size_t)(g.flip ? g.ny - 1 - q : q) * A.pitch + g.cbase;
-    store_vec<T, CPL, NT>(A.un + o, R.KO[0]);
-    store_vec<T, CPL, NT>(A.vn + o, R.KO[1]);
-    store_vec<T, CPL, NT>(A.wn + o, R.KO[2]);
+    const bool row_ok = q >= g.re[K] && q < g.hi[K];                 // uniform
+    const int nbytes = row_ok ? g.span * (int)sizeof(T) : 0;
+    const size_t o = (size_t)(row_ok ? (g.flip ? g.ny - 1 - q : q) : 0) * A.pitch + g.o0;
+    const int voff = (g.cbase - g.o0) * (int)sizeof(T);           // negative left of the span: out of range
+    buffer_store_vec<T, CPL, NT>(A.un + o, nbytes, voff, R.KO[0]);
+    buffer_store_vec<T, CPL, NT>(A.vn + o, nbytes, voff, R.KO[1]);
+    buffer_store_vec<T, CPL, NT>(A.wn + o, nbytes, voff, R.KO[2]);
     if constexpr (COMP) {
-        store_vec<T, CPL, NT>(A.unlo + o, R.KO[3]);
-        store_vec<T, CPL, NT>(A.vnlo + o, R.KO[4]);
-        store_vec<T, CPL, NT>(A.wnlo + o, R.KO[5]);
+        buffer_store_vec<T, CPL, NT>(A.unlo + o, nbytes, voff, R.KO[3]);
+        buffer_store_vec<T, CPL, NT>(A.vnlo + o, nbytes, voff, R.KO[4]);
+        buffer_store_vec<T, CPL, NT>(A.wnlo + o, nbytes, voff, R.KO[5]);
     }
 }
 
@@ -392,7 +401,8 @@ __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, co
     g.own = threadIdx.x;
     g.cbase = e0 + (int)threadIdx.x * CPL;
     g.lcol = min(max(g.cbase, 0), A.pitch - CPL);
-    g.store_ok = g.cbase >= o0 && g.cbase < o0 + Sh::OUTW && g.cbase < A.pitch;
+    g.o0 = o0;
+    g.span = min(Sh::OUTW, A.pitch - o0);
     g.flip = strip_flips(sy);
     int j0, j1;
     strip_rows(g.ny, A.rows, sy, j0, j1);
@@ -445,7 +455,20 @@ __device__ __forceinline__ void dpp_strip(const StepArgs<T> &A, const int sx, co
     const int r_start = g.lo[1] - 2;
     const int r_end = g.hi[K] + 2 * K - 2;
     const int r0 = r_start - pmod(r_start, kPeriod);
+    // Two waves share each SIMD, and among waves of equal priority the
+    // instruction arbiter issues the older one first: measured on MI355X (4096²
+    // FP64, one round of strips), the older wave of every SIMD pair finished
+    // first, the younger one took 1.3-1.55 times as long, and for the last third
+    // of the launch one wave per SIMD was left, which moves fewer bytes per
+    // second.  The younger wave (odd slot in the SIMD's wave list) therefore
+    // runs at raised priority for the first half of its sweep and at the common
+    // one after it, so the two finish closer together.  Only the issue order
+    // changes, not the arithmetic.
+    const unsigned int slot = __builtin_amdgcn_s_getreg(kHwIdWaveSlotBit0) & 1u;
+    const int r_half = r_start + (r_end - r_start) / 2;
     for (int rb = r0; rb <= r_end; rb += kPeriod) {
+        if (slot != 0u && rb < r_half) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
         const int ba = ring_base<RTA>(rb), bc = ring_base<RTC>(rb);
         lane_iter<T, COMP, CPL, K, 0, RTA, RTC, EDGE, BATCH>(A, g, m, R, L, rb + 0, r_start, r_end, ba, bc);
         lane_iter<T, COMP, CPL, K, 1, RTA, RTC, EDGE, BATCH>(A, g, m, R, L, rb + 1, r_start, r_end, ba, bc);

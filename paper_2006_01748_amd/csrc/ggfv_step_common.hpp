@@ -52,6 +52,35 @@ __device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&in)[CPL])
     }
 }
 
+// Store CPL values at byte offset voff of a buffer of nbytes bytes starting at
+// base (base and nbytes uniform across the wave).  A lane whose offset lies
+// outside [0, nbytes) (a negative offset reads as a large unsigned one) stores
+// nothing: the hardware's range check of buffer accesses drops it.  Offsets
+// and nbytes are multiples of the store's width, so a store is never partly
+// in range.
+template <typename T, int CPL, bool NT>
+__device__ __forceinline__ void buffer_store_vec(T *base, int nbytes, int voff, const T (&in)[CPL])
+{
+    constexpr int kBytes = (int)sizeof(T) * CPL;
+    static_assert(kBytes == 4 || kBytes == 8 || kBytes == 16, "4, 8 or 16 bytes per lane");
+    // word 3 of a gfx9 buffer resource: 32-bit data format, no swizzle, no index
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nbytes, 0x00020000);
+    constexpr int aux = NT ? 2 : 0;                      // 2: the non-temporal bit
+    unsigned int w[kBytes / 4];
+    __builtin_memcpy(w, in, kBytes);
+    if constexpr (kBytes == 16) {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        const u4 x = {w[0], w[1], w[2], w[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(x, rsrc, voff, 0, aux);
+    } else if constexpr (kBytes == 8) {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        const u2 x = {w[0], w[1]};
+        __builtin_amdgcn_raw_buffer_store_b64(x, rsrc, voff, 0, aux);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(w[0], rsrc, voff, 0, aux);
+    }
+}
+
 template <typename T, int CPL>
 __device__ __forceinline__ void lds_store_vec(T *p, const T (&in)[CPL])
 {
