@@ -238,14 +238,15 @@ def cfg4_perturbation(seed: int = BASE_SEED + 4, n: int = 512):
 
 
 def front_instance(delta1: float, kappa: float, nx: int = 512, ny: int = 256, lx: float = 1.0,
-                   ly: float = 0.5, steps: int = 0, seed: int = BASE_SEED + 5) -> Workload:
+                   ly: float = 0.5, steps: int = 0, seed: int = BASE_SEED + 5, Delta2: float = 0.01) -> Workload:
     """Propagating-front workload (Section 2's invasion experiment): healthy
     tissue u = 1 everywhere, the tumour v = 1 behind a front at x0(y) = 0.2 +
     0.02 sin(4 pi y / ly + phase) (seeded phase), no acid.  The fronts advance
     along +x.  The acid diffuses with kappa * lam along x, the direction of
     propagation (lower diffusivity there for kappa < 1), and lam across it, lam a
     smooth seeded field in [0.75, 1.25] (heterogeneous); as (lambda1, lambda2,
-    theta) = (kappa lam, lam, 0).  Parameters (delta1, 1, 0.01, 70, 70)."""
+    theta) = (kappa lam, lam, 0).  Parameters (delta1, 1, Delta2, 70, 70), Delta2 =
+    0.01 unless given."""
     rng = np.random.Generator(np.random.PCG64(seed))
     X, Y = cell_centres(nx, ny, lx, ly)
     phase = rng.uniform(0.0, 2.0 * math.pi)
@@ -255,7 +256,7 @@ def front_instance(delta1: float, kappa: float, nx: int = 512, ny: int = 256, lx
     w = np.zeros((ny, nx))
     lam = 0.75 + 0.5 * smooth_field(rng, nx, ny)
     theta = np.zeros((ny, nx))
-    return Workload(f"front d={delta1} kappa={kappa}", nx, ny, lx, ly, (delta1, 1.0, 0.01, 70.0, 70.0),
+    return Workload(f"front d={delta1} kappa={kappa} D2={Delta2}", nx, ny, lx, ly, (delta1, 1.0, Delta2, 70.0, 70.0),
                     u, v, w, eig=(kappa * lam, lam, theta), safety=0.9, steps=steps, seed=seed)
 
 

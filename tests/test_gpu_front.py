@@ -78,6 +78,14 @@ def test_invasion_run_bitwise_and_fronts():
     ctx.close()
 
 
+def acid_at_front(V, W):
+    """Largest over rows of the acid at the tumour front: the mean of w over the
+    last cell with v >= 1/2 and the cell after it."""
+    last = np.array([np.nonzero(r >= 0.5)[0].max() if np.any(r >= 0.5) else -1 for r in V])
+    ok = (last >= 0) & (last + 1 < V.shape[1])
+    return float(np.max(0.5 * (W[ok, last[ok]] + W[ok, last[ok] + 1])))
+
+
 def test_invasion_sweep_batch():
     """The delta1 sweep across 1, for acid diffusing equally in both directions
     (kappa = 1) and five times more slowly along the direction of propagation
@@ -88,7 +96,10 @@ def test_invasion_sweep_batch():
     degraded behind the front (u -> 0) and a gap opens ahead of it, wider for
     larger delta1.  Lower acid diffusivity along the propagation direction
     narrows the gap, and a larger delta1 compensates for it.  Fronts and
-    LeVeque-Yee tumour speeds grow with delta1.  (The run is 7 x 10^5 steps per
+    LeVeque-Yee tumour speeds grow with delta1.  Where delta1 times the acid
+    at the tumour front stays below 1 - theta_u, no gap can open: ahead of the
+    front u' = u (1 - u - delta1 w) >= 0 once u <= 1 - delta1 max w, so u stays
+    above the tissue threshold theta_u.  (The run is 7 x 10^5 steps per
     instance, beyond the oracle; the batch's front diagnostics are held to the
     oracle's on the seeded initial fronts, and the batched step to the oracle
     in the ensemble tests.)"""
@@ -120,19 +131,22 @@ def test_invasion_sweep_batch():
         assert w.params[0] == keys[i][1]
         d = b[i].diagnostics()
         f = b[i].front_diagnostics(0.25, 0.5)
-        U, V, _ = b[i].get_state()
+        U, V, W = b[i].get_state()
         speed = pk.front_speed(m0[i], d["mass"][1], 0.0, d["t"], w.ly, 1.0, 0.0)
         behind = V >= 0.9                 # the tumour bulk behind the front
         res[keys[i]] = {"front": f["tumour"][0], "gap": f["gap"][0] if f["rows_gap"] else 0.0,
                         "rows_gap": f["rows_gap"], "u_behind": float(U[behind].min()), "speed": speed,
-                        "advance": f["tumour"][0] - f0[i]["tumour"][0]}
+                        "advance": f["tumour"][0] - f0[i]["tumour"][0], "w_front": acid_at_front(V, W)}
     for kappa in kappas:
         r = [res[(kappa, d)] for d in deltas]
         print(f"kappa {kappa}: fronts {[round(x['front'], 4) for x in r]}, gaps {[round(x['gap'], 4) for x in r]}, "
-              f"u behind {[round(x['u_behind'], 4) for x in r]}, speeds {[round(x['speed'], 4) for x in r]}")
+              f"u behind {[round(x['u_behind'], 4) for x in r]}, speeds {[round(x['speed'], 4) for x in r]}, "
+              f"acid at the tumour front {[round(x['w_front'], 4) for x in r]}")
         for d, x in zip(deltas, r):
             if d < 1.0:       # heterogeneous invasion: coexistence, no gap
                 assert x["u_behind"] > (1.0 - d) - 0.02 and x["gap"] < 2 * h, (kappa, d, x)
+            if d * x["w_front"] < 1.0 - 0.25:   # u cannot fall below theta_u ahead of the front
+                assert x["gap"] < 2 * h, (kappa, d, x)
         for d in (6.0, 12.5):  # homogeneous invasion: degradation and a gap
             x = res[(kappa, d)]
             assert x["u_behind"] < 1e-2 and x["gap"] > 3 * h and x["rows_gap"] == ws[0].ny, (kappa, d, x)
@@ -147,3 +161,45 @@ def test_invasion_sweep_batch():
         assert res[(0.2, d)]["gap"] < 0.75 * res[(1.0, d)]["gap"], d
     assert res[(0.2, 12.5)]["gap"] > res[(1.0, 6.0)]["gap"]
     b.close()
+
+
+def test_gap_opens_at_smaller_delta1_for_slower_tumour_diffusion():
+    """Section 2: the emergence of the gap depends on the diffusion rates.  The
+    acid at the tumour front stays below 1/2 (0.47-0.50), so delta1 = 1.5
+    keeps delta1 w at most 1 - theta_u = 0.75 and opens no gap at either
+    tumour diffusivity (a sharper, slower front brings w at the front towards
+    1/2, where delta1 = 1.5 reaches that bound).  At delta1 = 3 the tissue
+    ahead of the front is degraded only if the front takes long enough to
+    cross the acid's reach: with Delta2 = 0.01 no gap has opened by t = 4,
+    with a ten times slower tumour diffusion (Delta2 = 0.001) one has, in
+    every row.  256 x 128 fronts, kappa = 1, FP64, batched lane-shift kernel,
+    t = 4."""
+    cases = [(1.5, 0.01), (3.0, 0.01), (1.5, 0.001), (3.0, 0.001)]
+    ws = [wl.front_instance(d, 1.0, 256, 128, Delta2=D2) for d, D2 in cases]
+    b = pk.Batch([(w.nx, w.ny) for w in ws], lx=ws[0].lx, ly=ws[0].ly, dtype="f64")
+    dts = []
+    for i, w in enumerate(ws):
+        c = b[i]
+        c.set_params(w.params)
+        c.set_tensor_eig(*w.eig)
+        c.set_state(w.u0, w.v0, w.w0)
+        dts.append(c.stable_dt(w.safety))
+    dt = min(dts)
+    for i in range(len(ws)):
+        b.set_dt(i, dt)
+    b.set_tuning(threads=64, rows_per_strip=16, graph_steps=48, fused_steps=4)
+    b.run(int(4.0 / dt))
+    h = ws[0].lx / ws[0].nx
+    res = {}
+    for i, key in enumerate(cases):
+        f = b[i].front_diagnostics(0.25, 0.5)
+        _, V, W = b[i].get_state()
+        res[key] = (f["gap"][0] if f["rows_gap"] else 0.0, f["rows_gap"], acid_at_front(V, W))
+    b.close()
+    print("(delta1, Delta2): (gap, rows with a gap, acid at the tumour front):", res)
+    for D2 in (0.01, 0.001):
+        gap, _, wf = res[(1.5, D2)]
+        assert wf < 0.5 and gap < 2 * h, (D2, res[(1.5, D2)])
+    assert res[(3.0, 0.01)][0] < 2 * h, res[(3.0, 0.01)]
+    gap, rows, _ = res[(3.0, 0.001)]
+    assert gap > 3 * h and rows == ws[0].ny, res[(3.0, 0.001)]
