@@ -142,10 +142,10 @@ __device__ __forceinline__ void x_difference(const T (&X)[CPL], const ColumnMask
 // Where and how level K's output row is stored (measured on MI355X).  FP64
 // with wide lanes (the headline kernel): late, after the ring update has
 // waited for the loads of the iteration's old-state row, with non-temporal
-// stores.  A store issued between a load and the wait for it is waited for
-// too (the memory counter drains in order, and a conditional store keeps the
-// compiler from counting past it); storing late gives the store a whole
-// iteration instead (+1-2%).  Every other kernel stores at level K.  The FP32
+// stores.  The memory counter drains in order, so a wait for a load also
+// waits for every store issued before that load; stored late, a row's stores
+// have the rest of the iteration before the next such wait (+1-2%, measured
+// when the stores still sat behind a branch).  Every other kernel stores at level K.  The FP32
 // single-context kernels write through the caches (+2-5%); FP64 and the
 // ensemble kernels keep non-temporal stores (the ensemble and the narrow FP64
 // kernel measured slower otherwise).
