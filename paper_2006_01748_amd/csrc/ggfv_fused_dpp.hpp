@@ -233,8 +233,8 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         const T ur = k + 1 < CPL ? U0[k1] : uR;
         const T vr = k + 1 < CPL ? V0[k1] : vR;
         const T hA = L.hA[ts][k * kWave + g.own];
-        const T fx = (hA * ((wr - W0[k]) * A.idx) + half * (BT[k] + btr));
-        const T gx = ((one - half * (U0[k] + ur)) * ((vr - V0[k]) * A.idx));
+        const T fx = madd<T, COMP>(hA, (wr - W0[k]) * A.idx, half * (BT[k] + btr));
+        const T gx = madd<T, COMP>(-half, U0[k] + ur, one) * ((vr - V0[k]) * A.idx);
         FXe[k] = (!EDGE || m.ve[k]) ? fx : T(0);
         GXe[k] = (!EDGE || m.ve[k]) ? gx : T(0);
     }
@@ -250,23 +250,23 @@ __device__ __forceinline__ void level_row(const StepArgs<T> &A, const LaneGeom<K
         const T FXw = k > 0 ? FXe[k > 0 ? k - 1 : 0] : FXl;
         const T GXw = k > 0 ? GXe[k > 0 ? k - 1 : 0] : GXl;
         const T Wc = W0[k], Uc = U0[k], Vc = V0[k];
-        const T fy = (hC * ((Wp[k] - Wc) * A.idy) + half * (B0[k] * R.TX[I][k] + Bp * TXn[k]));
-        const T gy = ((one - half * (Uc + Up)) * ((Vp - Vc) * A.idy));
+        const T fy = madd<T, COMP>(hC, (Wp[k] - Wc) * A.idy, half * (B0[k] * R.TX[I][k] + Bp * TXn[k]));
+        const T gy = madd<T, COMP>(-half, Uc + Up, one) * ((Vp - Vc) * A.idy);
         const T FYn = has_n ? fy : T(0);
         const T GYn = has_n ? gy : T(0);
         const T divW = (FXe[k] - FXw) * A.idx + (FYn - R.FYs[I][k]) * A.idy;
         const T divV = (GXe[k] - GXw) * A.idx + (GYn - R.GYs[I][k]) * A.idy;
-        const T fu = Uc * (one - Uc) - (A.d1 * Uc) * Wc;
-        const T fv = (A.r2 * Vc) * (one - Vc) + A.D2 * divV;
-        const T fw = (A.r3 * Vc - A.d3 * Wc) + divW;
+        const T fu = madd<T, COMP>(-(A.d1 * Uc), Wc, Uc * (one - Uc));
+        const T fv = madd<T, COMP>(A.D2, divV, (A.r2 * Vc) * (one - Vc));
+        const T fw = madd<T, COMP>(A.r3, Vc, -(A.d3 * Wc)) + divW;
         if constexpr (COMP) {
             comp_add(Uc, R.Ul[I][q2][k], A.dt * fu, ou[k], oul[k]);
             comp_add(Vc, R.Vl[I][q2][k], A.dt * fv, ov[k], ovl[k]);
             comp_add(Wc, R.Wl[I][q2][k], A.dt * fw, ow[k], owl[k]);
         } else {
-            ou[k] = Uc + A.dt * fu;
-            ov[k] = Vc + A.dt * fv;
-            ow[k] = Wc + A.dt * fw;
+            ou[k] = madd<T, COMP>(A.dt, fu, Uc);
+            ov[k] = madd<T, COMP>(A.dt, fv, Vc);
+            ow[k] = madd<T, COMP>(A.dt, fw, Wc);
         }
         R.FYs[I][k] = FYn;
         R.GYs[I][k] = GYn;

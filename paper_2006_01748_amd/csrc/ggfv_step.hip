@@ -198,20 +198,22 @@ __device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, c
             const T txn = (WRn - WLn) * A.hx;
 
             const bool has_e = (i + 1 < nx), has_w = (i > 0);
-            const T FXe = has_e ? half * (ac + aR) * ((WR - Wc) * A.idx) + half * (bc * tyc + bR * tyR) : T(0);
-            const T FXw = has_w ? half * (aL + ac) * ((Wc - WL) * A.idx) + half * (bL * tyL + bc * tyc) : T(0);
-            const T FYn = has_n ? half * (cur.c[k] + nxt.c[k]) * ((Wn - Wc) * A.idy) +
-                                      half * (bc * txc + nxt.b[k] * txn)
+            const T FXe = has_e ? madd<T, COMP>(half * (ac + aR), (WR - Wc) * A.idx, half * (bc * tyc + bR * tyR))
                                 : T(0);
-            const T GXe = has_e ? (one - half * (Uc + UR)) * ((VR - Vc) * A.idx) : T(0);
-            const T GXw = has_w ? (one - half * (UL + Uc)) * ((Vc - VL) * A.idx) : T(0);
-            const T GYn = has_n ? (one - half * (Uc + nxt.U[k])) * ((nxt.V[k] - Vc) * A.idy) : T(0);
+            const T FXw = has_w ? madd<T, COMP>(half * (aL + ac), (Wc - WL) * A.idx, half * (bL * tyL + bc * tyc))
+                                : T(0);
+            const T FYn = has_n ? madd<T, COMP>(half * (cur.c[k] + nxt.c[k]), (Wn - Wc) * A.idy,
+                                                half * (bc * txc + nxt.b[k] * txn))
+                                : T(0);
+            const T GXe = has_e ? madd<T, COMP>(-half, Uc + UR, one) * ((VR - Vc) * A.idx) : T(0);
+            const T GXw = has_w ? madd<T, COMP>(-half, UL + Uc, one) * ((Vc - VL) * A.idx) : T(0);
+            const T GYn = has_n ? madd<T, COMP>(-half, Uc + nxt.U[k], one) * ((nxt.V[k] - Vc) * A.idy) : T(0);
 
             const T divW = (FXe - FXw) * A.idx + (FYn - FYs[k]) * A.idy;
             const T divV = (GXe - GXw) * A.idx + (GYn - GYs[k]) * A.idy;
-            const T fu = Uc * (one - Uc) - (A.d1 * Uc) * Wc;
-            const T fv = (A.r2 * Vc) * (one - Vc) + A.D2 * divV;
-            const T fw = (A.r3 * Vc - A.d3 * Wc) + divW;
+            const T fu = madd<T, COMP>(-(A.d1 * Uc), Wc, Uc * (one - Uc));
+            const T fv = madd<T, COMP>(A.D2, divV, (A.r2 * Vc) * (one - Vc));
+            const T fw = madd<T, COMP>(A.r3, Vc, -(A.d3 * Wc)) + divW;
             const bool inside = (i < nx);
             if constexpr (COMP) {
                 T h, l;
@@ -225,9 +227,9 @@ __device__ __forceinline__ void step_strip(const StepArgs<T> &A, const int sx, c
                 ow[k] = inside ? h : T(0);
                 owl[k] = inside ? l : T(0);
             } else {
-                ou[k] = inside ? Uc + A.dt * fu : T(0);
-                ov[k] = inside ? Vc + A.dt * fv : T(0);
-                ow[k] = inside ? Wc + A.dt * fw : T(0);
+                ou[k] = inside ? madd<T, COMP>(A.dt, fu, Uc) : T(0);
+                ov[k] = inside ? madd<T, COMP>(A.dt, fv, Vc) : T(0);
+                ow[k] = inside ? madd<T, COMP>(A.dt, fw, Wc) : T(0);
             }
             FYs[k] = FYn;
             GYs[k] = GYn;

@@ -90,6 +90,24 @@ __device__ __forceinline__ void lds_store_vec(T *p, const T (&in)[CPL])
     *reinterpret_cast<VecN<T, CPL> *>(p) = x;
 }
 
+// a * b + c.  The plain FP32 state evaluates it as one fused multiply-add (one
+// rounding); FP64 and the compensated FP32 state keep the multiply and the add,
+// so that FP64 follows the oracle's operations one for one.  The single-step
+// and the fused kernels call it at the same places with the same operands, so
+// they keep giving the same bits in every precision.  The places are the face
+// fluxes of w, the mobilities 1 - (U + U')/2, the reactions and the Euler
+// updates: each is its own expression, so transposing the grid, mirroring it
+// or sweeping a strip downward maps it to itself or to its exact negative
+// (fma(a, -b, -c) = -fma(a, b, c)), and those symmetries stay bit for bit.
+// The divergences keep their separate products: fusing one of their two
+// terms would make the transposed grid round differently.
+template <typename T, bool COMP>
+__device__ __forceinline__ T madd(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 4 && !COMP) return __builtin_fmaf(a, b, c);
+    else return a * b + c;
+}
+
 // x + inc with the compensated pair (hi, lo): returns new (hi, lo).
 template <typename T>
 __device__ __forceinline__ void comp_add(T hi, T lo, T inc_dt, T &nhi, T &nlo)
