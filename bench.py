@@ -44,8 +44,8 @@ METRIC = "Gcell-updates/s + % HBM peak, 4096² aniso FV step FP32/FP64; adjoint/
 # once, shared by its two cells): x/y faces of W 2 x 10, tangential differences
 # 4, divergence of W 5, faces of V 2 x 6, divergence of V 5, reactions 14,
 # Euler updates 6.  FP64 and the compensated FP32 state evaluate them without
-# fused multiply-adds, each one vector operation; plain FP32 fuses ten pairs,
-# so its 66 flops take 56 operations (its valu_frac below counts flops).
+# fused multiply-adds, each one vector operation; plain FP32 fuses ten
+# multiply-add pairs into single operations (its valu_frac still counts flops).
 FLOPS_PER_CELL = 66
 # MI355X vector FP64 (and non-packed FP32) rate without FMA: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz = 39.3e12 operations per second (78.6 TFLOP/s counts an FMA
