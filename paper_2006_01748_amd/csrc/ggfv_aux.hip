@@ -614,7 +614,7 @@ hipError_t launch_diagnostics(ggfv_ctx *ctx, double dt)
 // blocks, whatever the grid size).  Each device the library runs on holds its
 // own copy until the process ends.  Host code never uses the array's name as an
 // address: its device address, per device, comes from hipGetSymbolAddress.
-__device__ __align__(256) double scratch[kMaxPartialBlocks * kDiagSlots];
+static __device__ __align__(256) double scratch[kMaxPartialBlocks * kDiagSlots];
 
 namespace {
 
