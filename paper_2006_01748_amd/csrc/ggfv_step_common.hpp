@@ -23,12 +23,21 @@ struct StepArgs {
     T d1, r2, D2, r3, d3;
 };
 
-template <typename T, int CPL>
+// NT = true loads non-temporally (the row is not kept in the caches for a
+// later reader).
+template <typename T, int CPL, bool NT = false>
 __device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&out)[CPL])
 {
-    VecN<T, CPL> x = *reinterpret_cast<const VecN<T, CPL> *>(p);
+    if constexpr (NT) {
+        typedef T vec_t __attribute__((ext_vector_type(CPL)));
+        const vec_t x = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(p));
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) out[k] = x.v[k];
+        for (int k = 0; k < CPL; ++k) out[k] = x[k];
+    } else {
+        VecN<T, CPL> x = *reinterpret_cast<const VecN<T, CPL> *>(p);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) out[k] = x.v[k];
+    }
 }
 
 // Output rows are written with non-temporal stores by default: the next step
