@@ -86,14 +86,14 @@ def test_leveque_yee_recovers_a_translation(orc=oracle):
     assert math.isclose(s, 0.37 / 0.5, rel_tol=1e-12)
 
 
-def _invasion(d, T, nx=100, lx=1.0, orc=oracle):
-    ny, ly = 2, 0.02
+def _invasion(d, T, nx=100, lx=1.0, orc=oracle, Delta2=0.01):
+    ny, ly = 2, 2.0 * lx / nx
     x = cell_x(nx, lx)
     v0 = np.tile((x < 0.2).astype(float), (ny, 1))
     u0 = np.ones((ny, nx))
     w0 = np.zeros((ny, nx))
     ones = np.ones((ny, nx))
-    prm = (d, 1.0, 0.01, 70.0, 70.0)
+    prm = (d, 1.0, Delta2, 70.0, 70.0)
     dt = orc.stable_dt(ones, 0 * ones, ones, prm[2], 0.9, lx, ly)
     u, v, w, _ = orc.run(u0, v0, w0, ones, 0 * ones, ones, prm, dt, int(T / dt), lx, ly)
     return u, v, w, orc.front_diag(u, v, 0.25, 0.5, lx)
@@ -119,3 +119,24 @@ def test_homogeneous_invasion_degrades_and_opens_a_gap(orc=oracle):
         if d == 12.5:
             assert f["gap"][1] > 10.0 / 100 and u[0, 5] < 1e-3
     assert fronts[0] < fronts[1] < fronts[2]   # more aggressive invasion travels faster
+
+
+def test_gap_onset_bound_and_tumour_diffusivity(orc=oracle):
+    """Ahead of the tumour front u' = u (1 - u - d w) >= 0 once u <= 1 - d max w,
+    so while d w stays below 1 - theta_u the tissue cannot fall below theta_u
+    and no gap opens.  With rho3 = delta3 the acid at the tumour front stays
+    below 1/2, so d = 1.5 opens no gap even with slow tumour diffusion; d = 3
+    opens one only when the tumour diffuses slowly (Delta2 = 0.001 against
+    0.01), the dependence on the diffusion rates of Section 2.  Channel of
+    128 cells, t = 4."""
+    nx = 128
+    h = 1.0 / nx
+    res = {}
+    for d, D2 in ((1.5, 0.001), (3.0, 0.001), (3.0, 0.01)):
+        u, v, w, f = _invasion(d, 4.0, nx=nx, orc=orc, Delta2=D2)
+        last = int(np.nonzero(v[0] >= 0.5)[0].max())
+        res[(d, D2)] = (f["gap"][0], 0.5 * (w[0, last] + w[0, last + 1]))
+    gap, wf = res[(1.5, 0.001)]
+    assert wf < 0.5 and 1.5 * wf < 1.0 - 0.25 and gap < h, res
+    assert res[(3.0, 0.01)][0] < h, res
+    assert res[(3.0, 0.001)][0] > 1.5 * h, res
